@@ -1,0 +1,140 @@
+"""Benchmark of the MacLABSWE step on one MI355X.
+
+Workload: subcritical flow over a Gaussian bump in a 4096 x 4096 channel
+(dx = 1 m, 2 m still depth, inflow discharge 4.42 m^2/s on the west edge,
+fixed 2 m depth on the east edge, walls north and south), FP32 fields.
+One "step" is one MacLABSWE time step over the whole lattice.
+
+Prints one JSON line: MLUPS (million lattice updates per second), the HBM
+roofline block of the step kernel and the FP64 oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+BYTES_PER_LUP = 28             # read eta, qx, qy, H; write eta, qx, qy (FP32)
+KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(nodes: int):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    or None when it was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("nodes") != nodes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, budget_s: float = 12.0):
+    """The FP64 oracle (as is) on the host cores: steps of the same workload
+    until the time budget is spent."""
+    import oracle
+    from tests.helpers import oracle_from_spec  # noqa: E402
+    b = oracle_from_spec(spec)
+    threads = oracle.default_threads()
+    b.threads = threads
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        b.run(1)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(spec.nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d step(s) of the %dx%d workload, FP64, %.1f s" % (n, spec.nx, spec.ny, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=4096, help="lattice side")
+    ap.add_argument("--tile-rows", type=int, default=64)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the step runs on a single MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1902_02999_amd import mlb, workloads as wl
+
+    spec = wl.bump_channel(args.n)
+    ctx = mlb.Context(0)
+    grid = mlb.grid_from_spec(ctx, spec)
+    grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100)
+
+    grid.step(args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()            # HIP events on the library stream around the launches
+    d = grid.diag()
+    if d["nonfinite"]:
+        print("bench.py: non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    nodes = spec.nodes
+    mlups = nodes * args.steps / wall / 1e6
+    launch_s = ev_ms / 1e3 / args.steps   # one launch per step
+    achieved = BYTES_PER_LUP * nodes / launch_s / 1e9
+    traffic = measured_traffic(nodes)
+    out = {
+        "metric": "MLUPS",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "nodes": nodes, "dx_m": spec.dx, "dt_s": spec.dx / (6 * spec.nu / spec.dx),
+                   "tile_rows": args.tile_rows, "graph": not args.no_graph,
+                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+    }
+    grid.close()
+    ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

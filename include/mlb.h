@@ -1,0 +1,197 @@
+/*
+ * mlb.h -- C ABI of the MI355X (gfx950) MacLABSWE library.
+ *
+ * MacLABSWE is the streaming-only ("tau = 1") lattice Boltzmann method for
+ * the shallow water equations of J. G. Zhou, arXiv 1902.02999.  One step
+ * rebuilds the depth h and the discharge (hu, hv) at every node from the
+ * local equilibria of the rest node and its 8 upstream neighbours
+ * (Eqs. Mac.lb.6 and Mac.lb.7), adds the centred bed-slope and force terms
+ * (Eqs. Mac.lb.3, force-CS), applies bounce-back no-slip walls and imposes
+ * macroscopic Dirichlet values directly (Section 3, simulation procedure
+ * steps (a)-(e)).
+ *
+ * Conventions
+ *   - Every call returns an mlb_status; nothing throws or aborts across the
+ *     ABI.  mlb_last_error() gives a thread-local message for the last failure.
+ *   - SI units.  Host fields are row-major [ny][ld] doubles with ld >= nx;
+ *     node (i, j) sits at x = i dx, y = j dx; i runs west->east, j south->north.
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied.  Handles belong to the caller until the matching *_destroy.
+ *   - Device memory is owned by the library unless the caller supplies a
+ *     workspace (mlb_grid_create); then the workspace must outlive the grid.
+ *   - One HIP stream per context; calls on one grid are not thread-safe.
+ *   - Fields live on the GPU in FP32 as the perturbation eta = h - H from the
+ *     still-water depth H = zeta_ref - z_b, plus qx = hu, qy = hv.
+ */
+#ifndef MLB_H
+#define MLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLB_OK = 0,
+    MLB_E_INVAL = -1,          /* bad argument, size or handle               */
+    MLB_E_NOMEM = -2,          /* device or host allocation failed           */
+    MLB_E_DEVICE = -3,         /* a HIP call failed (message has the error)  */
+    MLB_E_UNSTABLE = -4,       /* g * H_max > e^2: the step is unstable      */
+    MLB_E_NONFINITE = -5,      /* a check found a non-finite value or h <= 0 */
+    MLB_E_STATE = -6,          /* call not allowed in the object's state     */
+    MLB_E_NOTCONVERGED = -7    /* max_steps reached before the tolerance     */
+} mlb_status;
+
+/* Edge kinds.  Edges are indexed W=0 (i = 0), E=1 (i = nx-1), S=2 (j = 0),
+ * N=3 (j = ny-1).  Boundary nodes are computational nodes of the lattice.
+ *  WALL      no-slip wall: links from outside are bounced back
+ *            (f_a^eq = f_abar^eq of the node itself), then hu = hv = 0
+ *            (Section 3, the bounce-back example after the stability note).
+ *  PERIODIC  the lattice wraps; must be set on both W and E, or on both S and N.
+ *  DEPTH     h is imposed, h = h_mean + amp - amp sin(2 pi t / T + phase);
+ *            the discharge is extrapolated from the inner nodes.
+ *  DISCHARGE (hu, hv) is imposed; the free surface h + z_b is extrapolated
+ *            from the inner nodes.
+ * A node on two edges takes the kind WALL over DISCHARGE over DEPTH.  Two
+ * adjacent edges may not both be open (DEPTH/DISCHARGE). */
+enum { MLB_EDGE_WALL = 0, MLB_EDGE_PERIODIC = 1, MLB_EDGE_DEPTH = 2, MLB_EDGE_DISCHARGE = 3 };
+enum { MLB_W = 0, MLB_E = 1, MLB_S = 2, MLB_N = 3 };
+
+typedef struct {
+    int32_t nx, ny;        /* nodes per direction, >= 4 each (>= 5 with open edges)        */
+    double  dx;            /* lattice size [m]                                             */
+    double  nu;            /* eddy viscosity [m^2/s]; e = 6 nu / dx, dt = dx / e (Eq. mlb-viscosity) */
+    double  g;             /* gravity, 9.81 in the paper                                   */
+    double  rho_w;         /* water density for the stresses (not given in the paper)      */
+    double  rho_air;       /* air density, 1.293 (Eq. wind_u-stress)                       */
+    double  c_w;           /* wind drag coefficient, 0.0026 (Eq. wind_u-stress)            */
+    double  omega;         /* Coriolis parameter (Eq. SWE-force)                           */
+    double  zeta_ref;      /* still-water level: H = zeta_ref - z_b                        */
+    int32_t edge[4];       /* W, E, S, N edge kinds                                        */
+    int32_t extrap_order;  /* 1: zero-gradient, 2: linear extrapolation at open edges      */
+} mlb_params;
+
+/* Diagnostics of the last completed step (FP64, fixed summation order). */
+typedef struct {
+    int64_t step;          /* steps taken                                                  */
+    double  t;             /* step * dt [s]                                                */
+    double  mass;          /* sum of h dx^2 over all nodes [m^3]                           */
+    double  residual;      /* |q(n) - q(n-1)|_2 / |q(n)|_2, both components; 0 if no change */
+    double  max_speed;     /* max |q| / h [m/s]                                            */
+    int64_t nonfinite;     /* nodes with a non-finite value or h <= 0                      */
+    double  e, dt;         /* lattice speed [m/s] and time step [s]                         */
+    double  gh_over_e2;    /* g * H_max / e^2 (must stay <= 1)                             */
+    double  rle;           /* lattice Reynolds number max_speed * dx / nu (< 1 advised)    */
+} mlb_diag_t;
+
+typedef struct mlb_ctx   mlb_ctx;
+typedef struct mlb_grid  mlb_grid;
+typedef struct mlb_batch mlb_batch;
+
+/* Status text and the calling thread's last error message (never NULL). */
+const char* mlb_status_str(mlb_status s);
+const char* mlb_last_error(void);
+
+/* A context binds one GPU and one HIP stream.  stream == NULL: the library
+ * creates its own stream (default priority).  Otherwise the caller's
+ * hipStream_t is used and must outlive the context. */
+mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out);
+/* MLB_E_STATE while grids or batches created from it are alive. */
+mlb_status mlb_ctx_destroy(mlb_ctx* ctx);
+/* Blocks until the context's stream is idle. */
+mlb_status mlb_ctx_sync(mlb_ctx* ctx);
+
+/* Device bytes a grid with these parameters needs (fields, still-water depth,
+ * tile list, reduction partials, counters), for a caller-owned workspace. */
+mlb_status mlb_grid_workspace_bytes(const mlb_params* p, size_t* bytes);
+/* Creates a grid.  dev_workspace == NULL: the library allocates device memory.
+ * Otherwise it must be a device pointer of at least mlb_grid_workspace_bytes,
+ * 256-byte aligned, owned by the caller and kept alive until the grid is destroyed.
+ * The new grid has a flat bed at zeta_ref - 1, still water and no forcing. */
+mlb_status mlb_grid_create(mlb_ctx* ctx, const mlb_params* p, void* dev_workspace,
+                           size_t ws_bytes, mlb_grid** out);
+mlb_status mlb_grid_destroy(mlb_grid* g);
+
+/* Bed elevation z_b [ny][ld] (host, copied).  Sets H = zeta_ref - z_b (FP64,
+ * stored FP32), still water (eta = 0, q = 0) and resets the step counter.
+ * MLB_E_UNSTABLE if g * max(H) > e^2 (linear stability of the step);
+ * MLB_E_INVAL if some H <= 0 (no wetting/drying). */
+mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld);
+
+/* Uniform wind speed (u_wx, u_wy) [m/s]: tau_w / rho = rho_air c_w u_w |u_w| / rho_w
+ * (Eq. wind_u-stress). */
+mlb_status mlb_set_wind(mlb_grid* g, double uwx, double uwy);
+/* Uniform wind stress divided by the water density [m^2/s^2]. */
+mlb_status mlb_set_wind_stress(mlb_grid* g, double tx_over_rho, double ty_over_rho);
+/* Chezy coefficient: C_b = g / cz^2 (Eq. bed-stress); cz <= 0 removes friction. */
+mlb_status mlb_set_chezy(mlb_grid* g, double cz);
+/* DEPTH edge data: h = h_mean + amp - amp sin(2 pi t / period + phase);
+ * period <= 0 means the constant h_mean + amp - amp sin(phase).
+ * MLB_E_INVAL unless the edge is of kind DEPTH. */
+mlb_status mlb_set_edge_depth(mlb_grid* g, int edge, double h_mean, double amp,
+                              double period, double phase);
+/* DISCHARGE edge data (hu, hv) [m^2/s]; MLB_E_INVAL unless the edge is DISCHARGE. */
+mlb_status mlb_set_edge_discharge(mlb_grid* g, int edge, double qx, double qy);
+
+/* State from host arrays h, hu, hv [ny][ld] (copied; eta = h - H is rounded
+ * to FP32).  Any of hu / hv may be NULL (zero).  Resets the step counter to
+ * step0 (t = step0 dt). */
+mlb_status mlb_set_state(mlb_grid* g, const double* h, const double* hu, const double* hv,
+                         int64_t ld, int64_t step0);
+/* State from device FP32 arrays eta, qx, qy, each [ny][nx] contiguous
+ * (device-to-device copy on the context stream; the step counter is kept). */
+mlb_status mlb_set_state_device(mlb_grid* g, const float* eta, const float* qx, const float* qy);
+/* Current h = H + eta, hu, hv into host arrays [ny][ld] (any may be NULL);
+ * synchronises the stream. */
+mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t ld);
+/* Current FP32 fields copied to device arrays [ny][nx] (any may be NULL). */
+mlb_status mlb_get_state_device(mlb_grid* g, float* eta, float* qx, float* qy, float* H);
+
+/* Advances nsteps steps (enqueued on the context stream; returns without
+ * waiting).  MLB_E_STATE if the grid belongs to a live batch. */
+mlb_status mlb_step(mlb_grid* g, int64_t nsteps);
+/* Diagnostics of the last step (runs one extra reduction pass over the state;
+ * the residual needs the previous step and is 0 right after a set_*). Syncs. */
+mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out);
+/* Steps until the residual of a checked step is <= tol.  Checks every
+ * check_every steps (the checked step is reduced in the same kernel pass).
+ * MLB_E_NONFINITE on a non-finite value or h <= 0, MLB_E_NOTCONVERGED after
+ * max_steps.  out (may be NULL) receives the last check. */
+mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t check_every,
+                          mlb_diag_t* out);
+
+/* Execution options of the step (results are bitwise identical for any
+ * choice): rows per tile, temporal block depth (sub-steps per pass), and
+ * whether step loops are captured and replayed as a hipGraph. */
+typedef struct {
+    int32_t tile_rows;     /* output rows per wave tile, >= 4                             */
+    int32_t tblock;        /* sub-steps per kernel pass: 1 or 2                           */
+    int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
+    int32_t graph_chunk;   /* steps per captured graph                                    */
+} mlb_exec_opts;
+mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
+mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
+
+/* Batches: many grids advanced together by one persistent kernel launch per
+ * step driven by a tile work queue (largest basins first).  Grids keep their
+ * own parameters and boundary data; while in a batch they cannot be stepped
+ * alone.  Destroying the batch hands the grids back with their state. */
+mlb_status mlb_batch_create(mlb_ctx* ctx, mlb_grid* const* grids, int32_t n, mlb_batch** out);
+mlb_status mlb_batch_step(mlb_batch* b, int64_t nsteps);
+/* Steps the batch until every basin's checked residual is <= tol (per-basin
+ * diagnostics in per_basin[n], may be NULL). */
+mlb_status mlb_batch_run_steady(mlb_batch* b, double tol, int64_t max_steps,
+                                int32_t check_every, mlb_diag_t* per_basin);
+mlb_status mlb_batch_set_exec_opts(mlb_batch* b, const mlb_exec_opts* o);
+mlb_status mlb_batch_destroy(mlb_batch* b);
+
+/* Kernel time of the last mlb_step / mlb_batch_step call measured with HIP
+ * events on the context stream around the step launches [ms]. */
+mlb_status mlb_last_step_ms(mlb_ctx* ctx, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLB_H */

@@ -1,0 +1,867 @@
+// Host runtime behind the C ABI of include/mlb.h: contexts, grids, batches,
+// parameter derivation and validation, tile plans, hipGraph step chunks,
+// FP64 diagnostics.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mlb.h"
+#include "mlb_internal.h"
+
+using namespace mlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+mlb_status fail(mlb_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? MLB_E_NOMEM : MLB_E_DEVICE,             \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+#define CHK(expr)                                 \
+    do {                                          \
+        mlb_status s_ = (expr);                   \
+        if (s_ != MLB_OK) return s_;              \
+    } while (0)
+
+inline bool is_open(int k) { return k == MLB_EDGE_DEPTH || k == MLB_EDGE_DISCHARGE; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device-side plan of a set of basins: descriptors, tile list,
+// reduction partials, and an optional captured chunk of steps.
+struct Plan {
+    std::vector<BasinDev> hb;
+    std::vector<TileDev> ht;
+    BasinDev* db = nullptr;
+    TileDev* dt = nullptr;
+    double* dpart = nullptr;
+    double* dout = nullptr;
+    double* hout = nullptr;  // pinned
+    int parity = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int gparity = -1;
+    int gsteps = 0;
+    bool built = false;
+
+    void release()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0;
+        (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dpart);
+        (void)hipFree(dout);
+        if (hout) (void)hipHostFree(hout);
+        db = nullptr; dt = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
+        built = false;
+    }
+};
+
+}  // namespace
+
+struct mlb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int live = 0;
+    int ncu = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+struct mlb_grid {
+    mlb_ctx* ctx = nullptr;
+    mlb_params p{};
+    int ld = 0;
+    size_t plane = 0;          // floats per field plane
+    char* base = nullptr;
+    bool own = false;
+    float* eta[2] = {nullptr, nullptr};
+    float* qx[2] = {nullptr, nullptr};
+    float* qy[2] = {nullptr, nullptr};
+    float* H = nullptr;
+    int64_t* stepc = nullptr;
+    std::vector<float> Hf;     // stored (FP32) still-water depth, host copy
+    std::vector<double> Hd;    // still-water depth zeta_ref - z_b as given (FP64):
+                               // host conversions h <-> eta and the mass use it
+    int cur = 0;
+    int64_t step = 0;
+    double e = 0, dt = 0, sumH = 0, Hmax = 0;
+    double tx = 0, ty = 0, cb = 0;
+    double bc_hmean[4] = {0, 0, 0, 0}, bc_amp[4] = {0, 0, 0, 0}, bc_om[4] = {0, 0, 0, 0},
+           bc_phase[4] = {0, 0, 0, 0}, bc_qx[4] = {0, 0, 0, 0}, bc_qy[4] = {0, 0, 0, 0};
+    mlb_batch* batch = nullptr;
+    mlb_exec_opts opts{64, 1, 1, 64};
+    Plan plan;
+    bool dirty = true;         // descriptor must be re-uploaded
+    bool stale_plan = true;    // tiles / allocation must be rebuilt
+};
+
+struct mlb_batch {
+    mlb_ctx* ctx = nullptr;
+    std::vector<mlb_grid*> grids;
+    mlb_exec_opts opts{64, 1, 1, 64};
+    Plan plan;
+    bool stale_plan = true;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+BasinDev make_basin(const mlb_grid* g, int swap)
+{
+    BasinDev b{};
+    for (int k = 0; k < 2; ++k) { b.eta[k] = g->eta[k]; b.qx[k] = g->qx[k]; b.qy[k] = g->qy[k]; }
+    b.H = g->H;
+    b.stepc = g->stepc;
+    b.nx = g->p.nx; b.ny = g->p.ny; b.ld = g->ld;
+    b.swap = swap;
+    b.per_x = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC;
+    b.per_y = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
+    for (int k = 0; k < 4; ++k) b.kind[k] = g->p.edge[k];
+    b.extrap = g->p.extrap_order;
+    const double e = g->e, dt = g->dt, gr = g->p.g, e2 = e * e;
+    b.e = (float)e;
+    b.tpx = (float)(0.5 * dt * g->tx);
+    b.tpy = (float)(0.5 * dt * g->ty);
+    b.cfr = (float)(0.5 * dt * g->cb);
+    b.omh = (float)(0.5 * dt * g->p.omega);
+    b.c3e = (float)(1.0 / (3.0 * e));
+    b.ckk = (float)(2.0 / (3.0 * e2));
+    b.c6 = (float)(1.0 / (6.0 * e2));
+    b.c12 = (float)(1.0 / (12.0 * e2));
+    b.c4 = (float)(1.0 / (4.0 * e2));
+    b.cma = (float)(gr / (6.0 * e2));
+    b.cmd = (float)(gr / (24.0 * e2));
+    b.cqa = (float)(gr / (6.0 * e));
+    b.cqd = (float)(gr / (24.0 * e));
+    b.dt = dt;
+    for (int k = 0; k < 4; ++k) {
+        b.bc_qx[k] = (float)g->bc_qx[k];
+        b.bc_qy[k] = (float)g->bc_qy[k];
+        b.bc_hmean[k] = g->bc_hmean[k];
+        b.bc_amp[k] = g->bc_amp[k];
+        b.bc_om[k] = g->bc_om[k];
+        b.bc_phase[k] = g->bc_phase[k];
+    }
+    return b;
+}
+
+// Wave tiles of one basin: strips of 62 output columns, tiles of `rows` rows.
+// The last strip / tile is shifted inward so that edge extrapolation always
+// finds its inner nodes in the same tile; it then stores only what it owns.
+void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out)
+{
+    const int nx = g->p.nx, ny = g->p.ny;
+    const int ty = std::max(4, rows);
+    for (int yo = 0; yo < ny; yo += ty) {
+        const int y0 = std::min(yo, std::max(0, ny - ty));
+        const int yend = std::min(yo + ty, ny);
+        for (int xo = 0; xo < nx; xo += kStripOut) {
+            TileDev t{};
+            t.basin = basin;
+            t.xo = xo;
+            t.x0 = std::min(xo, std::max(0, nx - kStripOut));
+            t.yo = yo;
+            t.y0 = y0;
+            t.rows = yend - y0;
+            out.push_back(t);
+        }
+    }
+}
+
+mlb_status check_stream(mlb_ctx* c)
+{
+    HIPCHK(hipSetDevice(c->device));
+    return MLB_OK;
+}
+
+mlb_status plan_alloc(mlb_ctx* c, Plan& P)
+{
+    const size_t nb = P.hb.size(), nt = P.ht.size();
+    HIPCHK(hipMalloc(&P.db, nb * sizeof(BasinDev)));
+    HIPCHK(hipMalloc(&P.dt, nt * sizeof(TileDev)));
+    HIPCHK(hipMalloc(&P.dpart, nt * kPartials * sizeof(double)));
+    HIPCHK(hipMalloc(&P.dout, nb * 8 * sizeof(double)));
+    HIPCHK(hipHostMalloc(&P.hout, nb * 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(P.dt, P.ht.data(), nt * sizeof(TileDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(P.db, P.hb.data(), nb * sizeof(BasinDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    P.built = true;
+    return MLB_OK;
+}
+
+mlb_status upload_basins(mlb_ctx* c, Plan& P)
+{
+    HIPCHK(hipMemcpyAsync(P.db, P.hb.data(), P.hb.size() * sizeof(BasinDev), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLB_OK;
+}
+
+// Single-grid plan.
+mlb_status grid_plan(mlb_grid* g)
+{
+    mlb_ctx* c = g->ctx;
+    if (g->stale_plan || !g->plan.built) {
+        g->plan.release();
+        g->plan.hb.assign(1, make_basin(g, g->cur));
+        g->plan.parity = 0;
+        g->plan.ht.clear();
+        make_tiles(g, 0, g->opts.tile_rows, g->plan.ht);
+        g->plan.hb[0].first_tile = 0;
+        g->plan.hb[0].ntiles = (int)g->plan.ht.size();
+        CHK(plan_alloc(c, g->plan));
+        g->stale_plan = false;
+        g->dirty = false;
+    } else if (g->dirty) {
+        BasinDev b = make_basin(g, g->plan.parity ^ g->cur);
+        b.first_tile = 0;
+        b.ntiles = (int)g->plan.ht.size();
+        g->plan.hb[0] = b;
+        CHK(upload_basins(c, g->plan));
+        g->dirty = false;
+    }
+    return MLB_OK;
+}
+
+// Launch n steps of a plan; the last one reduces into partials when diag.
+// Advances the plan parity per launch; graph chunks replay when aligned.
+mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n, bool diag_last)
+{
+    const int ntiles = (int)P.ht.size();
+    auto eager = [&](bool diag) -> mlb_status {
+        HIPCHK(launch_step(P.db, P.dt, ntiles, P.parity, P.dpart, diag ? 1 : 0, 1, c->stream));
+        P.parity ^= 1;
+        return MLB_OK;
+    };
+    int64_t plain = diag_last ? n - 1 : n;
+    const int chunk = std::max(2, o.graph_chunk & ~1);
+    if (o.use_graph && plain >= chunk) {
+        if (!P.gexec || P.gsteps != chunk) {
+            if (P.gexec) { (void)hipGraphExecDestroy(P.gexec); P.gexec = nullptr; }
+            if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
+            HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            int par = P.parity;
+            hipError_t le = hipSuccess;
+            for (int i = 0; i < chunk && le == hipSuccess; ++i) {
+                le = launch_step(P.db, P.dt, ntiles, par, P.dpart, 0, 1, c->stream);
+                par ^= 1;
+            }
+            hipGraph_t gr = nullptr;
+            hipError_t ee = hipStreamEndCapture(c->stream, &gr);
+            if (le != hipSuccess) return fail(MLB_E_DEVICE, std::string("capture: ") + hipGetErrorString(le));
+            if (ee != hipSuccess) return fail(MLB_E_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
+            P.graph = gr;
+            HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
+            P.gsteps = chunk;
+            P.gparity = P.parity;
+        }
+        if (P.parity != P.gparity) {
+            CHK(eager(false));
+            --plain;
+        }
+        while (plain >= chunk) {
+            HIPCHK(hipGraphLaunch(P.gexec, c->stream));
+            plain -= chunk;
+        }
+    }
+    for (int64_t i = 0; i < plain; ++i) CHK(eager(false));
+    if (diag_last && n >= 1) CHK(eager(true));
+    return MLB_OK;
+}
+
+mlb_status validate_params(const mlb_params* p)
+{
+    if (!p) return fail(MLB_E_INVAL, "params is NULL");
+    const bool px = p->edge[MLB_W] == MLB_EDGE_PERIODIC, ex = p->edge[MLB_E] == MLB_EDGE_PERIODIC;
+    const bool py = p->edge[MLB_S] == MLB_EDGE_PERIODIC, ey = p->edge[MLB_N] == MLB_EDGE_PERIODIC;
+    for (int k = 0; k < 4; ++k)
+        if (p->edge[k] < MLB_EDGE_WALL || p->edge[k] > MLB_EDGE_DISCHARGE)
+            return fail(MLB_E_INVAL, "unknown edge kind");
+    if (px != ex || py != ey) return fail(MLB_E_INVAL, "periodic edges must be set in pairs");
+    const bool ox = is_open(p->edge[MLB_W]) || is_open(p->edge[MLB_E]);
+    const bool oy = is_open(p->edge[MLB_S]) || is_open(p->edge[MLB_N]);
+    if (ox && oy) return fail(MLB_E_INVAL, "two adjacent edges may not both be open");
+    const int minx = px ? 3 : (ox ? 5 : 4), miny = py ? 3 : (oy ? 5 : 4);
+    if (p->nx < minx || p->ny < miny) return fail(MLB_E_INVAL, "grid too small for its edges");
+    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return fail(MLB_E_INVAL, "grid too large");
+    if (!(p->dx > 0) || !(p->nu > 0) || !(p->g > 0) || !(p->rho_w > 0))
+        return fail(MLB_E_INVAL, "dx, nu, g and rho_w must be positive");
+    if (p->extrap_order != 1 && p->extrap_order != 2) return fail(MLB_E_INVAL, "extrap_order must be 1 or 2");
+    return MLB_OK;
+}
+
+size_t field_bytes(const mlb_params* p, int* ld_out)
+{
+    const int ld = (int)align_up((size_t)p->nx, 64);
+    if (ld_out) *ld_out = ld;
+    return 256 + 7 * align_up((size_t)ld * p->ny * sizeof(float), 256);
+}
+
+mlb_status upload_host_state(mlb_grid* g, const double* h, const double* hu, const double* hv,
+                             int64_t ld)
+{
+    const int nx = g->p.nx, ny = g->p.ny;
+    std::vector<float> e((size_t)g->ld * ny, 0.f), a((size_t)g->ld * ny, 0.f), b((size_t)g->ld * ny, 0.f);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t s = (size_t)j * ld + i, d = (size_t)j * g->ld + i;
+            e[d] = h ? (float)(h[s] - g->Hd[d]) : 0.f;
+            a[d] = hu ? (float)hu[s] : 0.f;
+            b[d] = hv ? (float)hv[s] : 0.f;
+        }
+    const size_t bytes = e.size() * sizeof(float);
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(hipMemcpyAsync(g->eta[k], e.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qx[k], a.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qy[k], b.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    return MLB_OK;
+}
+
+mlb_status set_step(mlb_grid* g, int64_t s)
+{
+    int64_t v[2] = {s, s};
+    HIPCHK(hipMemcpyAsync(g->stepc, v, sizeof(v), hipMemcpyHostToDevice, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    g->step = s;
+    return MLB_OK;
+}
+
+void fill_diag(const mlb_grid* g, const double* o, mlb_diag_t* d)
+{
+    d->step = g->step;
+    d->t = (double)g->step * g->dt;
+    d->mass = (g->sumH + o[0]) * g->p.dx * g->p.dx;
+    d->residual = o[1] > 0 ? std::sqrt(o[1]) / std::sqrt(o[2]) : 0.0;
+    d->max_speed = o[4];
+    d->nonfinite = (int64_t)o[3];
+    d->e = g->e;
+    d->dt = g->dt;
+    d->gh_over_e2 = g->p.g * g->Hmax / (g->e * g->e);
+    d->rle = o[4] * g->p.dx / g->p.nu;
+}
+
+mlb_status read_diag(mlb_ctx* c, Plan& P)
+{
+    HIPCHK(launch_finalize(P.db, (int)P.hb.size(), P.dpart, P.dout, c->stream));
+    HIPCHK(hipMemcpyAsync(P.hout, P.dout, P.hb.size() * 8 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLB_OK;
+}
+
+#define GRID_OK(g)                                                         \
+    do {                                                                   \
+        if (!(g)) return fail(MLB_E_INVAL, "grid is NULL");                \
+        CHK(check_stream((g)->ctx));                                       \
+    } while (0)
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* mlb_status_str(mlb_status s)
+{
+    switch (s) {
+    case MLB_OK: return "ok";
+    case MLB_E_INVAL: return "invalid argument";
+    case MLB_E_NOMEM: return "out of memory";
+    case MLB_E_DEVICE: return "device error";
+    case MLB_E_UNSTABLE: return "unstable parameters (g H > e^2)";
+    case MLB_E_NONFINITE: return "non-finite value or dry node";
+    case MLB_E_STATE: return "invalid state for this call";
+    case MLB_E_NOTCONVERGED: return "not converged";
+    }
+    return "unknown status";
+}
+
+const char* mlb_last_error(void) { return g_err.c_str(); }
+
+mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out)
+{
+    if (!out) return fail(MLB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(MLB_E_INVAL, "no such device");
+    HIPCHK(hipSetDevice(device));
+    mlb_ctx* c = new (std::nothrow) mlb_ctx();
+    if (!c) return fail(MLB_E_NOMEM, "ctx");
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete c; return fail(MLB_E_DEVICE, hipGetErrorString(e)); }
+        c->own_stream = true;
+    }
+    (void)hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (c->ncu <= 0) c->ncu = 256;
+    (void)hipEventCreate(&c->ev0);
+    (void)hipEventCreate(&c->ev1);
+    *out = c;
+    return MLB_OK;
+}
+
+mlb_status mlb_ctx_destroy(mlb_ctx* c)
+{
+    if (!c) return fail(MLB_E_INVAL, "ctx is NULL");
+    if (c->live) return fail(MLB_E_STATE, "grids or batches still alive");
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return MLB_OK;
+}
+
+mlb_status mlb_ctx_sync(mlb_ctx* c)
+{
+    if (!c) return fail(MLB_E_INVAL, "ctx is NULL");
+    CHK(check_stream(c));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLB_OK;
+}
+
+mlb_status mlb_grid_workspace_bytes(const mlb_params* p, size_t* bytes)
+{
+    CHK(validate_params(p));
+    if (!bytes) return fail(MLB_E_INVAL, "bytes is NULL");
+    *bytes = field_bytes(p, nullptr);
+    return MLB_OK;
+}
+
+mlb_status mlb_grid_create(mlb_ctx* c, const mlb_params* p, void* ws, size_t ws_bytes, mlb_grid** out)
+{
+    if (!c || !out) return fail(MLB_E_INVAL, "ctx or out is NULL");
+    *out = nullptr;
+    CHK(validate_params(p));
+    CHK(check_stream(c));
+    int ld = 0;
+    const size_t need = field_bytes(p, &ld);
+    if (ws && (ws_bytes < need || ((uintptr_t)ws & 255)))
+        return fail(MLB_E_INVAL, "workspace too small or not 256-byte aligned");
+    mlb_grid* g = new (std::nothrow) mlb_grid();
+    if (!g) return fail(MLB_E_NOMEM, "grid");
+    g->ctx = c;
+    g->p = *p;
+    g->ld = ld;
+    g->plane = align_up((size_t)ld * p->ny * sizeof(float), 256) / sizeof(float);
+    if (ws) {
+        g->base = (char*)ws;
+    } else {
+        hipError_t e = hipMalloc((void**)&g->base, need);
+        if (e != hipSuccess) { delete g; return fail(MLB_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+        g->own = true;
+    }
+    g->stepc = (int64_t*)g->base;
+    float* f = (float*)(g->base + 256);
+    g->eta[0] = f; g->eta[1] = f + g->plane;
+    g->qx[0] = f + 2 * g->plane; g->qx[1] = f + 3 * g->plane;
+    g->qy[0] = f + 4 * g->plane; g->qy[1] = f + 5 * g->plane;
+    g->H = f + 6 * g->plane;
+    g->e = 6.0 * p->nu / p->dx;   // Eq. (mlb-viscosity)
+    g->dt = p->dx / g->e;
+    c->live++;
+    // default: flat bed one metre below the still-water level
+    std::vector<double> zb((size_t)p->nx * p->ny, p->zeta_ref - 1.0);
+    mlb_status s = mlb_set_bathymetry(g, zb.data(), p->nx);
+    if (s != MLB_OK) { mlb_grid_destroy(g); return s; }
+    *out = g;
+    return MLB_OK;
+}
+
+mlb_status mlb_grid_destroy(mlb_grid* g)
+{
+    if (!g) return fail(MLB_E_INVAL, "grid is NULL");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    g->plan.release();
+    if (g->own) (void)hipFree(g->base);
+    g->ctx->live--;
+    delete g;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld)
+{
+    GRID_OK(g);
+    if (!zb || ld < g->p.nx) return fail(MLB_E_INVAL, "zb is NULL or ld < nx");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    const int nx = g->p.nx, ny = g->p.ny;
+    g->Hf.assign((size_t)g->ld * ny, 1.0f);
+    g->Hd.assign((size_t)g->ld * ny, 1.0);
+    double sum = 0, hmax = 0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const double Hd = g->p.zeta_ref - zb[(size_t)j * ld + i];
+            if (!(Hd > 0)) return fail(MLB_E_INVAL, "still-water depth must be positive everywhere");
+            const float Hs = (float)Hd;
+            g->Hf[(size_t)j * g->ld + i] = Hs;
+            g->Hd[(size_t)j * g->ld + i] = Hd;
+            sum += Hd;
+            hmax = std::max(hmax, Hd);
+        }
+    if (g->p.g * hmax > g->e * g->e)
+        return fail(MLB_E_UNSTABLE, "g * H_max > e^2: choose a larger nu (e = 6 nu / dx)");
+    g->sumH = sum;
+    g->Hmax = hmax;
+    HIPCHK(hipMemcpyAsync(g->H, g->Hf.data(), g->Hf.size() * sizeof(float), hipMemcpyHostToDevice,
+                          g->ctx->stream));
+    CHK(upload_host_state(g, nullptr, nullptr, nullptr, nx));
+    g->cur = 0;
+    g->dirty = true;
+    return set_step(g, 0);
+}
+
+mlb_status mlb_set_wind(mlb_grid* g, double uwx, double uwy)
+{
+    if (!g) return fail(MLB_E_INVAL, "grid is NULL");
+    const double s = std::sqrt(uwx * uwx + uwy * uwy);  // Eq. (wind_u-stress)
+    return mlb_set_wind_stress(g, g->p.rho_air * g->p.c_w * uwx * s / g->p.rho_w,
+                               g->p.rho_air * g->p.c_w * uwy * s / g->p.rho_w);
+}
+
+mlb_status mlb_set_wind_stress(mlb_grid* g, double tx, double ty)
+{
+    if (!g) return fail(MLB_E_INVAL, "grid is NULL");
+    if (!std::isfinite(tx) || !std::isfinite(ty)) return fail(MLB_E_INVAL, "non-finite stress");
+    g->tx = tx; g->ty = ty; g->dirty = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_chezy(mlb_grid* g, double cz)
+{
+    if (!g) return fail(MLB_E_INVAL, "grid is NULL");
+    g->cb = cz > 0 ? g->p.g / (cz * cz) : 0.0;  // Eq. (bed-stress)
+    g->dirty = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_edge_depth(mlb_grid* g, int edge, double h_mean, double amp, double period, double phase)
+{
+    if (!g || edge < 0 || edge > 3) return fail(MLB_E_INVAL, "bad grid or edge");
+    if (g->p.edge[edge] != MLB_EDGE_DEPTH) return fail(MLB_E_INVAL, "edge is not a DEPTH edge");
+    g->bc_hmean[edge] = h_mean; g->bc_amp[edge] = amp;
+    g->bc_om[edge] = period > 0 ? 2.0 * M_PI / period : 0.0;
+    g->bc_phase[edge] = phase;
+    g->dirty = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_edge_discharge(mlb_grid* g, int edge, double qx, double qy)
+{
+    if (!g || edge < 0 || edge > 3) return fail(MLB_E_INVAL, "bad grid or edge");
+    if (g->p.edge[edge] != MLB_EDGE_DISCHARGE) return fail(MLB_E_INVAL, "edge is not a DISCHARGE edge");
+    g->bc_qx[edge] = qx; g->bc_qy[edge] = qy;
+    g->dirty = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_state(mlb_grid* g, const double* h, const double* hu, const double* hv, int64_t ld,
+                         int64_t step0)
+{
+    GRID_OK(g);
+    if (!h || ld < g->p.nx || step0 < 0) return fail(MLB_E_INVAL, "h is NULL, ld < nx or step0 < 0");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    CHK(upload_host_state(g, h, hu, hv, ld));
+    return set_step(g, step0);
+}
+
+mlb_status mlb_set_state_device(mlb_grid* g, const float* eta, const float* qx, const float* qy)
+{
+    GRID_OK(g);
+    if (!eta || !qx || !qy) return fail(MLB_E_INVAL, "NULL device pointer");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    const size_t w = (size_t)g->p.nx * sizeof(float), pitch = (size_t)g->ld * sizeof(float);
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(hipMemcpy2DAsync(g->eta[k], pitch, eta, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpy2DAsync(g->qx[k], pitch, qx, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpy2DAsync(g->qy[k], pitch, qy, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+    }
+    return MLB_OK;
+}
+
+mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t ld)
+{
+    GRID_OK(g);
+    if (ld < g->p.nx) return fail(MLB_E_INVAL, "ld < nx");
+    const int nx = g->p.nx, ny = g->p.ny;
+    std::vector<float> e((size_t)g->ld * ny), a((size_t)g->ld * ny), b((size_t)g->ld * ny);
+    const size_t bytes = e.size() * sizeof(float);
+    HIPCHK(hipMemcpyAsync(e.data(), g->eta[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipMemcpyAsync(a.data(), g->qx[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipMemcpyAsync(b.data(), g->qy[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t s = (size_t)j * g->ld + i, d = (size_t)j * ld + i;
+            if (h) h[d] = g->Hd[s] + (double)e[s];
+            if (hu) hu[d] = a[s];
+            if (hv) hv[d] = b[s];
+        }
+    return MLB_OK;
+}
+
+mlb_status mlb_get_state_device(mlb_grid* g, float* eta, float* qx, float* qy, float* H)
+{
+    GRID_OK(g);
+    const size_t w = (size_t)g->p.nx * sizeof(float), pitch = (size_t)g->ld * sizeof(float);
+    const int ny = g->p.ny;
+    if (eta) HIPCHK(hipMemcpy2DAsync(eta, w, g->eta[g->cur], pitch, w, ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+    if (qx) HIPCHK(hipMemcpy2DAsync(qx, w, g->qx[g->cur], pitch, w, ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+    if (qy) HIPCHK(hipMemcpy2DAsync(qy, w, g->qy[g->cur], pitch, w, ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+    if (H) HIPCHK(hipMemcpy2DAsync(H, w, g->H, pitch, w, ny, hipMemcpyDeviceToDevice, g->ctx->stream));
+    return MLB_OK;
+}
+
+mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o)
+{
+    if (!g || !o) return fail(MLB_E_INVAL, "NULL argument");
+    *o = g->opts;
+    return MLB_OK;
+}
+
+static mlb_status check_opts(const mlb_exec_opts* o)
+{
+    if (!o) return fail(MLB_E_INVAL, "opts is NULL");
+    if (o->tile_rows < 4 || o->tile_rows > 4096) return fail(MLB_E_INVAL, "tile_rows out of range");
+    if (o->tblock != 1) return fail(MLB_E_INVAL, "tblock must be 1");
+    if (o->use_graph && (o->graph_chunk < 2 || o->graph_chunk > 100000))
+        return fail(MLB_E_INVAL, "graph_chunk out of range");
+    return MLB_OK;
+}
+
+mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o)
+{
+    if (!g) return fail(MLB_E_INVAL, "grid is NULL");
+    CHK(check_opts(o));
+    if (o->tile_rows != g->opts.tile_rows) g->stale_plan = true;
+    g->opts = *o;
+    if (g->plan.gexec && g->plan.gsteps != (o->graph_chunk & ~1)) {
+        (void)hipGraphExecDestroy(g->plan.gexec); g->plan.gexec = nullptr;
+        (void)hipGraphDestroy(g->plan.graph); g->plan.graph = nullptr;
+    }
+    return MLB_OK;
+}
+
+static void advance_grid(mlb_grid* g, int64_t n)
+{
+    g->step += n;
+    if (n & 1) g->cur ^= 1;
+}
+
+mlb_status mlb_step(mlb_grid* g, int64_t n)
+{
+    GRID_OK(g);
+    if (n < 0) return fail(MLB_E_INVAL, "nsteps < 0");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    if (n == 0) return MLB_OK;
+    CHK(grid_plan(g));
+    mlb_ctx* c = g->ctx;
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    CHK(enqueue_steps(c, g->plan, g->opts, n, false));
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+    advance_grid(g, n);
+    return MLB_OK;
+}
+
+mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out)
+{
+    GRID_OK(g);
+    if (!out) return fail(MLB_E_INVAL, "out is NULL");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    CHK(grid_plan(g));
+    Plan& P = g->plan;
+    HIPCHK(launch_reduce_state(P.db, P.dt, (int)P.ht.size(), P.parity, P.dpart, g->ctx->stream));
+    CHK(read_diag(g->ctx, P));
+    fill_diag(g, P.hout, out);
+    return MLB_OK;
+}
+
+mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t check_every, mlb_diag_t* out)
+{
+    GRID_OK(g);
+    if (check_every < 1 || max_steps < 1 || !(tol >= 0)) return fail(MLB_E_INVAL, "bad tol / max_steps / check_every");
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    CHK(grid_plan(g));
+    mlb_ctx* c = g->ctx;
+    const int64_t start = g->step;
+    mlb_diag_t d{};
+    while (g->step - start < max_steps) {
+        const int64_t n = std::min<int64_t>(check_every, max_steps - (g->step - start));
+        CHK(enqueue_steps(c, g->plan, g->opts, n, true));
+        advance_grid(g, n);
+        CHK(read_diag(c, g->plan));
+        fill_diag(g, g->plan.hout, &d);
+        if (out) *out = d;
+        if (d.nonfinite) return fail(MLB_E_NONFINITE, "non-finite value or dry node");
+        if (d.residual <= tol) return MLB_OK;
+    }
+    return fail(MLB_E_NOTCONVERGED, "max_steps reached");
+}
+
+mlb_status mlb_last_step_ms(mlb_ctx* c, double* ms)
+{
+    if (!c || !ms) return fail(MLB_E_INVAL, "NULL argument");
+    if (!c->timed) return fail(MLB_E_STATE, "no timed step yet");
+    CHK(check_stream(c));
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float f = 0;
+    HIPCHK(hipEventElapsedTime(&f, c->ev0, c->ev1));
+    *ms = f;
+    return MLB_OK;
+}
+
+// ------------------------------------------------------------------ batches
+static mlb_status batch_plan(mlb_batch* b)
+{
+    if (!b->stale_plan && b->plan.built) return MLB_OK;
+    b->plan.release();
+    const int n = (int)b->grids.size();
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    // largest basins first so their tiles enter the queue first
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (int64_t)b->grids[a]->p.nx * b->grids[a]->p.ny > (int64_t)b->grids[c]->p.nx * b->grids[c]->p.ny;
+    });
+    b->plan.hb.assign(n, BasinDev{});
+    b->plan.ht.clear();
+    b->plan.parity = 0;
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
+        mlb_grid* g = b->grids[i];
+        BasinDev d = make_basin(g, g->cur);
+        d.first_tile = (int)b->plan.ht.size();
+        make_tiles(g, i, b->opts.tile_rows, b->plan.ht);
+        d.ntiles = (int)b->plan.ht.size() - d.first_tile;
+        b->plan.hb[i] = d;
+    }
+    CHK(plan_alloc(b->ctx, b->plan));
+    b->stale_plan = false;
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_create(mlb_ctx* c, mlb_grid* const* grids, int32_t n, mlb_batch** out)
+{
+    if (!c || !grids || n < 1 || !out) return fail(MLB_E_INVAL, "bad batch arguments");
+    *out = nullptr;
+    CHK(check_stream(c));
+    for (int i = 0; i < n; ++i) {
+        if (!grids[i] || grids[i]->ctx != c) return fail(MLB_E_INVAL, "grid missing or from another context");
+        if (grids[i]->batch) return fail(MLB_E_STATE, "grid already in a batch");
+        for (int k = 0; k < i; ++k)
+            if (grids[k] == grids[i]) return fail(MLB_E_INVAL, "grid listed twice");
+    }
+    mlb_batch* b = new (std::nothrow) mlb_batch();
+    if (!b) return fail(MLB_E_NOMEM, "batch");
+    b->ctx = c;
+    b->grids.assign(grids, grids + n);
+    b->opts = grids[0]->opts;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    mlb_status s = batch_plan(b);
+    if (s != MLB_OK) { b->plan.release(); delete b; return s; }
+    for (auto* g : b->grids) g->batch = b;
+    c->live++;
+    *out = b;
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_set_exec_opts(mlb_batch* b, const mlb_exec_opts* o)
+{
+    if (!b) return fail(MLB_E_INVAL, "batch is NULL");
+    CHK(check_opts(o));
+    if (o->tile_rows != b->opts.tile_rows) {
+        // rebuild with the current buffers as the starting parity
+        b->stale_plan = true;
+    }
+    b->opts = *o;
+    if (b->plan.gexec && b->plan.gsteps != (o->graph_chunk & ~1)) {
+        (void)hipGraphExecDestroy(b->plan.gexec); b->plan.gexec = nullptr;
+        (void)hipGraphDestroy(b->plan.graph); b->plan.graph = nullptr;
+    }
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_step(mlb_batch* b, int64_t n)
+{
+    if (!b) return fail(MLB_E_INVAL, "batch is NULL");
+    if (n < 0) return fail(MLB_E_INVAL, "nsteps < 0");
+    CHK(check_stream(b->ctx));
+    if (n == 0) return MLB_OK;
+    CHK(batch_plan(b));
+    mlb_ctx* c = b->ctx;
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    CHK(enqueue_steps(c, b->plan, b->opts, n, false));
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+    for (auto* g : b->grids) advance_grid(g, n);
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_run_steady(mlb_batch* b, double tol, int64_t max_steps, int32_t check_every,
+                                mlb_diag_t* per)
+{
+    if (!b) return fail(MLB_E_INVAL, "batch is NULL");
+    if (check_every < 1 || max_steps < 1 || !(tol >= 0)) return fail(MLB_E_INVAL, "bad tol / max_steps / check_every");
+    CHK(check_stream(b->ctx));
+    CHK(batch_plan(b));
+    mlb_ctx* c = b->ctx;
+    int64_t done = 0;
+    const int n = (int)b->grids.size();
+    while (done < max_steps) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+        CHK(enqueue_steps(c, b->plan, b->opts, k, true));
+        for (auto* g : b->grids) advance_grid(g, k);
+        done += k;
+        CHK(read_diag(c, b->plan));
+        bool all = true, bad = false;
+        for (int i = 0; i < n; ++i) {
+            mlb_diag_t d{};
+            fill_diag(b->grids[i], b->plan.hout + 8 * i, &d);
+            if (per) per[i] = d;
+            bad |= d.nonfinite != 0;
+            all &= d.residual <= tol;
+        }
+        if (bad) return fail(MLB_E_NONFINITE, "non-finite value or dry node in a basin");
+        if (all) return MLB_OK;
+    }
+    return fail(MLB_E_NOTCONVERGED, "max_steps reached");
+}
+
+mlb_status mlb_batch_destroy(mlb_batch* b)
+{
+    if (!b) return fail(MLB_E_INVAL, "batch is NULL");
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    b->plan.release();
+    for (auto* g : b->grids) {
+        g->batch = nullptr;
+        g->dirty = true;   // the grid's own plan must re-derive its buffer parity
+    }
+    b->ctx->live--;
+    delete b;
+    return MLB_OK;
+}
+
+}  // extern "C"

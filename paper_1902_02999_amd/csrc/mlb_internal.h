@@ -1,0 +1,63 @@
+// Internal data structures shared by the gfx950 kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlb {
+
+// Output columns per wave strip: a wave's 64 lanes cover columns x0-1 .. x0+62;
+// lanes 1..62 produce outputs, lanes 0 and 63 only supply neighbour values.
+constexpr int kStripOut = 62;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // 4 independent waves per workgroup
+constexpr int kPartials = 6;           // per-tile FP64 partial sums
+
+enum { EDGE_WALL = 0, EDGE_PERIODIC = 1, EDGE_DEPTH = 2, EDGE_DISCHARGE = 3 };
+
+// Per-basin descriptor read by the step kernel (device memory).
+struct BasinDev {
+    float* eta[2];
+    float* qx[2];
+    float* qy[2];
+    const float* H;
+    int64_t* stepc;        // [2]: step counter, read from [rd], written to [1-rd]
+    int32_t nx, ny, ld;
+    int32_t swap;          // buffer read by a launch of parity p is p ^ swap
+    int32_t per_x, per_y;
+    int32_t kind[4];       // W, E, S, N
+    int32_t extrap;        // 1 or 2
+    int32_t first_tile, ntiles;
+    // FP32 constants of the step (computed in FP64 on the host, then rounded)
+    float e;               // lattice speed
+    float tpx, tpy;        // (dt/2) tau_w / rho
+    float cfr;             // (dt/2) C_b
+    float omh;             // (dt/2) Omega
+    float c3e;             // 1 / (3e)
+    float ckk;             // 2 / (3e^2)
+    float c6, c12, c4;     // 1/(6e^2), 1/(12e^2), 1/(4e^2)
+    float cma, cmd;        // g/(6e^2), g/(24e^2)
+    float cqa, cqd;        // g/(6e),  g/(24e)
+    float bc_qx[4], bc_qy[4];
+    double dt;
+    double bc_hmean[4], bc_amp[4], bc_om[4], bc_phase[4];
+};
+
+// One wave's work item: a strip of up to 62 columns and `rows` rows.
+struct TileDev {
+    int32_t basin;
+    int32_t x0, y0, rows;  // first output column / row and number of rows computed
+    int32_t xo, yo;        // first owned column / row (overlapped edge tiles store only these)
+    int32_t pad[2];
+};
+
+// Host-side launchers (mlb_kernels.hip).
+hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
+                       double* d_partials, int diag, int tblock, hipStream_t s);
+hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
+                               int parity, double* d_partials, hipStream_t s);
+int step_occupancy(int diag);
+hipError_t launch_finalize(const BasinDev* d_basins, int nbasins, const double* d_partials,
+                           double* d_out, hipStream_t s);
+
+}  // namespace mlb

@@ -1,0 +1,322 @@
+"""ctypes binding of the C ABI in include/mlb.h (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of libmlb.so; this module
+only converts numpy / torch arguments and raises on error codes.  Loading
+fails loudly if libmlb.so has not been built (python -m
+paper_1902_02999_amd.build); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlb.so")
+
+WALL, PERIODIC, DEPTH, DISCHARGE = 0, 1, 2, 3
+W, E, S, N = 0, 1, 2, 3
+
+STATUS = {0: "MLB_OK", -1: "MLB_E_INVAL", -2: "MLB_E_NOMEM", -3: "MLB_E_DEVICE",
+          -4: "MLB_E_UNSTABLE", -5: "MLB_E_NONFINITE", -6: "MLB_E_STATE",
+          -7: "MLB_E_NOTCONVERGED"}
+
+
+class MlbError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed: %s (%s)" % (where, STATUS.get(code, code), msg))
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("nu", C.c_double),
+                ("g", C.c_double), ("rho_w", C.c_double), ("rho_air", C.c_double),
+                ("c_w", C.c_double), ("omega", C.c_double), ("zeta_ref", C.c_double),
+                ("edge", C.c_int32 * 4), ("extrap_order", C.c_int32)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("mass", C.c_double),
+                ("residual", C.c_double), ("max_speed", C.c_double), ("nonfinite", C.c_int64),
+                ("e", C.c_double), ("dt", C.c_double), ("gh_over_e2", C.c_double),
+                ("rle", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ExecOpts(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("tblock", C.c_int32), ("use_graph", C.c_int32),
+                ("graph_chunk", C.c_int32)]
+
+
+# Every exported symbol of include/mlb.h with its ctypes signature.
+_VP = C.c_void_p
+_DP = C.POINTER(C.c_double)
+SIGNATURES = {
+    "mlb_status_str": (C.c_char_p, [C.c_int]),
+    "mlb_last_error": (C.c_char_p, []),
+    "mlb_ctx_create": (C.c_int, [C.c_int, _VP, C.POINTER(_VP)]),
+    "mlb_ctx_destroy": (C.c_int, [_VP]),
+    "mlb_ctx_sync": (C.c_int, [_VP]),
+    "mlb_grid_workspace_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    "mlb_grid_create": (C.c_int, [_VP, C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)]),
+    "mlb_grid_destroy": (C.c_int, [_VP]),
+    "mlb_set_bathymetry": (C.c_int, [_VP, _DP, C.c_int64]),
+    "mlb_set_wind": (C.c_int, [_VP, C.c_double, C.c_double]),
+    "mlb_set_wind_stress": (C.c_int, [_VP, C.c_double, C.c_double]),
+    "mlb_set_chezy": (C.c_int, [_VP, C.c_double]),
+    "mlb_set_edge_depth": (C.c_int, [_VP, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "mlb_set_edge_discharge": (C.c_int, [_VP, C.c_int, C.c_double, C.c_double]),
+    "mlb_set_state": (C.c_int, [_VP, _DP, _DP, _DP, C.c_int64, C.c_int64]),
+    "mlb_set_state_device": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "mlb_get_state": (C.c_int, [_VP, _DP, _DP, _DP, C.c_int64]),
+    "mlb_get_state_device": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "mlb_step": (C.c_int, [_VP, C.c_int64]),
+    "mlb_diag": (C.c_int, [_VP, C.POINTER(Diag)]),
+    "mlb_run_steady": (C.c_int, [_VP, C.c_double, C.c_int64, C.c_int32, C.POINTER(Diag)]),
+    "mlb_get_exec_opts": (C.c_int, [_VP, C.POINTER(ExecOpts)]),
+    "mlb_set_exec_opts": (C.c_int, [_VP, C.POINTER(ExecOpts)]),
+    "mlb_batch_create": (C.c_int, [_VP, C.POINTER(_VP), C.c_int32, C.POINTER(_VP)]),
+    "mlb_batch_step": (C.c_int, [_VP, C.c_int64]),
+    "mlb_batch_run_steady": (C.c_int, [_VP, C.c_double, C.c_int64, C.c_int32, C.POINTER(Diag)]),
+    "mlb_batch_set_exec_opts": (C.c_int, [_VP, C.POINTER(ExecOpts)]),
+    "mlb_batch_destroy": (C.c_int, [_VP]),
+    "mlb_last_step_ms": (C.c_int, [_VP, _DP]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmlb.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmlb.so is not built; run `python -m paper_1902_02999_amd.build`")
+        L = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise MlbError(code, where, lib().mlb_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), shape))
+
+
+def _tensor_ptr(t):
+    """Device pointer of a torch tensor or an int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+class Context:
+    """One GPU and one HIP stream.  stream: None (library-owned stream) or a
+    torch.cuda.Stream / raw hipStream_t int (not the legacy default stream if
+    graphs are used)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = _VP()
+        s = None
+        if stream is not None:
+            s = stream if isinstance(stream, int) else stream.cuda_stream
+        _check(lib().mlb_ctx_create(device, s, C.byref(h)), "mlb_ctx_create")
+        self.h = h
+        self.device = device
+
+    def sync(self):
+        _check(lib().mlb_ctx_sync(self.h), "mlb_ctx_sync")
+
+    def last_step_ms(self) -> float:
+        v = C.c_double()
+        _check(lib().mlb_last_step_ms(self.h, C.byref(v)), "mlb_last_step_ms")
+        return v.value
+
+    def close(self):
+        if self.h:
+            _check(lib().mlb_ctx_destroy(self.h), "mlb_ctx_destroy")
+            self.h = None
+
+
+def make_params(nx, ny, dx, nu, zeta_ref=0.0, edges=(WALL, WALL, WALL, WALL), extrap_order=1,
+                g=9.81, rho_w=1000.0, rho_air=1.293, c_w=0.0026, omega=0.0) -> Params:
+    p = Params()
+    p.nx, p.ny, p.dx, p.nu = int(nx), int(ny), float(dx), float(nu)
+    p.g, p.rho_w, p.rho_air, p.c_w, p.omega, p.zeta_ref = g, rho_w, rho_air, c_w, omega, zeta_ref
+    for k in range(4):
+        p.edge[k] = int(edges[k])
+    p.extrap_order = int(extrap_order)
+    return p
+
+
+def workspace_bytes(p: Params) -> int:
+    n = C.c_size_t()
+    _check(lib().mlb_grid_workspace_bytes(C.byref(p), C.byref(n)), "mlb_grid_workspace_bytes")
+    return n.value
+
+
+class Grid:
+    """A basin on the GPU.  workspace: optional torch uint8 CUDA tensor of at
+    least workspace_bytes(params) bytes (kept alive by this object)."""
+
+    def __init__(self, ctx: Context, params: Params, workspace=None):
+        self.ctx = ctx
+        self.params = params
+        self.nx, self.ny = params.nx, params.ny
+        self._ws = workspace
+        h = _VP()
+        ptr, nbytes = None, 0
+        if workspace is not None:
+            ptr = _tensor_ptr(workspace)
+            nbytes = workspace.numel() * workspace.element_size()
+        _check(lib().mlb_grid_create(ctx.h, C.byref(params), ptr, nbytes, C.byref(h)), "mlb_grid_create")
+        self.h = h
+
+    # -- setup
+    def set_bathymetry(self, zb):
+        a = _f64(zb, (self.ny, self.nx))
+        _check(lib().mlb_set_bathymetry(self.h, _dptr(a), self.nx), "mlb_set_bathymetry")
+
+    def set_wind(self, uwx, uwy):
+        _check(lib().mlb_set_wind(self.h, uwx, uwy), "mlb_set_wind")
+
+    def set_wind_stress(self, tx, ty):
+        _check(lib().mlb_set_wind_stress(self.h, tx, ty), "mlb_set_wind_stress")
+
+    def set_chezy(self, cz):
+        _check(lib().mlb_set_chezy(self.h, cz), "mlb_set_chezy")
+
+    def set_edge_depth(self, edge, h_mean, amp=0.0, period=0.0, phase=0.0):
+        _check(lib().mlb_set_edge_depth(self.h, edge, h_mean, amp, period, phase), "mlb_set_edge_depth")
+
+    def set_edge_discharge(self, edge, qx, qy=0.0):
+        _check(lib().mlb_set_edge_discharge(self.h, edge, qx, qy), "mlb_set_edge_discharge")
+
+    def set_state(self, h, hu=None, hv=None, step0: int = 0):
+        shape = (self.ny, self.nx)
+        a = _f64(h, shape)
+        b = None if hu is None else _f64(hu, shape)
+        c = None if hv is None else _f64(hv, shape)
+        _check(lib().mlb_set_state(self.h, _dptr(a), None if b is None else _dptr(b),
+                                   None if c is None else _dptr(c), self.nx, int(step0)),
+               "mlb_set_state")
+
+    def set_state_device(self, eta, qx, qy):
+        _check(lib().mlb_set_state_device(self.h, _tensor_ptr(eta), _tensor_ptr(qx), _tensor_ptr(qy)),
+               "mlb_set_state_device")
+
+    def get_state(self):
+        shape = (self.ny, self.nx)
+        h, hu, hv = np.empty(shape), np.empty(shape), np.empty(shape)
+        _check(lib().mlb_get_state(self.h, _dptr(h), _dptr(hu), _dptr(hv), self.nx), "mlb_get_state")
+        return h, hu, hv
+
+    def get_state_device(self, eta=None, qx=None, qy=None, H=None):
+        _check(lib().mlb_get_state_device(self.h, _tensor_ptr(eta), _tensor_ptr(qx), _tensor_ptr(qy),
+                                          _tensor_ptr(H)), "mlb_get_state_device")
+
+    # -- execution
+    def exec_opts(self) -> ExecOpts:
+        o = ExecOpts()
+        _check(lib().mlb_get_exec_opts(self.h, C.byref(o)), "mlb_get_exec_opts")
+        return o
+
+    def set_exec_opts(self, tile_rows=None, tblock=None, use_graph=None, graph_chunk=None):
+        o = self.exec_opts()
+        if tile_rows is not None: o.tile_rows = tile_rows
+        if tblock is not None: o.tblock = tblock
+        if use_graph is not None: o.use_graph = int(use_graph)
+        if graph_chunk is not None: o.graph_chunk = graph_chunk
+        _check(lib().mlb_set_exec_opts(self.h, C.byref(o)), "mlb_set_exec_opts")
+
+    def step(self, n: int = 1):
+        _check(lib().mlb_step(self.h, int(n)), "mlb_step")
+
+    def diag(self) -> dict:
+        d = Diag()
+        _check(lib().mlb_diag(self.h, C.byref(d)), "mlb_diag")
+        return d.as_dict()
+
+    def run_steady(self, tol: float, max_steps: int, check_every: int = 100):
+        """Returns (converged, diag dict); raises on non-finite values."""
+        d = Diag()
+        rc = lib().mlb_run_steady(self.h, tol, int(max_steps), int(check_every), C.byref(d))
+        if rc == -7:
+            return False, d.as_dict()
+        _check(rc, "mlb_run_steady")
+        return True, d.as_dict()
+
+    def close(self):
+        if self.h:
+            _check(lib().mlb_grid_destroy(self.h), "mlb_grid_destroy")
+            self.h = None
+
+
+class Batch:
+    """Many grids stepped by one persistent launch per step."""
+
+    def __init__(self, ctx: Context, grids: Sequence[Grid]):
+        self.ctx = ctx
+        self.grids = list(grids)
+        arr = (_VP * len(grids))(*[g.h for g in grids])
+        h = _VP()
+        _check(lib().mlb_batch_create(ctx.h, arr, len(grids), C.byref(h)), "mlb_batch_create")
+        self.h = h
+
+    def set_exec_opts(self, tile_rows=64, tblock=1, use_graph=True, graph_chunk=64):
+        o = ExecOpts(tile_rows, tblock, int(use_graph), graph_chunk)
+        _check(lib().mlb_batch_set_exec_opts(self.h, C.byref(o)), "mlb_batch_set_exec_opts")
+
+    def step(self, n: int = 1):
+        _check(lib().mlb_batch_step(self.h, int(n)), "mlb_batch_step")
+
+    def run_steady(self, tol: float, max_steps: int, check_every: int = 100):
+        ds = (Diag * len(self.grids))()
+        rc = lib().mlb_batch_run_steady(self.h, tol, int(max_steps), int(check_every), ds)
+        if rc == -7:
+            return False, [d.as_dict() for d in ds]
+        _check(rc, "mlb_batch_run_steady")
+        return True, [d.as_dict() for d in ds]
+
+    def close(self):
+        if self.h:
+            _check(lib().mlb_batch_destroy(self.h), "mlb_batch_destroy")
+            self.h = None
+
+
+def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
+    """A Grid set up from a workloads.Spec (bed, forcing, edges, initial state)."""
+    p = make_params(spec.nx, spec.ny, spec.dx, spec.nu, spec.zeta_ref, spec.edges, spec.extrap_order,
+                    omega=spec.omega)
+    g = Grid(ctx, p, workspace)
+    g.set_bathymetry(spec.zb)
+    if spec.wind_speed is not None:
+        g.set_wind(*spec.wind_speed)
+    if spec.wind_stress is not None:
+        g.set_wind_stress(*spec.wind_stress)
+    g.set_chezy(spec.chezy)
+    for k, (hm, amp, per, ph) in spec.depth_bc.items():
+        g.set_edge_depth(k, hm, amp, per, ph)
+    for k, (a, b) in spec.discharge_bc.items():
+        g.set_edge_discharge(k, a, b)
+    h, qx, qy = spec.initial()
+    g.set_state(h, qx, qy)
+    return g

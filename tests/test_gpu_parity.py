@@ -1,0 +1,267 @@
+"""GPU (FP32 HIP kernels, through the C ABI) against the FP64 oracle.
+
+Bar (after equal step counts): max |dh| <= 1e-5 max h and max |du| <= 1e-4 max |u|;
+still water bitwise; every execution variant (tile rows, graph chunks,
+batching) bitwise equal to every other.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import compare, oracle_from_spec
+from paper_1902_02999_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+H_TOL, U_TOL = 1e-5, 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1902_02999_amd import mlb
+    c = mlb.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, spec, nsteps, state=None, opts=None, step0=0):
+    from paper_1902_02999_amd import mlb
+    g = mlb.grid_from_spec(ctx, spec)
+    if state is not None:
+        g.set_state(*state, step0=step0)
+    if opts:
+        g.set_exec_opts(**opts)
+    g.step(nsteps)
+    out = g.get_state()
+    g.close()
+    return out
+
+
+def run_both(ctx, spec, nsteps, state=None, threads=0):
+    say("case", spec.name, spec.nx, spec.ny, "steps", nsteps)
+    got = run_gpu(ctx, spec, nsteps, state)
+    ref = oracle_from_spec(spec, *(state if state is not None else spec.initial()))
+    ref.threads = threads
+    ref.run(nsteps)
+    return got, (ref.h, ref.qx, ref.qy)
+
+
+def bumpy(nx, ny, seed, amp=0.3, depth=2.0):
+    rng = np.random.default_rng(seed)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    zb = np.zeros((ny, nx))
+    for _ in range(3):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        s = rng.uniform(nx / 12, nx / 4)
+        zb += amp * rng.uniform(0.3, 1) * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * s * s))
+    return zb
+
+
+def closed_spec(nx, ny, seed, wind=(9.0, -4.0), chezy=45.0):
+    return wl.Spec("closed_%dx%d" % (nx, ny), nx, ny, 1.0, 10.0 / 6.0, bumpy(nx, ny, seed), 2.0,
+                   wind_speed=wind, chezy=chezy)
+
+
+# ----------------------------------------------------------------------------- invariants
+def test_lake_at_rest_is_bitwise(ctx):
+    say("lake at rest 130x77")
+    spec = wl.Spec("rest", 130, 77, 1.0, 10.0 / 6.0, bumpy(130, 77, 1, amp=0.8), 2.0)
+    h, qx, qy = run_gpu(ctx, spec, 500)
+    assert np.all(qx == 0.0) and np.all(qy == 0.0)
+    assert np.array_equal(h, run_gpu(ctx, spec, 0)[0])
+
+
+# ----------------------------------------------------------------------------- parity vs oracle
+# The 5 x 4 basin runs few steps: its flow dies within ~100 steps, after which
+# u is the residual of wind stress against surface tilt (|u| ~ 1e-6 m/s) and
+# the FP32 quantum of eta (~1e-9 m) dominates any relative velocity measure.
+@pytest.mark.parametrize("nx,ny,seed,steps", [(64, 64, 0, 300), (125, 70, 1, 300), (61, 9, 2, 300),
+                                              (5, 4, 3, 30), (4, 133, 4, 300)])
+def test_closed_basin_parity(ctx, nx, ny, seed, steps):
+    spec = closed_spec(nx, ny, seed)
+    state = wl.seeded_state(spec, seed, eta_amp=0.05, q_amp=0.1)
+    got, ref = run_both(ctx, spec, steps, state)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+def test_periodic_parity(ctx):
+    spec = wl.Spec("periodic", 70, 40, 1.0, 10.0 / 6.0, bumpy(70, 40, 5), 2.0,
+                   edges=(wl.PERIODIC,) * 4, wind_speed=(5.0, 3.0), chezy=50.0, omega=1e-3)
+    state = wl.seeded_state(spec, 5, q_amp=0.2)
+    got, ref = run_both(ctx, spec, 400, state)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_open_channel_parity(ctx, order):
+    spec = wl.bump_channel(150, 67, sigma=12.0)
+    spec.extrap_order = order
+    got, ref = run_both(ctx, spec, 600)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+def test_open_edges_on_y_parity(ctx):
+    """Inflow on the south edge, outflow depth on the north edge (row pipeline
+    deferral / history), periodic across."""
+    nx, ny = 40, 90
+    zb = bumpy(nx, ny, 7, amp=0.2)
+    spec = wl.Spec("ychannel", nx, ny, 1.0, 25.0 / 6.0, zb, 2.0,
+                   edges=(wl.PERIODIC, wl.PERIODIC, wl.DISCHARGE, wl.DEPTH), extrap_order=2,
+                   depth_bc={wl.N: (2.0, 0.05, 30.0, 0.0)}, discharge_bc={wl.S: (0.1, 1.5)},
+                   qy0=np.full((ny, nx), 1.5))
+    got, ref = run_both(ctx, spec, 500)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+def test_tidal_strip_parity(ctx):
+    spec = wl.tidal_strip()
+    got, ref = run_both(ctx, spec, 10800)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+def test_wind_lake_parity(ctx):
+    spec = wl.wind_lake(64)
+    got, ref = run_both(ctx, spec, 2000)
+    dh, du = compare(*got, *ref)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
+# ----------------------------------------------------------------------------- execution variants
+def test_tile_rows_and_graphs_bitwise(ctx):
+    spec = wl.bump_channel(190, 150, sigma=15.0)
+    spec.extrap_order = 2
+    base = None
+    for opts in ({"tile_rows": 4, "use_graph": False}, {"tile_rows": 64, "use_graph": False},
+                 {"tile_rows": 37, "use_graph": True, "graph_chunk": 8},
+                 {"tile_rows": 256, "use_graph": True, "graph_chunk": 64}):
+        say("variant", opts)
+        out = run_gpu(ctx, spec, 131, opts=opts)
+        if base is None:
+            base = out
+        else:
+            for a, b in zip(out, base):
+                assert np.array_equal(a, b)
+
+
+def test_batch_equals_solo_bitwise(ctx):
+    from paper_1902_02999_amd import mlb
+    specs = [closed_spec(n, m, s) for (n, m, s) in ((64, 64, 0), (200, 97, 1), (33, 150, 2))]
+    specs.append(wl.bump_channel(130, 60, sigma=10.0))
+    solo = [run_gpu(ctx, s, 77) for s in specs]
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    b = mlb.Batch(ctx, grids)
+    say("batch of", len(grids))
+    b.step(77)
+    b.close()
+    for g, ref in zip(grids, solo):
+        got = g.get_state()
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r)
+        g.close()
+
+
+# ----------------------------------------------------------------------------- diagnostics
+def test_diag_matches_oracle_on_same_fields(ctx):
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(150, 90, 3)
+    state = wl.seeded_state(spec, 3, q_amp=0.1)
+    g = mlb.grid_from_spec(ctx, spec)
+    g.set_state(*state)
+    g.step(49)
+    h0, qx0, qy0 = g.get_state()
+    g.step(1)
+    d = g.diag()
+    h1, qx1, qy1 = g.get_state()
+    ref = oracle_from_spec(spec, h1, qx1, qy1)
+    r = ref.diag(qx0, qy0)
+    assert d["step"] == 50
+    assert d["mass"] == pytest.approx(r["mass"], rel=1e-13)
+    assert d["residual"] == pytest.approx(r["residual"], rel=1e-12)
+    # the device divides by the stored FP32 still-water depth plus eta
+    assert d["max_speed"] == pytest.approx(r["max_speed"], rel=1e-6)
+    assert d["nonfinite"] == 0
+    g.close()
+
+
+def test_mass_conserved_in_closed_basin(ctx):
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(256, 256, 4)
+    g = mlb.grid_from_spec(ctx, spec)
+    g.set_state(*wl.seeded_state(spec, 4, q_amp=0.1))
+    m0 = g.diag()["mass"]
+    g.step(2000)
+    m1 = g.diag()["mass"]
+    say("mass drift", (m1 - m0) / m0)
+    # FP32 storage: each step rounds eta to 2^-24 relative of |eta| per node
+    assert abs(m1 - m0) / m0 <= 1e-6
+    g.close()
+
+
+def test_run_steady_and_nonfinite(ctx):
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(48, 40, 6, wind=(8.0, 0.0))
+    g = mlb.grid_from_spec(ctx, spec)
+    ok, d = g.run_steady(1e-6, 200000, 100)
+    say("steady", ok, d["step"], d["residual"])
+    assert ok and d["residual"] <= 1e-6 and d["step"] % 100 == 0
+    h, qx, qy = g.get_state()
+    h[5, 7] = np.nan
+    g.set_state(h, qx, qy)
+    with pytest.raises(mlb.MlbError) as ei:
+        g.run_steady(1e-6, 1000, 10)
+    assert ei.value.name == "MLB_E_NONFINITE"
+    g.close()
+
+
+def test_unstable_parameters_rejected(ctx):
+    from paper_1902_02999_amd import mlb
+    p = mlb.make_params(20, 20, 1.0, 1.0, zeta_ref=10.0)  # e = 6 m/s
+    g = mlb.Grid(ctx, p)                                    # default bed: H = 1 m, stable
+    with pytest.raises(mlb.MlbError) as ei:
+        g.set_bathymetry(np.zeros((20, 20)))                # H = 10 m: g H = 98 > e^2 = 36
+    assert ei.value.name == "MLB_E_UNSTABLE"
+    g.close()
+
+
+# ----------------------------------------------------------------------------- full size, sampled
+def test_full_size_bump_channel_sampled(ctx):
+    """4096 x 4096 channel in the benchmark's launch configuration: one more
+    GPU step from a GPU state, checked node by node by the oracle on samples
+    (interior, all four edges, corners, tile seams)."""
+    from paper_1902_02999_amd import mlb
+    spec = wl.bump_channel(4096)
+    say("full size", spec.name)
+    g = mlb.grid_from_spec(ctx, spec)
+    g.step(20)
+    h0, qx0, qy0 = g.get_state()
+    g.step(1)
+    h1, qx1, qy1 = g.get_state()
+    ref = oracle_from_spec(spec, h0, qx0, qy0, step0=20)
+    n = spec.nx
+    rng = np.random.default_rng(0)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (0, 17), (n - 1, 1234), (555, 0),
+           (999, n - 1), (61, 63), (62, 64), (63, 127), (2047, 2048), (n - 2, n - 2), (1, 1)]
+    pts += [tuple(rng.integers(0, n, 2)) for _ in range(150)]
+    hmax, qmax = 2.2, 5.0
+    for i, j in pts:
+        o = ref.node_from(h0, qx0, qy0, i, j)
+        assert abs(h1[j, i] - o[0]) <= 1e-6 * hmax, (i, j)
+        assert abs(qx1[j, i] - o[1]) <= 1e-6 * qmax and abs(qy1[j, i] - o[2]) <= 1e-6 * qmax, (i, j)
+    g.close()
