@@ -11,7 +11,6 @@ roofline block of the step kernel and the FP64 oracle timed on the host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -27,8 +26,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_1902_02999_amd.profiling import kernel_sha
+    return kernel_sha()
 
 
 def measured_traffic(nodes: int):
@@ -71,10 +70,12 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
-    ap.add_argument("--tile-rows", type=int, default=64)
+    ap.add_argument("--tile-rows", type=int, default=33)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run the plain copy kernel on this many MiB and print GB/s")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the step runs on a single MI355X); "
@@ -84,8 +85,14 @@ def main():
     import torch
     from paper_1902_02999_amd import mlb, workloads as wl
 
-    spec = wl.bump_channel(args.n)
     ctx = mlb.Context(0)
+    if args.copy_probe_mib:
+        gbps = ctx.copy_probe(args.copy_probe_mib << 20, reps=5)
+        print(json.dumps({"copy_probe_bytes": args.copy_probe_mib << 20, "GBps": round(gbps, 1)}), flush=True)
+        ctx.close()
+        return
+    copy_gbps = ctx.copy_probe(1 << 30, reps=10)
+    spec = wl.bump_channel(args.n)
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100)
 
@@ -123,7 +130,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nodes": nodes, "dx_m": spec.dx, "dt_s": spec.dx / (6 * spec.nu / spec.dx),
                    "tile_rows": args.tile_rows, "graph": not args.no_graph,
-                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1)},
+                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1),
+                   "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
     }

@@ -103,8 +103,9 @@ mlb_status mlb_ctx_destroy(mlb_ctx* ctx);
 /* Blocks until the context's stream is idle. */
 mlb_status mlb_ctx_sync(mlb_ctx* ctx);
 
-/* Device bytes a grid with these parameters needs (fields, still-water depth,
- * tile list, reduction partials, counters), for a caller-owned workspace. */
+/* Device bytes of a grid's fields (two copies of eta, qx, qy; the still-water
+ * depth; the step counter) for a caller-owned workspace.  The small tile list
+ * and reduction buffers are always allocated by the library. */
 mlb_status mlb_grid_workspace_bytes(const mlb_params* p, size_t* bytes);
 /* Creates a grid.  dev_workspace == NULL: the library allocates device memory.
  * Otherwise it must be a device pointer of at least mlb_grid_workspace_bytes,
@@ -190,6 +191,12 @@ mlb_status mlb_batch_destroy(mlb_batch* b);
 /* Kernel time of the last mlb_step / mlb_batch_step call measured with HIP
  * events on the context stream around the step launches [ms]. */
 mlb_status mlb_last_step_ms(mlb_ctx* ctx, double* ms);
+
+/* Practical HBM bandwidth: copies `bytes` (multiple of 16, >= 4096) between
+ * two device buffers the library allocates for the call, `reps` times, with a
+ * plain 16-byte-vector copy kernel; returns read + write bytes per second
+ * [GB/s] from HIP events.  Used as the reference for measured HBM traffic. */
+mlb_status mlb_copy_probe(mlb_ctx* ctx, size_t bytes, int32_t reps, double* gbps);
 
 #ifdef __cplusplus
 }

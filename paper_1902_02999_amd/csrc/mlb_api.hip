@@ -104,7 +104,7 @@ struct mlb_grid {
     double bc_hmean[4] = {0, 0, 0, 0}, bc_amp[4] = {0, 0, 0, 0}, bc_om[4] = {0, 0, 0, 0},
            bc_phase[4] = {0, 0, 0, 0}, bc_qx[4] = {0, 0, 0, 0}, bc_qy[4] = {0, 0, 0, 0};
     mlb_batch* batch = nullptr;
-    mlb_exec_opts opts{64, 1, 1, 64};
+    mlb_exec_opts opts{33, 1, 1, 64};
     Plan plan;
     bool dirty = true;         // descriptor must be re-uploaded
     bool stale_plan = true;    // tiles / allocation must be rebuilt
@@ -113,7 +113,7 @@ struct mlb_grid {
 struct mlb_batch {
     mlb_ctx* ctx = nullptr;
     std::vector<mlb_grid*> grids;
-    mlb_exec_opts opts{64, 1, 1, 64};
+    mlb_exec_opts opts{33, 1, 1, 64};
     Plan plan;
     bool stale_plan = true;
 };
@@ -730,6 +730,30 @@ mlb_status mlb_last_step_ms(mlb_ctx* c, double* ms)
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, c->ev0, c->ev1));
     *ms = f;
+    return MLB_OK;
+}
+
+mlb_status mlb_copy_probe(mlb_ctx* c, size_t bytes, int32_t reps, double* gbps)
+{
+    if (!c || !gbps || reps < 1 || bytes < 4096 || (bytes & 15)) return fail(MLB_E_INVAL, "bad copy probe arguments");
+    CHK(check_stream(c));
+    void *a = nullptr, *b = nullptr;
+    HIPCHK(hipMalloc(&a, bytes));
+    hipError_t e = hipMalloc(&b, bytes);
+    if (e != hipSuccess) { (void)hipFree(a); return fail(MLB_E_NOMEM, hipGetErrorString(e)); }
+    const int nblocks = c->ncu * 8;
+    e = hipMemsetAsync(a, 0, bytes, c->stream);
+    if (e == hipSuccess) e = launch_copy_probe(a, b, bytes, nblocks, c->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_copy_probe(a, b, bytes, nblocks, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(MLB_E_DEVICE, hipGetErrorString(e));
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return MLB_OK;
 }
 

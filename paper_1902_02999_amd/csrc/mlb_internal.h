@@ -57,6 +57,7 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int nblocks, hipStream_t s);
 hipError_t launch_finalize(const BasinDev* d_basins, int nbasins, const double* d_partials,
                            double* d_out, hipStream_t s);
 

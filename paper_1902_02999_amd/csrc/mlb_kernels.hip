@@ -30,15 +30,16 @@
 namespace mlb {
 
 // ------------------------------------------------------------------ lanes
+// DPP wave shifts; lanes without a source (lane 0 / lane 63) read 0
 __device__ __forceinline__ float from_left(float v)  // lane i receives lane i-1
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        0, __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_right(float v)  // lane i receives lane i+1
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        0, __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -471,7 +472,23 @@ __global__ __launch_bounds__(kWave) void finalize_kernel(const BasinDev* __restr
     }
 }
 
+// Plain device-to-device copy (16-byte vectors, grid-stride): the reference
+// for the practical HBM bandwidth and for scaling the HBM byte counters.
+__global__ __launch_bounds__(kBlock) void copy_probe_kernel(const float4* __restrict__ a,
+                                                           float4* __restrict__ b, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = a[i];
+}
+
 // ------------------------------------------------------------------ launchers
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_probe_kernel, dim3(nblocks), dim3(kBlock), 0, s, (const float4*)src,
+                       (float4*)dst, bytes / sizeof(float4));
+    return hipGetLastError();
+}
+
 int step_occupancy(int diag)
 {
     int n = 0;

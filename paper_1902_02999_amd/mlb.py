@@ -86,6 +86,7 @@ SIGNATURES = {
     "mlb_batch_set_exec_opts": (C.c_int, [_VP, C.POINTER(ExecOpts)]),
     "mlb_batch_destroy": (C.c_int, [_VP]),
     "mlb_last_step_ms": (C.c_int, [_VP, _DP]),
+    "mlb_copy_probe": (C.c_int, [_VP, C.c_size_t, C.c_int32, _DP]),
 }
 
 _lib = None
@@ -148,6 +149,12 @@ class Context:
     def last_step_ms(self) -> float:
         v = C.c_double()
         _check(lib().mlb_last_step_ms(self.h, C.byref(v)), "mlb_last_step_ms")
+        return v.value
+
+    def copy_probe(self, nbytes: int, reps: int = 10) -> float:
+        """Read + write GB/s of a plain device copy of nbytes."""
+        v = C.c_double()
+        _check(lib().mlb_copy_probe(self.h, int(nbytes), int(reps), C.byref(v)), "mlb_copy_probe")
         return v.value
 
     def close(self):
