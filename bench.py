@@ -70,12 +70,18 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
-    ap.add_argument("--tile-rows", type=int, default=33)
+    ap.add_argument("--tile-rows", type=int, default=15)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run the plain copy kernel on this many MiB and print GB/s")
+    ap.add_argument("--blocks-per-cu", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (by default it picks tile rows and the CU cap before timing)")
+    ap.add_argument("--workload", default="bump", choices=["bump", "ensemble", "lake_steady"],
+                    help="bump: 4096^2 channel (default line); ensemble: 512 basins 64^2..512^2 in "
+                         "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the step runs on a single MI355X); "
@@ -92,9 +98,15 @@ def main():
         ctx.close()
         return
     copy_gbps = ctx.copy_probe(1 << 30, reps=10)
+    if args.workload == "ensemble":
+        return bench_ensemble(args, ctx, copy_gbps)
+    if args.workload == "lake_steady":
+        return bench_lake_steady(args, ctx)
     spec = wl.bump_channel(args.n)
     grid = mlb.grid_from_spec(ctx, spec)
-    grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100)
+    grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
+                       blocks_per_cu=args.blocks_per_cu)
+    tuned = None if args.no_autotune else grid.autotune(steps=40)
 
     grid.step(args.warmup)
     ctx.sync()
@@ -129,7 +141,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": spec.name, "nodes": nodes, "dx_m": spec.dx, "dt_s": spec.dx / (6 * spec.nu / spec.dx),
-                   "tile_rows": args.tile_rows, "graph": not args.no_graph,
+                   "tile_rows": grid.exec_opts().tile_rows, "blocks_per_cu": grid.exec_opts().blocks_per_cu,
+                   "autotuned": tuned is not None, "graph": not args.no_graph,
                    "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1),
                    "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -142,6 +155,60 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args, ctx, copy_gbps):
+    """512 closed basins (sizes 64^2..512^2, seed 1902) in one launch per step."""
+    import torch
+    from paper_1902_02999_amd import mlb, workloads as wl
+    specs = wl.ensemble(512, 1902)
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    nodes = sum(s.nodes for s in specs)
+    b = mlb.Batch(ctx, grids)
+    b.set_exec_opts(tile_rows=args.tile_rows, graph_chunk=100, blocks_per_cu=args.blocks_per_cu)
+    tuned = None if args.no_autotune else b.autotune(steps=10)
+    b.step(args.warmup)
+    ctx.sync()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()
+    ok, diags = b.run_steady(0.0, 1, 1)   # one checked step: finiteness of every basin
+    bad = sum(d["nonfinite"] for d in diags)
+    b.close()
+    for g in grids:
+        g.close()
+    ctx.close()
+    mlups = nodes * args.steps / wall / 1e6
+    achieved = BYTES_PER_LUP * nodes / (ev_ms / 1e3 / args.steps) / 1e9
+    print(json.dumps({
+        "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ensemble_512_basins_64-512_seed1902", "basins": len(specs), "nodes": nodes,
+                   "tuned": tuned, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None}), flush=True)
+
+
+def bench_lake_steady(args, ctx):
+    """256^2 wind-driven dish lake from rest to a per-step residual of 1e-6."""
+    from paper_1902_02999_amd import mlb, workloads as wl
+    spec = wl.wind_lake(256)
+    g = mlb.grid_from_spec(ctx, spec)
+    g.set_exec_opts(graph_chunk=98)
+    t0 = time.perf_counter()
+    ok, d = g.run_steady(1e-6, 3_000_000, 100)
+    wall = time.perf_counter() - t0
+    g.close()
+    ctx.close()
+    print(json.dumps({"metric": "wall_s_to_residual_1e-6", "value": round(wall, 4), "unit": "s",
+                      "higher_is_better": False, "converged": ok, "steps": d["step"],
+                      "residual": d["residual"], "t_model_s": d["t"],
+                      "config": {"workload": spec.name, "nodes": spec.nodes}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -164,19 +164,31 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
                           mlb_diag_t* out);
 
 /* Execution options of the step (results are bitwise identical for any
- * choice): rows per tile, temporal block depth (sub-steps per pass), and
- * whether step loops are captured and replayed as a hipGraph. */
+ * choice): rows per tile, temporal block depth (sub-steps per pass), whether
+ * step loops are captured and replayed as a hipGraph, and a cap on resident
+ * step workgroups per compute unit (fewer concurrent row streams). */
 typedef struct {
-    int32_t tile_rows;     /* output rows per wave tile, >= 4                             */
-    int32_t tblock;        /* sub-steps per kernel pass: 1 or 2                           */
+    int32_t tile_rows;     /* output rows per wave tile, 4..4096                          */
+    int32_t tblock;        /* sub-steps per kernel pass: 1                                */
     int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
-    int32_t graph_chunk;   /* steps per captured graph                                    */
+    int32_t graph_chunk;   /* steps per captured graph, 2..100000                         */
+    int32_t blocks_per_cu; /* 0: no cap; 1..8: at most this many step workgroups per CU   */
 } mlb_exec_opts;
 mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
 mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
 
-/* Batches: many grids advanced together by one persistent kernel launch per
- * step driven by a tile work queue (largest basins first).  Grids keep their
+/* Autotuner: times the step for every (tile_rows, blocks_per_cu) pair of a
+ * fixed candidate set (tile rows 6..45 x caps 0, 2..5) with HIP events (median of 3 runs of `steps` steps),
+ * applies the fastest and returns it in *best (may be NULL).  The grid's
+ * state and step counter are restored afterwards (results are bitwise
+ * independent of these options).  cache_path (may be NULL): a text file of
+ * "key tile_rows blocks_per_cu us" lines; a matching key is applied without
+ * timing, a new result is appended.  The key holds the device name and the
+ * grid shape. */
+mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_exec_opts* best);
+
+/* Batches: many grids advanced together by one kernel launch per step over a
+ * single tile list holding the largest basins first.  Grids keep their
  * own parameters and boundary data; while in a batch they cannot be stepped
  * alone.  Destroying the batch hands the grids back with their state. */
 mlb_status mlb_batch_create(mlb_ctx* ctx, mlb_grid* const* grids, int32_t n, mlb_batch** out);
@@ -186,6 +198,8 @@ mlb_status mlb_batch_step(mlb_batch* b, int64_t nsteps);
 mlb_status mlb_batch_run_steady(mlb_batch* b, double tol, int64_t max_steps,
                                 int32_t check_every, mlb_diag_t* per_basin);
 mlb_status mlb_batch_set_exec_opts(mlb_batch* b, const mlb_exec_opts* o);
+/* As mlb_autotune, for a batch (state of every member restored). */
+mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_path, mlb_exec_opts* best);
 mlb_status mlb_batch_destroy(mlb_batch* b);
 
 /* Kernel time of the last mlb_step / mlb_batch_step call measured with HIP

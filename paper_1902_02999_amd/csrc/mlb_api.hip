@@ -3,6 +3,7 @@
 // FP64 diagnostics.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -55,6 +56,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     int gparity = -1;
     int gsteps = 0;
+    unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool built = false;
 
     void release()
@@ -78,6 +80,8 @@ struct mlb_ctx {
     bool own_stream = false;
     int live = 0;
     int ncu = 0;
+    int lds_per_cu = 0;        // bytes
+    std::string arch;          // gcnArchName, for autotuner cache keys
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
 };
@@ -104,7 +108,7 @@ struct mlb_grid {
     double bc_hmean[4] = {0, 0, 0, 0}, bc_amp[4] = {0, 0, 0, 0}, bc_om[4] = {0, 0, 0, 0},
            bc_phase[4] = {0, 0, 0, 0}, bc_qx[4] = {0, 0, 0, 0}, bc_qy[4] = {0, 0, 0, 0};
     mlb_batch* batch = nullptr;
-    mlb_exec_opts opts{33, 1, 1, 64};
+    mlb_exec_opts opts{15, 1, 1, 64, 3};
     Plan plan;
     bool dirty = true;         // descriptor must be re-uploaded
     bool stale_plan = true;    // tiles / allocation must be rebuilt
@@ -113,7 +117,7 @@ struct mlb_grid {
 struct mlb_batch {
     mlb_ctx* ctx = nullptr;
     std::vector<mlb_grid*> grids;
-    mlb_exec_opts opts{33, 1, 1, 64};
+    mlb_exec_opts opts{15, 1, 1, 64, 3};
     Plan plan;
     bool stale_plan = true;
 };
@@ -240,25 +244,36 @@ mlb_status grid_plan(mlb_grid* g)
 
 // Launch n steps of a plan; the last one reduces into partials when diag.
 // Advances the plan parity per launch; graph chunks replay when aligned.
+// Dynamic LDS per step workgroup that leaves room for at most
+// o.blocks_per_cu resident workgroups on a CU (0: no cap).
+unsigned dyn_lds_for(const mlb_ctx* c, const mlb_exec_opts& o)
+{
+    if (o.blocks_per_cu <= 0 || c->lds_per_cu <= 0) return 0;
+    // rounded down to 2 KiB so that allocation granularity never lets fewer fit
+    const unsigned per = (unsigned)(c->lds_per_cu / o.blocks_per_cu) / 2048u * 2048u;
+    return (unsigned)(o.blocks_per_cu + 1) * per > (unsigned)c->lds_per_cu ? per : 0u;
+}
+
 mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n, bool diag_last)
 {
     const int ntiles = (int)P.ht.size();
+    const unsigned dyn = dyn_lds_for(c, o);
     auto eager = [&](bool diag) -> mlb_status {
-        HIPCHK(launch_step(P.db, P.dt, ntiles, P.parity, P.dpart, diag ? 1 : 0, 1, c->stream));
+        HIPCHK(launch_step(P.db, P.dt, ntiles, P.parity, P.dpart, diag ? 1 : 0, 1, dyn, c->stream));
         P.parity ^= 1;
         return MLB_OK;
     };
     int64_t plain = diag_last ? n - 1 : n;
     const int chunk = std::max(2, o.graph_chunk & ~1);
     if (o.use_graph && plain >= chunk) {
-        if (!P.gexec || P.gsteps != chunk) {
+        if (!P.gexec || P.gsteps != chunk || P.gdyn != dyn) {
             if (P.gexec) { (void)hipGraphExecDestroy(P.gexec); P.gexec = nullptr; }
             if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             int par = P.parity;
             hipError_t le = hipSuccess;
             for (int i = 0; i < chunk && le == hipSuccess; ++i) {
-                le = launch_step(P.db, P.dt, ntiles, par, P.dpart, 0, 1, c->stream);
+                le = launch_step(P.db, P.dt, ntiles, par, P.dpart, 0, 1, dyn, c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -269,6 +284,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
             P.gsteps = chunk;
             P.gparity = P.parity;
+            P.gdyn = dyn;
         }
         if (P.parity != P.gparity) {
             CHK(eager(false));
@@ -305,9 +321,14 @@ mlb_status validate_params(const mlb_params* p)
     return MLB_OK;
 }
 
+// Row pitch: nx rounded up to 64 floats (256 B), plus MLB_LD_PAD floats
+// (build-time knob; breaks power-of-two pitches).
+#ifndef MLB_LD_PAD
+#define MLB_LD_PAD 0
+#endif
 size_t field_bytes(const mlb_params* p, int* ld_out)
 {
-    const int ld = (int)align_up((size_t)p->nx, 64);
+    const int ld = (int)align_up((size_t)p->nx, 64) + MLB_LD_PAD;
     if (ld_out) *ld_out = ld;
     return 256 + 7 * align_up((size_t)ld * p->ny * sizeof(float), 256);
 }
@@ -414,6 +435,11 @@ mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out)
     }
     (void)hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device);
     if (c->ncu <= 0) c->ncu = 256;
+    (void)hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->arch = prop.gcnArchName;
+    if (c->arch.empty()) c->arch = "gpu";
+    for (auto& ch : c->arch) if (ch == ' ' || ch == ':') ch = '_';
     (void)hipEventCreate(&c->ev0);
     (void)hipEventCreate(&c->ev1);
     *out = c;
@@ -646,6 +672,7 @@ static mlb_status check_opts(const mlb_exec_opts* o)
     if (!o) return fail(MLB_E_INVAL, "opts is NULL");
     if (o->tile_rows < 4 || o->tile_rows > 4096) return fail(MLB_E_INVAL, "tile_rows out of range");
     if (o->tblock != 1) return fail(MLB_E_INVAL, "tblock must be 1");
+    if (o->blocks_per_cu < 0 || o->blocks_per_cu > 8) return fail(MLB_E_INVAL, "blocks_per_cu must be 0..8");
     if (o->use_graph && (o->graph_chunk < 2 || o->graph_chunk > 100000))
         return fail(MLB_E_INVAL, "graph_chunk out of range");
     return MLB_OK;
@@ -885,6 +912,196 @@ mlb_status mlb_batch_destroy(mlb_batch* b)
     }
     b->ctx->live--;
     delete b;
+    return MLB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+const int kTuneRows[] = {6, 9, 12, 15, 21, 27, 33, 45};
+const int kTuneCaps[] = {0, 2, 3, 4, 5};
+
+// Device copies of the current fields of some grids, to restore after tuning.
+struct Saved {
+    std::vector<float*> buf;
+    std::vector<int64_t> step;
+    void release() { for (float* p : buf) (void)hipFree(p); buf.clear(); }
+};
+
+mlb_status save_states(mlb_ctx* c, const std::vector<mlb_grid*>& gs, Saved& sv)
+{
+    for (mlb_grid* g : gs) {
+        float* p = nullptr;
+        HIPCHK(hipMalloc(&p, 3 * g->plane * sizeof(float)));
+        sv.buf.push_back(p);
+        sv.step.push_back(g->step);
+        HIPCHK(hipMemcpyAsync(p, g->eta[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(p + g->plane, g->qx[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(p + 2 * g->plane, g->qy[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    }
+    return MLB_OK;
+}
+
+mlb_status restore_states(mlb_ctx* c, const std::vector<mlb_grid*>& gs, Saved& sv)
+{
+    for (size_t i = 0; i < gs.size(); ++i) {
+        mlb_grid* g = gs[i];
+        const float* p = sv.buf[i];
+        for (int k = 0; k < 2; ++k) {  // both buffers: the next residual is 0
+            HIPCHK(hipMemcpyAsync(g->eta[k], p, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(g->qx[k], p + g->plane, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(g->qy[k], p + 2 * g->plane, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+        }
+        CHK(set_step(g, sv.step[i]));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLB_OK;
+}
+
+bool cache_lookup(const char* path, const std::string& key, mlb_exec_opts* o)
+{
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int tr = 0, bc = 0;
+    double us = 0;
+    bool hit = false;
+    while (std::fscanf(f, "%255s %d %d %lf", k, &tr, &bc, &us) == 4)
+        if (key == k) { o->tile_rows = tr; o->blocks_per_cu = bc; hit = true; }
+    std::fclose(f);
+    return hit;
+}
+
+void cache_store(const char* path, const std::string& key, const mlb_exec_opts& o, double us)
+{
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.3f\n", key.c_str(), o.tile_rows, o.blocks_per_cu, us);
+    std::fclose(f);
+}
+
+// Times `steps` steps of each candidate; `prepare` rebuilds the plan for the
+// options and returns it.  Leaves *opts at the fastest candidate.
+template <class Prepare>
+mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<mlb_grid*>& gs,
+                Prepare prepare, double* best_us)
+{
+    const mlb_exec_opts base = *opts;
+    mlb_exec_opts best = base;
+    double best_t = 1e300;
+    const int n = std::max(2, steps & ~1);
+    for (int tr : kTuneRows)
+        for (int cap : kTuneCaps) {
+            mlb_exec_opts o = base;
+            o.tile_rows = tr;
+            o.blocks_per_cu = cap;
+            o.use_graph = 1;
+            o.graph_chunk = n;
+            *opts = o;
+            Plan* P = nullptr;
+            CHK(prepare(o, &P));
+            CHK(enqueue_steps(c, *P, o, n, false));  // capture + warm-up
+            for (auto* g : gs) advance_grid(g, n);
+            float ms[3];
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHK(hipEventRecord(c->ev0, c->stream));
+                CHK(enqueue_steps(c, *P, o, n, false));
+                HIPCHK(hipEventRecord(c->ev1, c->stream));
+                HIPCHK(hipEventSynchronize(c->ev1));
+                HIPCHK(hipEventElapsedTime(&ms[rep], c->ev0, c->ev1));
+                for (auto* g : gs) advance_grid(g, n);
+            }
+            std::sort(ms, ms + 3);
+            const double us = 1e3 * ms[1] / n;
+            if (us < best_t) { best_t = us; best = o; }
+        }
+    best.use_graph = base.use_graph;
+    best.graph_chunk = base.graph_chunk;
+    *opts = best;
+    *best_us = best_t;
+    return MLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_exec_opts* best)
+{
+    GRID_OK(g);
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    if (steps < 2) return fail(MLB_E_INVAL, "steps must be >= 2");
+    mlb_ctx* c = g->ctx;
+    const std::string key = c->arch + "_g" + std::to_string(g->p.nx) + "x" + std::to_string(g->p.ny);
+    mlb_exec_opts o = g->opts;
+    if (cache_lookup(cache_path, key, &o)) {
+        CHK(mlb_set_exec_opts(g, &o));
+        if (best) *best = g->opts;
+        return MLB_OK;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<mlb_grid*> gs{g};
+    Saved sv;
+    mlb_status st = save_states(c, gs, sv);
+    double us = 0;
+    if (st == MLB_OK)
+        st = tune(c, &o, steps, gs, [&](const mlb_exec_opts& oo, Plan** P) -> mlb_status {
+            if (oo.tile_rows != g->opts.tile_rows) g->stale_plan = true;
+            g->opts = oo;
+            CHK(grid_plan(g));
+            *P = &g->plan;
+            return MLB_OK;
+        }, &us);
+    mlb_status rs = st == MLB_OK || !sv.buf.empty() ? restore_states(c, gs, sv) : MLB_OK;
+    sv.release();
+    if (st != MLB_OK) return st;
+    if (rs != MLB_OK) return rs;
+    g->stale_plan = true;
+    g->opts = o;
+    cache_store(cache_path, key, o, us);
+    if (best) *best = o;
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_path, mlb_exec_opts* best)
+{
+    if (!b) return fail(MLB_E_INVAL, "batch is NULL");
+    if (steps < 2) return fail(MLB_E_INVAL, "steps must be >= 2");
+    mlb_ctx* c = b->ctx;
+    CHK(check_stream(c));
+    int64_t nodes = 0;
+    for (auto* g : b->grids) nodes += (int64_t)g->p.nx * g->p.ny;
+    const std::string key = c->arch + "_b" + std::to_string(b->grids.size()) + "n" + std::to_string(nodes);
+    mlb_exec_opts o = b->opts;
+    if (cache_lookup(cache_path, key, &o)) {
+        CHK(mlb_batch_set_exec_opts(b, &o));
+        if (best) *best = b->opts;
+        return MLB_OK;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Saved sv;
+    mlb_status st = save_states(c, b->grids, sv);
+    double us = 0;
+    if (st == MLB_OK)
+        st = tune(c, &o, steps, b->grids, [&](const mlb_exec_opts& oo, Plan** P) -> mlb_status {
+            if (oo.tile_rows != b->opts.tile_rows) b->stale_plan = true;
+            b->opts = oo;
+            CHK(batch_plan(b));
+            *P = &b->plan;
+            return MLB_OK;
+        }, &us);
+    mlb_status rs = !sv.buf.empty() ? restore_states(c, b->grids, sv) : MLB_OK;
+    sv.release();
+    if (st != MLB_OK) return st;
+    if (rs != MLB_OK) return rs;
+    b->stale_plan = true;  // re-derive buffer parities from the restored grids
+    b->opts = o;
+    cache_store(cache_path, key, o, us);
+    if (best) *best = o;
     return MLB_OK;
 }
 

@@ -53,7 +53,7 @@ struct TileDev {
 
 // Host-side launchers (mlb_kernels.hip).
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, hipStream_t s);
+                       double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s);
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);

@@ -27,6 +27,12 @@
 // tile; the tile list holds the largest basins first.
 #include "mlb_internal.h"
 
+// Build-time knob (results are bitwise independent of it):
+//   MLB_NT_STORE  non-temporal stores of the new fields (written once per step)
+#ifndef MLB_NT_STORE
+#define MLB_NT_STORE 1
+#endif
+
 namespace mlb {
 
 // ------------------------------------------------------------------ lanes
@@ -83,14 +89,11 @@ __device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, f
     d.H = H; d.q0x = qx; d.q0y = qy;
 }
 
-// Eqs. Mac.lb.6 / Mac.lb.7 in increment form from the gathered neighbours.
-__device__ __forceinline__ void update(const BasinDev& B, const Derived& x, const float* ey,
-                                       const float* hy, const float* oy,
-                                       float& eta_n, float& qx_n, float& qy_n)
+// Eqs. Mac.lb.6 / Mac.lb.7 in increment form from the gathered neighbour
+// equilibria oy[a] = Out_a(y_a) and link products P[a] = (h_x + h_y)(eta_y - eta_x).
+__device__ __forceinline__ void update(const BasinDev& B, const Derived& x, const float* P,
+                                       const float* oy, float& eta_n, float& qx_n, float& qy_n)
 {
-    float P[9];
-#pragma unroll
-    for (int a = 1; a <= 8; ++a) P[a] = (x.h + hy[a]) * (ey[a] - x.eta);
     const float so = ((oy[1] + oy[2]) + (oy[3] + oy[4])) + ((oy[5] + oy[6]) + (oy[7] + oy[8]));
     const float pa = (P[1] + P[3]) + (P[5] + P[7]);
     const float pd = (P[2] + P[4]) + (P[6] + P[8]);
@@ -103,6 +106,14 @@ __device__ __forceinline__ void update(const BasinDev& B, const Derived& x, cons
     const float pym = __builtin_fmaf(B.cqa, P[3] - P[7], B.cqd * (p26 + (P[4] - P[8])));
     qx_n = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
     qy_n = x.fpy + __builtin_fmaf(B.e, myo, pym);
+}
+
+// Link product of node x with neighbour y: (h_x + h_y)(eta_y - eta_x).  The
+// same link seen from y is exactly its negative, so each node computes its
+// E, N, NE and NW links and takes the other four from its neighbours.
+__device__ __forceinline__ float link(float hx, float ex, float hy, float ey)
+{
+    return (hx + hy) * (ey - ex);
 }
 
 // What one row of the window keeps: own values and the neighbours' values
@@ -153,31 +164,34 @@ __device__ __forceinline__ double depth_bc(const BasinDev& B, int k, double tn)
     do {                                                                                          \
         derive(B, WN.eta, WN.qx, WN.qy, WN.H, DN);                                                \
         exchange(DN, N);                                                                          \
-        WN = load_raw(E0, QX0, QY0, HH, wrap_or_clamp((r) + 4, ny, per_y) * ld + xl);             \
-        float ey[9], hy[9], oy[9];                                                                \
-        ey[1] = C.el;  hy[1] = C.hl;  oy[1] = C.o1l;   /* W  */                                   \
-        ey[2] = S.el;  hy[2] = S.hl;  oy[2] = S.o2l;   /* SW */                                   \
-        ey[3] = S.eta; hy[3] = S.h;   oy[3] = S.o3;    /* S  */                                   \
-        ey[4] = S.er;  hy[4] = S.hr;  oy[4] = S.o4r;   /* SE */                                   \
-        ey[5] = C.er;  hy[5] = C.hr;  oy[5] = C.o5r;   /* E  */                                   \
-        ey[6] = N.er;  hy[6] = N.hr;  oy[6] = N.o6r;   /* NE */                                   \
-        ey[7] = N.eta; hy[7] = N.h;   oy[7] = N.o7;    /* N  */                                   \
-        ey[8] = N.el;  hy[8] = N.hl;  oy[8] = N.o8l;   /* NW */                                   \
+        /* prefetch row r+4; rows past r1 are never needed (clamped: cache hits) */             \
+        WN = load_raw(E0, QX0, QY0, HH,                                                           \
+                      (uint32_t)(wrap_or_clamp(min((r) + 4, r1), ny, per_y) * ld) + (uint32_t)xl); \
+        /* own links of row r (E, N, NE, NW) and the four received ones */                   \
+        const float lE = link(DC.h, DC.eta, C.hr, C.er), lN = link(DC.h, DC.eta, N.h, N.eta);     \
+        const float lNE = link(DC.h, DC.eta, N.hr, N.er), lNW = link(DC.h, DC.eta, N.hl, N.el);   \
+        const float lWx = from_left(lE);                                                          \
+        float P[9], oy[9];                                                                        \
+        P[1] = -lWx; P[2] = -cNEl; P[3] = -cN; P[4] = -cNWr;                                      \
+        P[5] = lE;   P[6] = lNE;   P[7] = lN;  P[8] = lNW;                                        \
+        cN = lN; cNEl = from_left(lNE); cNWr = from_right(lNW); /* for row r+1 */                 \
+        oy[1] = C.o1l; oy[2] = S.o2l; oy[3] = S.o3;  oy[4] = S.o4r;  /* W SW S SE */              \
+        oy[5] = C.o5r; oy[6] = N.o6r; oy[7] = N.o7;  oy[8] = N.o8l;  /* E NE N NW */              \
         if (EDGE) {                                                                               \
-            /* bounced link a: eta_y = eta_x (no bed term), A_a(y) = A_abar(x) */                 \
+            /* bounced link a: no bed term, A_a(y) = A_abar(x) */                                 \
             const bool sout = !per_y && (r) == 0, nout = !per_y && (r) == ny - 1;                 \
             const bool b2 = wout || sout, b4 = eout || sout, b6 = eout || nout, b8 = wout || nout; \
-            ey[1] = wout ? DC.eta : ey[1]; hy[1] = wout ? DC.h : hy[1]; oy[1] = wout ? DC.o[5] : oy[1]; \
-            ey[2] = b2 ? DC.eta : ey[2];   hy[2] = b2 ? DC.h : hy[2];   oy[2] = b2 ? DC.o[6] : oy[2];   \
-            ey[3] = sout ? DC.eta : ey[3]; hy[3] = sout ? DC.h : hy[3]; oy[3] = sout ? DC.o[7] : oy[3]; \
-            ey[4] = b4 ? DC.eta : ey[4];   hy[4] = b4 ? DC.h : hy[4];   oy[4] = b4 ? DC.o[8] : oy[4];   \
-            ey[5] = eout ? DC.eta : ey[5]; hy[5] = eout ? DC.h : hy[5]; oy[5] = eout ? DC.o[1] : oy[5]; \
-            ey[6] = b6 ? DC.eta : ey[6];   hy[6] = b6 ? DC.h : hy[6];   oy[6] = b6 ? DC.o[2] : oy[6];   \
-            ey[7] = nout ? DC.eta : ey[7]; hy[7] = nout ? DC.h : hy[7]; oy[7] = nout ? DC.o[3] : oy[7]; \
-            ey[8] = b8 ? DC.eta : ey[8];   hy[8] = b8 ? DC.h : hy[8];   oy[8] = b8 ? DC.o[4] : oy[8];   \
+            P[1] = wout ? 0.0f : P[1]; oy[1] = wout ? DC.o[5] : oy[1];                            \
+            P[2] = b2 ? 0.0f : P[2];   oy[2] = b2 ? DC.o[6] : oy[2];                              \
+            P[3] = sout ? 0.0f : P[3]; oy[3] = sout ? DC.o[7] : oy[3];                            \
+            P[4] = b4 ? 0.0f : P[4];   oy[4] = b4 ? DC.o[8] : oy[4];                              \
+            P[5] = eout ? 0.0f : P[5]; oy[5] = eout ? DC.o[1] : oy[5];                            \
+            P[6] = b6 ? 0.0f : P[6];   oy[6] = b6 ? DC.o[2] : oy[6];                              \
+            P[7] = nout ? 0.0f : P[7]; oy[7] = nout ? DC.o[3] : oy[7];                            \
+            P[8] = b8 ? 0.0f : P[8];   oy[8] = b8 ? DC.o[4] : oy[8];                              \
         }                                                                                         \
         float en, qxn, qyn;                                                                       \
-        update(B, DC, ey, hy, oy, en, qxn, qyn);                                                  \
+        update(B, DC, P, oy, en, qxn, qyn);                                                       \
         bool store = own_col && (r) >= T.yo && (r) < r1;                                          \
         if (EDGE) {                                                                               \
             /* pre-override values of the x-neighbours (inward normals of W / E) */               \
@@ -237,18 +251,36 @@ __device__ __forceinline__ double depth_bc(const BasinDev& B, int k, double tn)
             en = fe; qxn = fx; qyn = fy;                                                          \
         }                                                                                         \
         if (store) {                                                                              \
-            const size_t o = (size_t)(r) * ld + x;                                                \
-            E1[o] = en; QX1[o] = qxn; QY1[o] = qyn;                                               \
+            const uint32_t o = ((uint32_t)((r) * ld) + (uint32_t)x) * 4u;                         \
+            stf(E1, o, en); stf(QX1, o, qxn); stf(QY1, o, qyn);                                   \
             if (DIAG) account(sums, en, qxn, qyn, DC.H, DC.q0x, DC.q0y);                          \
         }                                                                                         \
     } while (0)
 
+// Field access as SGPR base + 32-bit VGPR byte offset (one offset per row
+// serves all fields).  Offsets fit in 32 bits: a plane holds < 2^30 floats.
+typedef __attribute__((address_space(1))) const char gcbyte;
+typedef __attribute__((address_space(1))) char gbyte;
+__device__ __forceinline__ float ldf(const gfloat* base, uint32_t byte_off)
+{
+    return *(const gfloat*)((gcbyte*)base + byte_off);
+}
+__device__ __forceinline__ void stf(gfloat* base, uint32_t byte_off, float v)
+{
+#if MLB_NT_STORE
+    __builtin_nontemporal_store(v, (gfloat*)((gbyte*)base + byte_off));
+#else
+    *(gfloat*)((gbyte*)base + byte_off) = v;
+#endif
+}
+
 __device__ __forceinline__ Raw load_raw(const gfloat* __restrict__ E0, const gfloat* __restrict__ QX0,
                                         const gfloat* __restrict__ QY0, const gfloat* __restrict__ HH,
-                                        size_t o)
+                                        uint32_t o)
 {
+    const uint32_t b = o * 4u;
     Raw w;
-    w.eta = E0[o]; w.qx = QX0[o]; w.qy = QY0[o]; w.H = HH[o];
+    w.eta = ldf(E0, b); w.qx = ldf(QX0, b); w.qy = ldf(QY0, b); w.H = ldf(HH, b);
     return w;
 }
 
@@ -325,21 +357,25 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     // are derived.  Raw slots, window rows and derived nodes rotate with
     // period 3, so the loop is unrolled by 3 and the rotation is a renaming
     // (no register copy ever waits on a load in flight).
-    Raw wa = load_raw(E0, QX0, QY0, HH, wrap_or_clamp(r0 + 1, ny, per_y) * ld + xl);
-    Raw wb = load_raw(E0, QX0, QY0, HH, wrap_or_clamp(r0 + 2, ny, per_y) * ld + xl);
-    Raw wc = load_raw(E0, QX0, QY0, HH, wrap_or_clamp(r0 + 3, ny, per_y) * ld + xl);
+    Raw wa = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 1, r1), ny, per_y) * ld) + (uint32_t)xl);
+    Raw wb = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 2, r1), ny, per_y) * ld) + (uint32_t)xl);
+    Raw wc = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 3, r1), ny, per_y) * ld) + (uint32_t)xl);
     Derived d0, d1, d2;
     Row R0, R1, R2;
     {
-        const Raw w = load_raw(E0, QX0, QY0, HH, wrap_or_clamp(r0 - 1, ny, per_y) * ld + xl);
+        const Raw w = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 - 1, r1), ny, per_y) * ld) + (uint32_t)xl);
         derive(B, w.eta, w.qx, w.qy, w.H, d0);
         exchange(d0, R0);
     }
     {
-        const Raw w = load_raw(E0, QX0, QY0, HH, wrap_or_clamp(r0, ny, per_y) * ld + xl);
+        const Raw w = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0, r1), ny, per_y) * ld) + (uint32_t)xl);
         derive(B, w.eta, w.qx, w.qy, w.H, d1);
         exchange(d1, R1);
     }
+    // links of row r0-1 towards row r0, as row r0 receives them
+    float cN = link(d0.h, d0.eta, R1.h, R1.eta);
+    float cNEl = from_left(link(d0.h, d0.eta, R1.hr, R1.er));
+    float cNWr = from_right(link(d0.h, d0.eta, R1.hl, R1.el));
     // single-exit counted loop: the tile's rows are rounded up to a multiple
     // of 3 and the pad rows (r >= r1) are computed but never stored
     const int nk = (T.rows + 2) / 3;
@@ -370,7 +406,8 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 
 // ------------------------------------------------------------------ kernels
 template <bool DIAG>
-__global__ __launch_bounds__(kBlock) void step_kernel(const BasinDev* __restrict__ basins,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIAG ? 4 : 5)))
+void step_kernel(const BasinDev* __restrict__ basins,
                                                       const TileDev* __restrict__ tiles, int ntiles,
                                                       int parity, double* __restrict__ partials)
 {
@@ -500,17 +537,18 @@ int step_occupancy(int diag)
 }
 
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, hipStream_t s)
+                       double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s)
 {
+    // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
     if (tblock != 1) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (diag)
-        hipLaunchKernelGGL(step_kernel<true>, grid, dim3(kBlock), 0, s, d_basins, d_tiles, ntiles,
-                           parity, d_partials);
+        hipLaunchKernelGGL(step_kernel<true>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+                           ntiles, parity, d_partials);
     else
-        hipLaunchKernelGGL(step_kernel<false>, grid, dim3(kBlock), 0, s, d_basins, d_tiles, ntiles,
-                           parity, d_partials);
+        hipLaunchKernelGGL(step_kernel<false>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+                           ntiles, parity, d_partials);
     return hipGetLastError();
 }
 

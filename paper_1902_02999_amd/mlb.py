@@ -50,7 +50,10 @@ class Diag(C.Structure):
 
 class ExecOpts(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("tblock", C.c_int32), ("use_graph", C.c_int32),
-                ("graph_chunk", C.c_int32)]
+                ("graph_chunk", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 # Every exported symbol of include/mlb.h with its ctypes signature.
@@ -87,6 +90,8 @@ SIGNATURES = {
     "mlb_batch_destroy": (C.c_int, [_VP]),
     "mlb_last_step_ms": (C.c_int, [_VP, _DP]),
     "mlb_copy_probe": (C.c_int, [_VP, C.c_size_t, C.c_int32, _DP]),
+    "mlb_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
+    "mlb_batch_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
 }
 
 _lib = None
@@ -246,13 +251,22 @@ class Grid:
         _check(lib().mlb_get_exec_opts(self.h, C.byref(o)), "mlb_get_exec_opts")
         return o
 
-    def set_exec_opts(self, tile_rows=None, tblock=None, use_graph=None, graph_chunk=None):
+    def set_exec_opts(self, tile_rows=None, tblock=None, use_graph=None, graph_chunk=None,
+                      blocks_per_cu=None):
         o = self.exec_opts()
         if tile_rows is not None: o.tile_rows = tile_rows
         if tblock is not None: o.tblock = tblock
         if use_graph is not None: o.use_graph = int(use_graph)
         if graph_chunk is not None: o.graph_chunk = graph_chunk
+        if blocks_per_cu is not None: o.blocks_per_cu = blocks_per_cu
         _check(lib().mlb_set_exec_opts(self.h, C.byref(o)), "mlb_set_exec_opts")
+
+    def autotune(self, steps: int = 40, cache_path: Optional[str] = None) -> dict:
+        """Time the candidate execution options, apply the fastest; state kept."""
+        o = ExecOpts()
+        _check(lib().mlb_autotune(self.h, int(steps), None if cache_path is None else cache_path.encode(),
+                                  C.byref(o)), "mlb_autotune")
+        return o.as_dict()
 
     def step(self, n: int = 1):
         _check(lib().mlb_step(self.h, int(n)), "mlb_step")
@@ -288,9 +302,15 @@ class Batch:
         _check(lib().mlb_batch_create(ctx.h, arr, len(grids), C.byref(h)), "mlb_batch_create")
         self.h = h
 
-    def set_exec_opts(self, tile_rows=64, tblock=1, use_graph=True, graph_chunk=64):
-        o = ExecOpts(tile_rows, tblock, int(use_graph), graph_chunk)
+    def set_exec_opts(self, tile_rows=27, tblock=1, use_graph=True, graph_chunk=64, blocks_per_cu=3):
+        o = ExecOpts(tile_rows, tblock, int(use_graph), graph_chunk, blocks_per_cu)
         _check(lib().mlb_batch_set_exec_opts(self.h, C.byref(o)), "mlb_batch_set_exec_opts")
+
+    def autotune(self, steps: int = 20, cache_path: Optional[str] = None) -> dict:
+        o = ExecOpts()
+        _check(lib().mlb_batch_autotune(self.h, int(steps), None if cache_path is None else cache_path.encode(),
+                                        C.byref(o)), "mlb_batch_autotune")
+        return o.as_dict()
 
     def step(self, n: int = 1):
         _check(lib().mlb_batch_step(self.h, int(n)), "mlb_batch_step")

@@ -265,3 +265,55 @@ def test_full_size_bump_channel_sampled(ctx):
         assert abs(h1[j, i] - o[0]) <= 1e-6 * hmax, (i, j)
         assert abs(qx1[j, i] - o[1]) <= 1e-6 * qmax and abs(qy1[j, i] - o[2]) <= 1e-6 * qmax, (i, j)
     g.close()
+
+
+# ----------------------------------------------------------------------------- tuning
+def test_blocks_per_cu_bitwise(ctx):
+    spec = wl.bump_channel(200, 130, sigma=12.0)
+    outs = [run_gpu(ctx, spec, 64, opts={"blocks_per_cu": cap, "tile_rows": 21}) for cap in (0, 1, 3, 8)]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_autotune_keeps_state_and_caches(ctx, tmp_path):
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(300, 170, 8)
+    g = mlb.grid_from_spec(ctx, spec)
+    g.set_state(*wl.seeded_state(spec, 8, q_amp=0.1), step0=5)
+    before = g.get_state()
+    cache = str(tmp_path / "tune.txt")
+    say("autotune", spec.name)
+    best = g.autotune(steps=8, cache_path=cache)
+    assert best["tile_rows"] in (6, 9, 12, 15, 21, 27, 33, 45) and best["blocks_per_cu"] in (0, 2, 3, 4, 5)
+    after = g.get_state()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert g.diag()["step"] == 5
+    lines = open(cache).read().split()
+    assert len(lines) == 4 and lines[0].endswith("_g300x170")
+    # second call: served from the cache, same choice
+    assert g.autotune(steps=8, cache_path=cache) == g.exec_opts().as_dict()
+    # stepping after tuning equals stepping an untuned copy
+    g.step(33)
+    ref = run_gpu(ctx, spec, 33, state=wl.seeded_state(spec, 8, q_amp=0.1), step0=5)
+    for a, b in zip(g.get_state(), ref):
+        assert np.array_equal(a, b)
+    g.close()
+
+
+def test_batch_autotune_keeps_state(ctx):
+    from paper_1902_02999_amd import mlb
+    specs = [closed_spec(n, n, s) for n, s in ((70, 1), (130, 2), (64, 3))]
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    for g, s in zip(grids, specs):
+        g.set_state(*wl.seeded_state(s, 1, q_amp=0.1))
+    before = [g.get_state() for g in grids]
+    b = mlb.Batch(ctx, grids)
+    best = b.autotune(steps=6)
+    assert best["tile_rows"] in (6, 9, 12, 15, 21, 27, 33, 45)
+    b.close()
+    for g, bf in zip(grids, before):
+        for x, y in zip(g.get_state(), bf):
+            assert np.array_equal(x, y)
+        g.close()
