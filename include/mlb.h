@@ -212,6 +212,68 @@ mlb_status mlb_last_step_ms(mlb_ctx* ctx, double* ms);
  * [GB/s] from HIP events.  Used as the reference for measured HBM traffic. */
 mlb_status mlb_copy_probe(mlb_ctx* ctx, size_t bytes, int32_t reps, double* gbps);
 
+/* ------------------------------------------------------------------ learned warm start
+ * A convolutional encoder-decoder maps a basin's still-water depth and forcing
+ * to a guess of its steady state (eta, hu, hv); the step then iterates from the
+ * guess (no counterpart in the paper: it only shortens steady-state runs).
+ *
+ * Architecture (levels L, ch[l] = base_ch 2^l): per encoder level two 3x3
+ * convolutions + ReLU (2x2 average pool between levels); per decoder level a
+ * nearest x2 upsample, a 3x3 conv + ReLU, concatenation with the encoder
+ * level's output, two 3x3 convs + ReLU; a 1x1 head to 3 channels.  The input
+ * has in_ch channels (6 features, the rest zero).  Convolutions run on BF16
+ * MFMA with FP32 accumulation; FP32 master parameters.  Parameters are ordered
+ * layer by layer in forward order, each 3x3 weight [Cout][3][3][Cin] then its
+ * bias; the head weight [3][base_ch] then its bias.
+ * Requirements: in_ch and base_ch multiples of 32; width / 2^(L-1) a
+ * multiple of 32; height a multiple of 2^(L-1). */
+typedef struct mlb_net mlb_net;
+typedef struct {
+    int32_t height, width;   /* field size                                            */
+    int32_t in_ch;           /* input channels (>= 6; 6 used)                          */
+    int32_t out_ch;          /* 3: eta, hu, hv                                         */
+    int32_t base_ch;         /* channels of the finest level                           */
+    int32_t levels;          /* >= 2                                                   */
+    int32_t max_batch;       /* samples per forward / backward call                    */
+} mlb_net_cfg;
+typedef struct {
+    float in_mean[4], in_std[4]; /* still-water depth, tau_x/rho, tau_y/rho, C_b       */
+    float s_eta, s_q;            /* output scales: eta = s_eta y0, q = s_q (y1, y2)     */
+} mlb_net_norm;
+typedef struct { float lr, beta1, beta2, eps, weight_decay; } mlb_adamw_cfg;
+
+/* Creates a net with He-normal weights from `seed` and zero biases. */
+mlb_status mlb_net_create(mlb_ctx* ctx, const mlb_net_cfg* cfg, uint64_t seed, mlb_net** out);
+mlb_status mlb_net_destroy(mlb_net* net);
+mlb_status mlb_net_param_count(const mlb_net* net, int64_t* n);
+/* FP32 parameters to / from host memory (set_params also refreshes the BF16 copies). */
+mlb_status mlb_net_get_params(mlb_net* net, float* host, int64_t n);
+mlb_status mlb_net_set_params(mlb_net* net, const float* host, int64_t n);
+mlb_status mlb_net_set_norm(mlb_net* net, const mlb_net_norm* norm);
+mlb_status mlb_net_get_norm(const mlb_net* net, mlb_net_norm* norm);
+/* Forward pass: x [n][height][width][6] FP32 (device) -> y [n][height][width][3] FP32 (device). */
+mlb_status mlb_net_forward(mlb_net* net, const float* x_dev, int32_t n, float* y_dev);
+/* Forward + backward of the masked MSE against targets t [n][h][w][3] (device);
+ * mask [n][h][w] (device, may be NULL = all ones) with mask_count = its sum.
+ * Leaves the parameter gradient in the net (for mlb_net_adamw); *loss (may
+ * be NULL) receives the loss; grad_host (may be NULL) receives the gradient. */
+mlb_status mlb_net_loss_grad(mlb_net* net, const float* x_dev, const float* t_dev, const float* mask_dev,
+                             double mask_count, int32_t n, double* loss, float* grad_host);
+/* One AdamW step (decoupled weight decay) with the last gradient. */
+mlb_status mlb_net_adamw(mlb_net* net, const mlb_adamw_cfg* cfg);
+/* Features of a grid (its still-water depth and forcing, normalised) into
+ * x_dev [height][width][6]; targets (its current state, normalised) into
+ * t_dev [height][width][3].  The grid must be height x width. */
+mlb_status mlb_net_features(mlb_net* net, mlb_grid* g, float* x_dev);
+mlb_status mlb_net_targets(mlb_net* net, mlb_grid* g, float* t_dev);
+/* Warm start: writes the net's guess into the grid's state.  The guess's mean
+ * surface perturbation is removed so the basin holds its still-water volume
+ * (closed basins conserve it, so the steady state has that volume), and
+ * discharge is zero on wall nodes. */
+mlb_status mlb_net_infer(mlb_net* net, mlb_grid* g);
+mlb_status mlb_net_save(const mlb_net* net, const char* path);
+mlb_status mlb_net_load(mlb_net* net, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

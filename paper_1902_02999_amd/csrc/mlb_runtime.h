@@ -1,0 +1,113 @@
+// Runtime objects shared by the host-side translation units of libmlb.so.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/mlb.h"
+#include "mlb_internal.h"
+
+namespace mlb {
+
+// Sets the calling thread's last error message and returns s.
+mlb_status fail(mlb_status s, const std::string& msg);
+
+}  // namespace mlb
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::mlb::fail(e_ == hipErrorOutOfMemory ? MLB_E_NOMEM : MLB_E_DEVICE,      \
+                               std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+#define CHK(expr)                                 \
+    do {                                          \
+        mlb_status s_ = (expr);                   \
+        if (s_ != MLB_OK) return s_;              \
+    } while (0)
+
+namespace mlb {
+
+// Device-side plan of a set of basins: descriptors, tile list,
+// reduction partials, and an optional captured chunk of steps.
+struct Plan {
+    std::vector<BasinDev> hb;
+    std::vector<TileDev> ht;
+    BasinDev* db = nullptr;
+    TileDev* dt = nullptr;
+    double* dpart = nullptr;
+    double* dout = nullptr;
+    double* hout = nullptr;  // pinned
+    int parity = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int gparity = -1;
+    int gsteps = 0;
+    unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
+    bool built = false;
+
+    void release()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0;
+        (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dpart);
+        (void)hipFree(dout);
+        if (hout) (void)hipHostFree(hout);
+        db = nullptr; dt = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
+        built = false;
+    }
+};
+
+}  // namespace mlb
+
+struct mlb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int live = 0;
+    int ncu = 0;
+    int lds_per_cu = 0;        // bytes
+    std::string arch;          // gcnArchName, for autotuner cache keys
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+struct mlb_grid {
+    mlb_ctx* ctx = nullptr;
+    mlb_params p{};
+    int ld = 0;
+    size_t plane = 0;          // floats per field plane
+    char* base = nullptr;
+    bool own = false;
+    float* eta[2] = {nullptr, nullptr};
+    float* qx[2] = {nullptr, nullptr};
+    float* qy[2] = {nullptr, nullptr};
+    float* H = nullptr;
+    int64_t* stepc = nullptr;
+    std::vector<float> Hf;     // stored (FP32) still-water depth, host copy
+    std::vector<double> Hd;    // still-water depth zeta_ref - z_b as given (FP64):
+                               // host conversions h <-> eta and the mass use it
+    int cur = 0;
+    int64_t step = 0;
+    double e = 0, dt = 0, sumH = 0, Hmax = 0;
+    double tx = 0, ty = 0, cb = 0;
+    double bc_hmean[4] = {0, 0, 0, 0}, bc_amp[4] = {0, 0, 0, 0}, bc_om[4] = {0, 0, 0, 0},
+           bc_phase[4] = {0, 0, 0, 0}, bc_qx[4] = {0, 0, 0, 0}, bc_qy[4] = {0, 0, 0, 0};
+    mlb_batch* batch = nullptr;
+    mlb_exec_opts opts{15, 1, 1, 64, 3};
+    mlb::Plan plan;
+    bool dirty = true;         // descriptor must be re-uploaded
+    bool stale_plan = true;    // tiles / allocation must be rebuilt
+};
+
+struct mlb_batch {
+    mlb_ctx* ctx = nullptr;
+    std::vector<mlb_grid*> grids;
+    mlb_exec_opts opts{15, 1, 1, 64, 3};
+    mlb::Plan plan;
+    bool stale_plan = true;
+};
+

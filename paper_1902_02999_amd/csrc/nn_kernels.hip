@@ -1,0 +1,611 @@
+// gfx950 kernels of the warm-start network: 3x3 convolutions as implicit
+// GEMMs on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation), the
+// weight gradient with a deterministic split-K, pooling / upsampling, the 1x1
+// head, the masked MSE loss and AdamW.
+//
+// Layouts: activations NHWC BF16 with a channel stride `ld` and offset (so a
+// concatenation is just two writers into one buffer); gradients NHWC FP32;
+// conv weights [Cout][9][Cin] BF16 (tap = 3 dy + dx), which is also the order
+// of the FP32 master parameters.
+//
+// MFMA 16x16x32 operand layout (64 lanes; l16 = lane % 16, lq = lane / 16):
+//   A (16 x 32):  lane holds A[l16][8 lq .. 8 lq + 7]
+//   B (32 x 16):  lane holds B[8 lq .. 8 lq + 7][l16]
+//   D (16 x 16):  lane holds D[4 lq .. 4 lq + 3][l16]
+#include "nn_internal.h"
+
+namespace mlb {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p)  // 16-byte aligned
+{
+    return *(const bf16x8*)p;
+}
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+
+// ------------------------------------------------------------------ conv 3x3
+// Y[p][n] = act(bias[n] + sum_{t,c} X[p + off_t][c] W[n][t][c]); one wave
+// computes 32 consecutive pixels of one image row x 32 output channels.
+// OUT_F32: FP32 output (optionally accumulated into), else BF16.
+template <bool OUT_F32>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ntile = a.cout / 32;
+    const int total = a.n * a.h * (a.w / 32) * ntile;
+    if (wave >= total) return;
+    const int nt = wave % ntile;
+    const int pt = wave / ntile;            // pixel tile: 32 pixels of one row
+    const int xt = pt % (a.w / 32);
+    const int row = pt / (a.w / 32);        // image * h + y
+    const int y = row % a.h, img = row / a.h;
+    const int x0 = xt * 32, n0 = nt * 32;
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const int yy = y + dy;
+        const bool rowok = yy >= 0 && yy < a.h;
+        for (int c0 = 0; c0 < a.cin; c0 += 32) {
+            bf16x8 A[2], Bm[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const int xx = x0 + mb * 16 + l16 + dx;
+                if (rowok && xx >= 0 && xx < a.w) {
+                    const size_t p = ((size_t)img * a.h + yy) * a.w + xx;
+                    A[mb] = load8(a.x + p * a.ldx + a.xoff + c0 + lq * 8);
+                } else {
+                    A[mb] = zero8();
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int n = n0 + nb * 16 + l16;
+                Bm[nb] = load8(a.wt + ((size_t)n * 9 + t) * a.cin + c0 + lq * 8);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+        }
+    }
+    // epilogue: D[mb][nb] lane holds pixels x0 + 16 mb + 4 lq + i, channel n0 + 16 nb + l16
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const int n = n0 + nb * 16 + l16;
+            const float bn = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xx = x0 + mb * 16 + lq * 4 + i;
+                const size_t p = ((size_t)img * a.h + y) * a.w + xx;
+                float v = acc[mb][nb][i] + bn;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                if (OUT_F32) {
+                    float* o = a.yf + p * a.ldy + a.yoff + n;
+                    *o = a.accumulate ? *o + v : v;
+                } else {
+                    a.yb[p * a.ldy + a.yoff + n] = (__bf16)v;
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------------ weight gradient
+// Partial dW over a pixel range: part[s][n][t][c] = sum_{p in chunk s} dz[p][n] X[p + off_t][c].
+// One wave: 32 output channels x (one tap, 32 input channels), K = pixels.
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
+{
+    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ntile = a.cout / 32, ctile = a.cin / 32;
+    const int per_split = ntile * 9 * ctile;
+    if (wave >= per_split * a.nsplit) return;
+    const int s = wave / per_split;
+    int r = wave % per_split;
+    const int ct = r % ctile; r /= ctile;
+    const int t = r % 9;
+    const int nt = r / 9;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int64_t nch = (int64_t)a.n * a.h * a.w / 32;                     // 32-pixel chunks
+    const int64_t pbeg = nch * s / a.nsplit * 32, pend = nch * (s + 1) / a.nsplit * 32;
+    const int n0 = nt * 32, c0 = ct * 32;
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
+        bf16x8 A[2], Bm[2];
+        // A (rows n, K = pixels): dz[p][n] for 8 consecutive pixels
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int n = n0 + mb * 16 + l16;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) A[mb][e] = a.dz[(p0 + lq * 8 + e) * a.cout + n];
+        }
+        // B (K = pixels, cols c): X at the tap-shifted pixel (zero outside the image)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t p = p0 + lq * 8 + e;
+            const int xx = (int)(p % a.w) + dx;
+            const int64_t ry = p / a.w;
+            const int yy = (int)(ry % a.h) + dy;
+            const bool ok = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h;
+            const int64_t q = p + (int64_t)dy * a.w + dx;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const int c = c0 + nb * 16 + l16;
+                Bm[nb][e] = ok ? a.x[q * a.ldx + a.xoff + c] : (__bf16)0.0f;
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+    }
+    float* out = a.part + (size_t)s * a.cout * 9 * a.cin;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = n0 + mb * 16 + lq * 4 + i;
+                const int c = c0 + nb * 16 + l16;
+                out[((size_t)n * 9 + t) * a.cin + c] = acc[mb][nb][i];
+            }
+}
+
+// Sum of nsplit partial arrays in a fixed order, written (not added) to dst.
+__global__ void sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t len,
+                                  float* __restrict__ dst)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.0f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + i];
+    dst[i] = s;
+}
+
+// Per-channel sums over pixels (bias gradients): part[chunk][c] then a fixed-order sum.
+__global__ void chan_sum_partial_kernel(const float* __restrict__ g, int64_t npix, int c, int ld,
+                                        int chunk, float* __restrict__ part)
+{
+    const int ch = threadIdx.x + blockIdx.y * blockDim.x;
+    if (ch >= c) return;
+    const int64_t b = (int64_t)blockIdx.x * chunk, e = min<int64_t>(b + chunk, npix);
+    float s = 0.0f;
+    for (int64_t p = b; p < e; ++p) s += g[p * ld + ch];
+    part[(size_t)blockIdx.x * c + ch] = s;
+}
+
+// ------------------------------------------------------------------ elementwise
+// dz (BF16 and FP32, contiguous [p][c]) = dy (FP32, stride ldd at doff) where
+// the activation y (BF16, stride ldy at yoff) > 0.
+__global__ void relu_mask_kernel(const float* __restrict__ dy, int ldd, int doff, const __bf16* __restrict__ y,
+                                 int ldy, int yoff, int64_t npix, int c, __bf16* __restrict__ dz,
+                                 float* __restrict__ dzf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * c) return;
+    const int64_t p = i / c;
+    const int ch = (int)(i % c);
+    const float v = (float)y[p * ldy + yoff + ch] > 0.0f ? dy[p * ldd + doff + ch] : 0.0f;
+    dz[i] = (__bf16)v;
+    dzf[i] = v;
+}
+
+// Rotated, transposed weights for the data gradient: wr[c][t][n] = w[n][8 - t][c].
+__global__ void weight_flip_kernel(const __bf16* __restrict__ w, int cout, int cin, __bf16* __restrict__ wr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)cout * 9 * cin) return;
+    const int c = (int)(i % cin);
+    const int t = (int)((i / cin) % 9);
+    const int n = (int)(i / ((int64_t)cin * 9));
+    wr[((size_t)c * 9 + (8 - t)) * cout + n] = w[i];
+}
+
+__global__ void pool2_kernel(const __bf16* __restrict__ x, int ldx, int xoff, int n, int h, int w, int c,
+                             __bf16* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ho = h / 2, wo = w / 2;
+    if (i >= (int64_t)n * ho * wo * c) return;
+    const int ch = (int)(i % c);
+    int64_t r = i / c;
+    const int xo = (int)(r % wo); r /= wo;
+    const int yo = (int)(r % ho);
+    const int img = (int)(r / ho);
+    auto at = [&](int yy, int xx) { return (float)x[(((int64_t)img * h + yy) * w + xx) * ldx + xoff + ch]; };
+    const float s = (at(2 * yo, 2 * xo) + at(2 * yo, 2 * xo + 1)) + (at(2 * yo + 1, 2 * xo) + at(2 * yo + 1, 2 * xo + 1));
+    y[i] = (__bf16)(0.25f * s);
+}
+
+// dx[fine] (+)= dy[coarse] / 4; dx has channel stride ldx at offset xoff
+__global__ void pool2_back_kernel(const float* __restrict__ dy, int n, int h, int w, int c,
+                                  float* __restrict__ dx, int ldx, int xoff, int accumulate)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * h * w * c) return;
+    const int ch = (int)(i % c);
+    const int64_t r0 = i / c;
+    int64_t r = r0;
+    const int xx = (int)(r % w); r /= w;
+    const int yy = (int)(r % h);
+    const int img = (int)(r / h);
+    const float v = 0.25f * dy[(((int64_t)img * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch];
+    float* o = dx + r0 * ldx + xoff + ch;
+    *o = accumulate ? *o + v : v;
+}
+
+// nearest x2: y[fine] = x[coarse]
+__global__ void up2_kernel(const __bf16* __restrict__ x, int n, int h, int w, int c, __bf16* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int hf = 2 * h, wf = 2 * w;
+    if (i >= (int64_t)n * hf * wf * c) return;
+    const int ch = (int)(i % c);
+    int64_t r = i / c;
+    const int xx = (int)(r % wf); r /= wf;
+    const int yy = (int)(r % hf);
+    const int img = (int)(r / hf);
+    y[i] = x[(((int64_t)img * h + yy / 2) * w + xx / 2) * c + ch];
+}
+
+// dx[coarse] = sum of the 4 fine gradients
+__global__ void up2_back_kernel(const float* __restrict__ dy, int n, int h, int w, int c, float* __restrict__ dx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * h * w * c) return;
+    const int ch = (int)(i % c);
+    int64_t r = i / c;
+    const int xx = (int)(r % w); r /= w;
+    const int yy = (int)(r % h);
+    const int img = (int)(r / h);
+    const int wf = 2 * w;
+    auto at = [&](int fy, int fx) { return dy[(((int64_t)img * 2 * h + fy) * wf + fx) * c + ch]; };
+    dx[i] = (at(2 * yy, 2 * xx) + at(2 * yy, 2 * xx + 1)) + (at(2 * yy + 1, 2 * xx) + at(2 * yy + 1, 2 * xx + 1));
+}
+
+// ------------------------------------------------------------------ head (1x1), loss
+// y[p][o] = b[o] + sum_c x[p][c] w[o][c]   (FP32 weights, FP32 output)
+__global__ void head_kernel(const __bf16* __restrict__ x, int64_t npix, int cin, const float* __restrict__ w,
+                            const float* __restrict__ b, int cout, float* __restrict__ y)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    for (int o = 0; o < cout; ++o) {
+        float s = b[o];
+        for (int c = 0; c < cin; ++c) s = __builtin_fmaf((float)x[p * cin + c], w[o * cin + c], s);
+        y[p * cout + o] = s;
+    }
+}
+
+// dx[p][c] = sum_o dy[p][o] w[o][c]
+__global__ void head_back_kernel(const float* __restrict__ dy, int64_t npix, int cout, const float* __restrict__ w,
+                                 int cin, float* __restrict__ dx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * cin) return;
+    const int64_t p = i / cin;
+    const int c = (int)(i % cin);
+    float s = 0.0f;
+    for (int o = 0; o < cout; ++o) s = __builtin_fmaf(dy[p * cout + o], w[o * cin + c], s);
+    dx[i] = s;
+}
+
+// part[chunk][o][c] = sum over the chunk's pixels of dy[p][o] x[p][c]
+__global__ void head_wgrad_partial_kernel(const float* __restrict__ dy, const __bf16* __restrict__ x, int64_t npix,
+                                          int cout, int cin, int chunk, float* __restrict__ part)
+{
+    const int j = threadIdx.x + blockIdx.y * blockDim.x;   // o * cin + c
+    if (j >= cout * cin) return;
+    const int o = j / cin, c = j % cin;
+    const int64_t b = (int64_t)blockIdx.x * chunk, e = min<int64_t>(b + chunk, npix);
+    float s = 0.0f;
+    for (int64_t p = b; p < e; ++p) s = __builtin_fmaf(dy[p * cout + o], (float)x[p * cin + c], s);
+    part[(size_t)blockIdx.x * cout * cin + j] = s;
+}
+
+// Masked MSE: dy = 2 m (y - t) / cnt, partial sums of m (y - t)^2 in FP64 per block.
+__global__ void mse_kernel(const float* __restrict__ y, const float* __restrict__ t, const float* __restrict__ mask,
+                           int64_t npix, int c, double inv_cnt, float* __restrict__ dy, double* __restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (i < npix * c) {
+        const float m = mask ? mask[i / c] : 1.0f;
+        const float r = (y[i] - t[i]) * m;
+        dy[i] = (float)(2.0 * inv_cnt) * r;
+        s = (double)r * (double)r;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_f64_kernel(const double* __restrict__ part, int n, double scale, double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+}
+
+// ------------------------------------------------------------------ AdamW
+// theta -= lr (mhat / (sqrt(vhat) + eps) + wd theta), FP32 masters; bf16 copies
+// of conv weights refreshed through the map wmap (index into bf16 array, -1: none).
+__global__ void adamw_kernel(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                             float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float wd,
+                             float c1, float c2, const int64_t* __restrict__ wmap, __bf16* __restrict__ wb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    const float t = th[i] - lr * (mh / (sqrtf(vh) + eps) + wd * th[i]);
+    th[i] = t;
+    const int64_t k = wmap[i];
+    if (k >= 0) wb[k] = (__bf16)t;
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ src, int64_t n, __bf16* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (__bf16)src[i];
+}
+
+// Input features (FP32 [p][nin]) -> BF16 [p][ldc] with zero padding channels.
+__global__ void pack_input_kernel(const float* __restrict__ x, int64_t npix, int nin, int ldc, __bf16* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * ldc) return;
+    const int64_t p = i / ldc;
+    const int c = (int)(i % ldc);
+    y[i] = (__bf16)(c < nin ? x[p * nin + c] : 0.0f);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
+{
+    const int64_t waves = (int64_t)a.n * a.h * (a.w / 32) * (a.cout / 32);
+    if (a.yf) hipLaunchKernelGGL(conv3x3_kernel<true>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(conv3x3_kernel<false>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
+{
+    const int64_t waves = (int64_t)(a.cout / 32) * 9 * (a.cin / 32) * a.nsplit;
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    const size_t len = (size_t)a.cout * 9 * a.cin;
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, a.part, a.nsplit, len, dw);
+    return hipGetLastError();
+}
+
+hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, int nchunk, float* dst, hipStream_t s)
+{
+    const int chunk = (int)((npix + nchunk - 1) / nchunk);
+    hipLaunchKernelGGL(chan_sum_partial_kernel, dim3(nchunk, (c + 255) / 256), dim3(256), 0, s, g, npix, c, ld, chunk, part);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(c, 256)), dim3(256), 0, s, part, nchunk, (size_t)c, dst);
+    return hipGetLastError();
+}
+
+hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
+                     __bf16* dz, float* dzf, hipStream_t s)
+{
+    hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c, 256)), dim3(256), 0, s, dy, ldd, doff, y, ldy,
+                       yoff, npix, c, dz, dzf);
+    return hipGetLastError();
+}
+
+hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream_t s)
+{
+    hipLaunchKernelGGL(weight_flip_kernel, dim3(blocks_for((int64_t)cout * 9 * cin, 256)), dim3(256), 0, s, w, cout, cin, wr);
+    return hipGetLastError();
+}
+
+hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c, __bf16* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * c, 256)), dim3(256), 0, s,
+                       x, ldx, xoff, n, h, w, c, y);
+    return hipGetLastError();
+}
+
+hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, int ldx, int xoff, int accumulate,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(pool2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c, 256)), dim3(256), 0, s,
+                       dy, n, h, w, c, dx, ldx, xoff, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t up2(const __bf16* x, int n, int h, int w, int c, __bf16* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(up2_kernel, dim3(blocks_for((int64_t)n * 4 * h * w * c, 256)), dim3(256), 0, s, x, n, h, w, c, y);
+    return hipGetLastError();
+}
+
+hipError_t up2_back(const float* dy, int n, int h, int w, int c, float* dx, hipStream_t s)
+{
+    hipLaunchKernelGGL(up2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c, 256)), dim3(256), 0, s, dy, n, h, w, c, dx);
+    return hipGetLastError();
+}
+
+hipError_t head(const __bf16* x, int64_t npix, int cin, const float* w, const float* b, int cout, float* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(npix, 256)), dim3(256), 0, s, x, npix, cin, w, b, cout, y);
+    return hipGetLastError();
+}
+
+hipError_t head_back(const float* dy, const __bf16* x, int64_t npix, int cout, int cin, const float* w,
+                     float* dx, float* part, int nchunk, float* dw, float* db, float* bpart, hipStream_t s)
+{
+    hipLaunchKernelGGL(head_back_kernel, dim3(blocks_for(npix * cin, 256)), dim3(256), 0, s, dy, npix, cout, w, cin, dx);
+    const int chunk = (int)((npix + nchunk - 1) / nchunk);
+    hipLaunchKernelGGL(head_wgrad_partial_kernel, dim3(nchunk, (cout * cin + 255) / 256), dim3(256), 0, s,
+                       dy, x, npix, cout, cin, chunk, part);
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout * cin, 256)), dim3(256), 0, s, part, nchunk,
+                       (size_t)cout * cin, dw);
+    return chan_sum(dy, npix, cout, cout, bpart, nchunk, db, s);
+}
+
+hipError_t mse(const float* y, const float* t, const float* mask, int64_t npix, int c, double inv_cnt, float* dy,
+               double* part, double* out, hipStream_t s)
+{
+    const unsigned nb = blocks_for(npix * c, 256);
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, y, t, mask, npix, c, inv_cnt, dy, part);
+    hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(64), 0, s, part, (int)nb, inv_cnt, out);
+    return hipGetLastError();
+}
+
+hipError_t adamw(float* th, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 float wd, float c1, float c2, const int64_t* wmap, __bf16* wb, hipStream_t s)
+{
+    hipLaunchKernelGGL(adamw_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, th, g, m, v, n, lr, b1, b2, eps, wd,
+                       c1, c2, wmap, wb);
+    return hipGetLastError();
+}
+
+hipError_t f32_to_bf16(const float* src, int64_t n, __bf16* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t pack_input(const float* x, int64_t npix, int nin, int ldc, __bf16* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(npix * ldc, 256)), dim3(256), 0, s, x, npix, nin, ldc, y);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace mlb
+
+namespace mlb {
+namespace nn {
+
+__global__ void features_kernel(const float* __restrict__ H, int nx, int ny, int ld, float m0, float s0,
+                                float f1, float f2, float f3, float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny) return;
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    float* o = out + i * 6;
+    o[0] = (H[(size_t)y * ld + x] - m0) / s0;
+    o[1] = f1; o[2] = f2; o[3] = f3;
+    o[4] = 0.0f;      // inflow channel: closed basins
+    o[5] = 1.0f;      // wet mask
+}
+
+hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, float tx,
+                    float ty, float cb, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, H, nx, ny, ld,
+                       mean[0], stdv[0], (tx - mean[1]) / stdv[1], (ty - mean[2]) / stdv[2],
+                       (cb - mean[3]) / stdv[3], out);
+    return hipGetLastError();
+}
+
+__global__ void targets_kernel(const float* __restrict__ eta, const float* __restrict__ qx,
+                               const float* __restrict__ qy, int nx, int ny, int ld, float ie, float iq,
+                               float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny) return;
+    const size_t o = (size_t)(i / nx) * ld + (i % nx);
+    out[i * 3 + 0] = eta[o] * ie;
+    out[i * 3 + 1] = qx[o] * iq;
+    out[i * 3 + 2] = qy[o] * iq;
+}
+
+hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, int ny, int ld, float s_eta,
+                   float s_q, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(targets_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, eta, qx, qy, nx,
+                       ny, ld, 1.0f / s_eta, 1.0f / s_q, out);
+    return hipGetLastError();
+}
+
+// Sum of s_eta * y0 over all nodes in FP64: one block, fixed order.
+__global__ void guess_mean_kernel(const float* __restrict__ y, int64_t n, float s_eta, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)(s_eta * y[i * 3]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] / (double)n;
+}
+
+__global__ void guess_write_kernel(const float* __restrict__ y, int nx, int ny, int ld, float s_eta, float s_q,
+                                   int w0, int w1, int w2, int w3, const double* __restrict__ mean,
+                                   float* eta0, float* qx0, float* qy0, float* eta1, float* qx1, float* qy1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny) return;
+    const int x = (int)(i % nx), yy = (int)(i / nx);
+    const bool wall = (w0 && x == 0) || (w1 && x == nx - 1) || (w2 && yy == 0) || (w3 && yy == ny - 1);
+    const float e = (float)((double)(s_eta * y[i * 3]) - mean[0]);
+    const float a = wall ? 0.0f : s_q * y[i * 3 + 1];
+    const float b = wall ? 0.0f : s_q * y[i * 3 + 2];
+    const size_t o = (size_t)yy * ld + x;
+    eta0[o] = e; qx0[o] = a; qy0[o] = b;
+    eta1[o] = e; qx1[o] = a; qy1[o] = b;
+}
+
+hipError_t guess_to_state(const float* y, int nx, int ny, int ld, float s_eta, float s_q, const int* wall4,
+                          double* scratch, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
+                          float* qy1, hipStream_t s)
+{
+    hipLaunchKernelGGL(guess_mean_kernel, dim3(1), dim3(256), 0, s, y, (int64_t)nx * ny, s_eta, scratch);
+    hipLaunchKernelGGL(guess_write_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, y, nx, ny,
+                       ld, s_eta, s_q, wall4[0], wall4[1], wall4[2], wall4[3], scratch, eta0, qx0, qy0, eta1, qx1,
+                       qy1);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace mlb

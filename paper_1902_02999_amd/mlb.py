@@ -56,6 +56,20 @@ class ExecOpts(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NetCfg(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("in_ch", C.c_int32), ("out_ch", C.c_int32),
+                ("base_ch", C.c_int32), ("levels", C.c_int32), ("max_batch", C.c_int32)]
+
+
+class NetNorm(C.Structure):
+    _fields_ = [("in_mean", C.c_float * 4), ("in_std", C.c_float * 4), ("s_eta", C.c_float), ("s_q", C.c_float)]
+
+
+class AdamWCfg(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
+
+
 # Every exported symbol of include/mlb.h with its ctypes signature.
 _VP = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -92,6 +106,21 @@ SIGNATURES = {
     "mlb_copy_probe": (C.c_int, [_VP, C.c_size_t, C.c_int32, _DP]),
     "mlb_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
     "mlb_batch_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
+    "mlb_net_create": (C.c_int, [_VP, C.POINTER(NetCfg), C.c_uint64, C.POINTER(_VP)]),
+    "mlb_net_destroy": (C.c_int, [_VP]),
+    "mlb_net_param_count": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "mlb_net_get_params": (C.c_int, [_VP, C.POINTER(C.c_float), C.c_int64]),
+    "mlb_net_set_params": (C.c_int, [_VP, C.POINTER(C.c_float), C.c_int64]),
+    "mlb_net_set_norm": (C.c_int, [_VP, C.POINTER(NetNorm)]),
+    "mlb_net_get_norm": (C.c_int, [_VP, C.POINTER(NetNorm)]),
+    "mlb_net_forward": (C.c_int, [_VP, _VP, C.c_int32, _VP]),
+    "mlb_net_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double, C.c_int32, _DP, C.POINTER(C.c_float)]),
+    "mlb_net_adamw": (C.c_int, [_VP, C.POINTER(AdamWCfg)]),
+    "mlb_net_features": (C.c_int, [_VP, _VP, _VP]),
+    "mlb_net_targets": (C.c_int, [_VP, _VP, _VP]),
+    "mlb_net_infer": (C.c_int, [_VP, _VP]),
+    "mlb_net_save": (C.c_int, [_VP, C.c_char_p]),
+    "mlb_net_load": (C.c_int, [_VP, C.c_char_p]),
 }
 
 _lib = None
@@ -347,3 +376,79 @@ def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
     h, qx, qy = spec.initial()
     g.set_state(h, qx, qy)
     return g
+
+
+class Net:
+    """The warm-start encoder-decoder (BF16 MFMA kernels, FP32 masters).
+    Tensors passed in are torch CUDA float32 tensors (or raw device pointers)."""
+
+    def __init__(self, ctx: Context, height: int, width: int, base_ch: int = 32, levels: int = 4,
+                 in_ch: int = 32, max_batch: int = 8, seed: int = 0):
+        self.ctx = ctx
+        self.cfg = NetCfg(height, width, in_ch, 3, base_ch, levels, max_batch)
+        h = _VP()
+        _check(lib().mlb_net_create(ctx.h, C.byref(self.cfg), int(seed), C.byref(h)), "mlb_net_create")
+        self.h = h
+        n = C.c_int64()
+        _check(lib().mlb_net_param_count(self.h, C.byref(n)), "mlb_net_param_count")
+        self.nparam = n.value
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparam, np.float32)
+        _check(lib().mlb_net_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), self.nparam),
+               "mlb_net_get_params")
+        return a
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, np.float32)
+        _check(lib().mlb_net_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "mlb_net_set_params")
+
+    def set_norm(self, in_mean, in_std, s_eta, s_q):
+        nm = NetNorm()
+        for k in range(4):
+            nm.in_mean[k], nm.in_std[k] = float(in_mean[k]), float(in_std[k])
+        nm.s_eta, nm.s_q = float(s_eta), float(s_q)
+        _check(lib().mlb_net_set_norm(self.h, C.byref(nm)), "mlb_net_set_norm")
+
+    def get_norm(self) -> dict:
+        nm = NetNorm()
+        _check(lib().mlb_net_get_norm(self.h, C.byref(nm)), "mlb_net_get_norm")
+        return {"in_mean": list(nm.in_mean), "in_std": list(nm.in_std), "s_eta": nm.s_eta, "s_q": nm.s_q}
+
+    def forward(self, x, n, y):
+        _check(lib().mlb_net_forward(self.h, _tensor_ptr(x), int(n), _tensor_ptr(y)), "mlb_net_forward")
+
+    def loss_grad(self, x, t, n, mask=None, mask_count=0.0, want_grad=False):
+        """Returns (loss, gradient as numpy or None)."""
+        loss = C.c_double()
+        g = np.empty(self.nparam, np.float32) if want_grad else None
+        _check(lib().mlb_net_loss_grad(self.h, _tensor_ptr(x), _tensor_ptr(t), _tensor_ptr(mask),
+                                       float(mask_count), int(n), C.byref(loss),
+                                       None if g is None else g.ctypes.data_as(C.POINTER(C.c_float))),
+               "mlb_net_loss_grad")
+        return loss.value, g
+
+    def adamw(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        a = AdamWCfg(lr, beta1, beta2, eps, weight_decay)
+        _check(lib().mlb_net_adamw(self.h, C.byref(a)), "mlb_net_adamw")
+
+    def features(self, grid, x):
+        _check(lib().mlb_net_features(self.h, grid.h, _tensor_ptr(x)), "mlb_net_features")
+
+    def targets(self, grid, t):
+        _check(lib().mlb_net_targets(self.h, grid.h, _tensor_ptr(t)), "mlb_net_targets")
+
+    def infer(self, grid):
+        _check(lib().mlb_net_infer(self.h, grid.h), "mlb_net_infer")
+
+    def save(self, path):
+        _check(lib().mlb_net_save(self.h, path.encode()), "mlb_net_save")
+
+    def load(self, path):
+        _check(lib().mlb_net_load(self.h, path.encode()), "mlb_net_load")
+
+    def close(self):
+        if self.h:
+            _check(lib().mlb_net_destroy(self.h), "mlb_net_destroy")
+            self.h = None
