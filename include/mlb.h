@@ -221,7 +221,10 @@ mlb_status mlb_copy_probe(mlb_ctx* ctx, size_t bytes, int32_t reps, double* gbps
  * convolutions + ReLU (2x2 average pool between levels); per decoder level a
  * nearest x2 upsample, a 3x3 conv + ReLU, concatenation with the encoder
  * level's output, two 3x3 convs + ReLU; a 1x1 head to 3 channels.  The input
- * has in_ch channels (6 features, the rest zero).  Convolutions run on BF16
+ * has in_ch channels (6 features, the rest zero): normalised still-water
+ * depth, tau_x/rho, tau_y/rho, C_b, and the node position x, y mapped to
+ * [-1, 1] (the steady surface of a closed basin depends on where a node lies
+ * relative to the walls, which a finite receptive field cannot see).  Convolutions run on BF16
  * MFMA with FP32 accumulation; FP32 master parameters.  Parameters are ordered
  * layer by layer in forward order, each 3x3 weight [Cout][3][3][Cin] then its
  * bias; the head weight [3][base_ch] then its bias.
@@ -273,6 +276,58 @@ mlb_status mlb_net_targets(mlb_net* net, mlb_grid* g, float* t_dev);
 mlb_status mlb_net_infer(mlb_net* net, mlb_grid* g);
 mlb_status mlb_net_save(const mlb_net* net, const char* path);
 mlb_status mlb_net_load(mlb_net* net, const char* path);
+
+/* Training over a dataset resident in device memory: x [n][height][width][6],
+ * t [n][height][width][3], optional mask [n][height][width] (NULL = all ones).
+ * Each epoch visits the samples in a fresh random order (seeded) in
+ * minibatches of `batch` (the last, smaller one included); each minibatch is
+ * one mlb_net_loss_grad + one AdamW step.  Step size: linear ramp over
+ * warmup_steps, then cosine decay from lr to lr_min over the remaining steps.
+ * epoch_loss (host, may be NULL) receives the mean minibatch loss of each
+ * epoch.  The AdamW moments continue from earlier calls. */
+typedef struct {
+    int32_t epochs;
+    int32_t batch;           /* 1 .. max_batch                                         */
+    float lr, lr_min;
+    int32_t warmup_steps;
+    float beta1, beta2, eps, weight_decay;
+    uint64_t seed;
+} mlb_train_cfg;
+mlb_status mlb_net_train(mlb_net* net, const float* x_dev, const float* t_dev, const float* mask_dev, int32_t n,
+                         const mlb_train_cfg* cfg, double* epoch_loss);
+
+/* Warm-started steady-state run of a closed or open basin: the grid's current
+ * state is the cold start.  Steps:
+ *   1. one probe step from the cold start gives its first residual r0_cold;
+ *   2. mlb_net_infer writes the net's guess (mean surface removed, walls
+ *      q = 0); its first step gives r0_guess;
+ *   3. the run continues from the guess like mlb_run_steady, unless the guess
+ *      is non-finite, r0_guess > r0_cold, or the residual rose at 3
+ *      consecutive checks and exceeds its value at the first check (or a
+ *      non-finite value appears): then the cold start is restored (fields and
+ *      step counter) and run with mlb_run_steady;
+ *   4. on convergence, guess_err receives the relative L2 distance of the
+ *      guess to the converged state per field (eta, hu, hv).
+ * Returns MLB_OK when converged, else the status of the last run. */
+typedef enum {
+    MLB_WARM_NONE = 0,            /* the guess was used                              */
+    MLB_WARM_NONFINITE_GUESS = 1, /* non-finite or dry guess                         */
+    MLB_WARM_WORSE_THAN_COLD = 2, /* r0_guess > r0_cold                              */
+    MLB_WARM_DIVERGING = 3        /* residual rising or non-finite while running     */
+} mlb_warm_fallback;
+typedef struct {
+    int32_t used_guess;      /* 1: converged from the guess; 0: from the cold start     */
+    int32_t fallback;        /* mlb_warm_fallback                                       */
+    double r0_guess, r0_cold;
+    double infer_ms;         /* features + forward + projection (HIP events)            */
+    double wall_s;           /* the whole call, host clock                              */
+    int64_t steps;           /* steps of the run that converged                         */
+    int64_t steps_total;     /* all steps: probe, abandoned warm steps, final run       */
+    double guess_err[3];     /* relative L2 of the guess vs the converged state         */
+    mlb_diag_t diag;         /* diagnostics at the end                                  */
+} mlb_warm_report;
+mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* net, double tol, int64_t max_steps, int32_t check_every,
+                              mlb_warm_report* report);
 
 #ifdef __cplusplus
 }

@@ -307,6 +307,10 @@ mlb_status read_diag(mlb_ctx* c, Plan& P)
 
 }  // namespace
 
+namespace mlb {
+mlb_status grid_set_step(mlb_grid* g, int64_t s) { return set_step(g, s); }
+}  // namespace mlb
+
 // ====================================================================== C ABI
 extern "C" {
 

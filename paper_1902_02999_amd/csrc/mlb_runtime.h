@@ -12,6 +12,9 @@ namespace mlb {
 // Sets the calling thread's last error message and returns s.
 mlb_status fail(mlb_status s, const std::string& msg);
 
+// Sets a grid's step counter (host and device copies); syncs the stream.
+mlb_status grid_set_step(mlb_grid* g, int64_t s);
+
 }  // namespace mlb
 
 #define HIPCHK(call)                                                                        \

@@ -1,6 +1,8 @@
 // Host runtime of the warm-start network behind the mlb_net_* C ABI:
 // parameter layout, activation / gradient buffers, forward and backward
 // orchestration, AdamW, features / targets from grids, inference into a grid.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,6 +61,11 @@ struct mlb_net {
     double* lpart = nullptr;
     double* dloss = nullptr;
     float* xstage = nullptr;   // features of one grid
+    float* cold = nullptr;     // [3][h w] cold-start state (eta, qx, qy) of a warm-start run
+    float* guess = nullptr;    // [3][h w] the guess
+    float* fin = nullptr;      // [3][h w] the converged state
+    double* npart = nullptr;   // partials of the guess-error norms
+    double* nout = nullptr;    // [6] the guess-error sums
     std::vector<void*> allocs;
     size_t wpart_len = 0;
 
@@ -188,6 +195,12 @@ mlb_status build(mlb_net* n)
     CHK(dalloc(n, &n->lpart, (px(0) * c.out_ch + 255) / 256 + 1));
     CHK(dalloc(n, &n->dloss, 1));
     CHK(dalloc(n, &n->xstage, (size_t)c.height * c.width * 6));
+    const size_t hw = (size_t)c.height * c.width;
+    CHK(dalloc(n, &n->cold, 3 * hw));
+    CHK(dalloc(n, &n->guess, 3 * hw));
+    CHK(dalloc(n, &n->fin, 3 * hw));
+    CHK(dalloc(n, &n->npart, 3 * 256 * 2));
+    CHK(dalloc(n, &n->nout, 6));
     return MLB_OK;
 }
 
@@ -541,6 +554,206 @@ mlb_status mlb_net_load(mlb_net* n, const char* path)
     if (!ok) return fail(MLB_E_INVAL, "file is not a net of this architecture");
     CHK(mlb_net_set_params(n, th.data(), np));
     return mlb_net_set_norm(n, &nm);
+}
+
+mlb_status mlb_net_train(mlb_net* n, const float* x, const float* t, const float* mask, int32_t ns,
+                         const mlb_train_cfg* cfg, double* epoch_loss)
+{
+    if (!n || !x || !t || !cfg || ns < 1) return fail(MLB_E_INVAL, "bad training arguments");
+    const mlb_train_cfg& c = *cfg;
+    if (c.epochs < 1 || c.batch < 1 || c.batch > n->cfg.max_batch || !(c.lr > 0) || !(c.lr_min >= 0) ||
+        c.warmup_steps < 0 || !(c.beta1 >= 0 && c.beta1 < 1) || !(c.beta2 >= 0 && c.beta2 < 1) || !(c.eps > 0) ||
+        !(c.weight_decay >= 0))
+        return fail(MLB_E_INVAL, "bad training settings (batch must be 1..max_batch)");
+    HIPCHK(hipSetDevice(n->ctx->device));
+    hipStream_t s = n->ctx->stream;
+    const size_t hw = (size_t)n->cfg.height * n->cfg.width;
+    const size_t sx = hw * 6, st = hw * 3;
+    const int B = c.batch;
+    // staging of one minibatch, per-sample mask sums, per-epoch loss sums
+    float *xb = nullptr, *tb = nullptr, *mb = nullptr;
+    double *msum = nullptr, *eloss = nullptr;
+    struct Guard {
+        std::vector<void*> p;
+        ~Guard() { for (void* q : p) (void)hipFree(q); }
+    } guard;
+    HIPCHK(hipMalloc((void**)&xb, B * sx * sizeof(float))); guard.p.push_back(xb);
+    HIPCHK(hipMalloc((void**)&tb, B * st * sizeof(float))); guard.p.push_back(tb);
+    HIPCHK(hipMalloc((void**)&eloss, c.epochs * sizeof(double))); guard.p.push_back(eloss);
+    HIPCHK(hipMemsetAsync(eloss, 0, c.epochs * sizeof(double), s));
+    std::vector<double> hsum;
+    if (mask) {
+        HIPCHK(hipMalloc((void**)&mb, B * hw * sizeof(float))); guard.p.push_back(mb);
+        HIPCHK(hipMalloc((void**)&msum, ns * sizeof(double))); guard.p.push_back(msum);
+        HIPCHK(nn::sample_sums(mask, ns, (int64_t)hw, msum, s));
+        hsum.resize(ns);
+        HIPCHK(hipMemcpyAsync(hsum.data(), msum, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    const int per_epoch = (ns + B - 1) / B;
+    const int64_t total = (int64_t)per_epoch * c.epochs;
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    uint64_t rs = c.seed ^ 0x747261696e6d6c62ull;
+    int64_t it = 0;
+    for (int ep = 0; ep < c.epochs; ++ep) {
+        for (int i = ns - 1; i > 0; --i) {   // Fisher-Yates
+            const int j = (int)((uint64_t)splitmix(rs) % (uint64_t)(i + 1));
+            std::swap(order[i], order[j]);
+        }
+        for (int b0 = 0; b0 < ns; b0 += B, ++it) {
+            const int nb = std::min(B, ns - b0);
+            double cnt = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                const int idx = order[b0 + k];
+                HIPCHK(hipMemcpyAsync(xb + k * sx, x + (size_t)idx * sx, sx * sizeof(float), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(tb + k * st, t + (size_t)idx * st, st * sizeof(float), hipMemcpyDeviceToDevice, s));
+                if (mask) {
+                    HIPCHK(hipMemcpyAsync(mb + k * hw, mask + (size_t)idx * hw, hw * sizeof(float),
+                                          hipMemcpyDeviceToDevice, s));
+                    cnt += hsum[idx];
+                }
+            }
+            if (mask && !(cnt > 0)) continue;   // an all-dry minibatch carries no information
+            CHK(mlb_net_loss_grad(n, xb, tb, mask ? mb : nullptr, cnt, nb, nullptr, nullptr));
+            HIPCHK(nn::add_f64(n->dloss, eloss + ep, s));
+            double lr = c.lr;
+            if (it < c.warmup_steps) {
+                lr = c.lr * (double)(it + 1) / (double)c.warmup_steps;
+            } else {
+                const double span = (double)std::max<int64_t>(1, total - c.warmup_steps);
+                const double f = (double)(it - c.warmup_steps) / span;
+                lr = c.lr_min + 0.5 * (c.lr - c.lr_min) * (1.0 + std::cos(M_PI * f));
+            }
+            mlb_adamw_cfg a{(float)lr, c.beta1, c.beta2, c.eps, c.weight_decay};
+            CHK(mlb_net_adamw(n, &a));
+        }
+    }
+    std::vector<double> el(c.epochs);
+    HIPCHK(hipMemcpyAsync(el.data(), eloss, c.epochs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (epoch_loss)
+        for (int ep = 0; ep < c.epochs; ++ep) epoch_loss[ep] = el[ep] / per_epoch;
+    return MLB_OK;
+}
+
+namespace {
+
+mlb_status save_fields(mlb_net* n, mlb_grid* g, float* dst)
+{
+    const size_t hw = (size_t)n->cfg.height * n->cfg.width;
+    return mlb_get_state_device(g, dst, dst + hw, dst + 2 * hw, nullptr);
+}
+
+// One checked chunk of at most `steps` steps; NOTCONVERGED is not an error here.
+mlb_status probe(mlb_grid* g, double tol, int64_t steps, int32_t check_every, mlb_diag_t* d, bool* converged)
+{
+    const mlb_status st = mlb_run_steady(g, tol, steps, check_every, d);
+    *converged = st == MLB_OK;
+    if (st == MLB_E_NOTCONVERGED || st == MLB_OK || st == MLB_E_NONFINITE) return MLB_OK;
+    return st;
+}
+
+}  // namespace
+
+mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* n, double tol, int64_t max_steps, int32_t check_every,
+                              mlb_warm_report* rep)
+{
+    if (!n || !rep) return fail(MLB_E_INVAL, "NULL argument");
+    if (check_every < 1 || max_steps < 2 || !(tol >= 0)) return fail(MLB_E_INVAL, "bad tol / max_steps / check_every");
+    CHK(check_grid(n, g));
+    HIPCHK(hipSetDevice(n->ctx->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = n->ctx->stream;
+    *rep = mlb_warm_report{};
+    const int64_t step0 = g->step;
+    const size_t hw = (size_t)n->cfg.height * n->cfg.width;
+    bool conv = false;
+    mlb_diag_t d{};
+
+    // 1. cold-start probe
+    CHK(save_fields(n, g, n->cold));
+    CHK(probe(g, tol, 1, 1, &d, &conv));
+    rep->r0_cold = d.nonfinite ? INFINITY : d.residual;
+    rep->steps_total = 1;
+    if (conv) {   // the cold start is already steady: nothing to guess
+        rep->steps = 1;
+        rep->diag = d;
+        for (int k = 0; k < 3; ++k) rep->guess_err[k] = NAN;
+        rep->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return MLB_OK;
+    }
+
+    // 2. the guess and its first step
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(MLB_E_DEVICE, "hipEventCreate"); }
+    float ms = 0.f;
+    mlb_status ist = MLB_OK;
+    if (hipEventRecord(e0, s) != hipSuccess) ist = fail(MLB_E_DEVICE, "hipEventRecord");
+    if (ist == MLB_OK) ist = mlb_net_infer(n, g);
+    if (ist == MLB_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        ist = fail(MLB_E_DEVICE, "timing the inference");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHK(ist);
+    rep->infer_ms = ms;
+    CHK(grid_set_step(g, step0));
+    CHK(save_fields(n, g, n->guess));
+    CHK(probe(g, tol, 1, 1, &d, &conv));
+    rep->steps_total += 1;
+    rep->r0_guess = d.nonfinite ? INFINITY : d.residual;
+    int reason = MLB_WARM_NONE;
+    if (d.nonfinite || !std::isfinite(d.residual)) reason = MLB_WARM_NONFINITE_GUESS;
+    else if (rep->r0_guess > rep->r0_cold) reason = MLB_WARM_WORSE_THAN_COLD;
+
+    // 3. the warm run, watched for divergence
+    int64_t used = 1;
+    if (reason == MLB_WARM_NONE && !conv) {
+        double first = -1.0, prev = d.residual;
+        int rises = 0;
+        while (used < max_steps) {
+            const int64_t chunk = std::min<int64_t>(check_every, max_steps - used);
+            CHK(probe(g, tol, chunk, check_every, &d, &conv));
+            used += chunk;
+            rep->steps_total += chunk;
+            if (d.nonfinite) { reason = MLB_WARM_DIVERGING; break; }
+            if (conv) break;
+            if (first < 0) first = d.residual;
+            rises = d.residual > prev ? rises + 1 : 0;
+            prev = d.residual;
+            if (rises >= 3 && d.residual > first) { reason = MLB_WARM_DIVERGING; break; }
+        }
+    }
+    mlb_status result = MLB_OK;
+    if (reason == MLB_WARM_NONE) {
+        rep->used_guess = 1;
+        rep->steps = used;
+        if (!conv) result = fail(MLB_E_NOTCONVERGED, "max_steps reached");
+    } else {
+        // 4. fallback: the cold start again
+        CHK(mlb_set_state_device(g, n->cold, n->cold + hw, n->cold + 2 * hw));
+        CHK(grid_set_step(g, step0));
+        result = mlb_run_steady(g, tol, max_steps, check_every, &d);
+        rep->steps = g->step - step0;
+        rep->steps_total += rep->steps;
+        conv = result == MLB_OK;
+    }
+    rep->fallback = reason;
+    rep->diag = d;
+    for (int k = 0; k < 3; ++k) rep->guess_err[k] = NAN;
+    if (conv) {
+        CHK(save_fields(n, g, n->fin));
+        HIPCHK(nn::diff_norms3(n->guess, n->fin, (int64_t)hw, (int64_t)hw, n->npart, n->nout, s));
+        double o[6];
+        HIPCHK(hipMemcpyAsync(o, n->nout, sizeof(o), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < 3; ++k)
+            rep->guess_err[k] = o[2 * k + 1] > 0 ? std::sqrt(o[2 * k] / o[2 * k + 1]) : std::sqrt(o[2 * k]);
+    }
+    rep->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return result;
 }
 
 }  // extern "C"

@@ -62,6 +62,14 @@ hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, i
                    float s_q, float* out, hipStream_t s);
 // Guess from the net output [p][3]: eta = s_eta y0 - mean, q = s_q (y1, y2), q = 0 on
 // wall nodes; written into both state buffers (pitch ld).  mean over all nodes (FP64).
+// Per-sample sums of a [n][len] FP32 array in FP64 (one block per sample, fixed order).
+hipError_t sample_sums(const float* a, int n, int64_t len, double* out, hipStream_t s);
+// dst += *src (FP64, one thread).
+hipError_t add_f64(const double* src, double* dst, hipStream_t s);
+// For k = 0..2: out[2k] = sum (a_k - b_k)^2, out[2k+1] = sum b_k^2 over n
+// elements of the planes a + k stride, b + k stride (FP64, fixed order).
+hipError_t diff_norms3(const float* a, const float* b, int64_t n, int64_t stride, double* part, double* out,
+                       hipStream_t s);
 hipError_t guess_to_state(const float* y, int nx, int ny, int ld, float s_eta, float s_q, const int* wall4,
                           double* scratch, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
                           float* qy1, hipStream_t s);

@@ -532,8 +532,8 @@ __global__ void features_kernel(const float* __restrict__ H, int nx, int ny, int
     float* o = out + i * 6;
     o[0] = (H[(size_t)y * ld + x] - m0) / s0;
     o[1] = f1; o[2] = f2; o[3] = f3;
-    o[4] = 0.0f;      // inflow channel: closed basins
-    o[5] = 1.0f;      // wet mask
+    o[4] = nx > 1 ? 2.0f * (float)x / (float)(nx - 1) - 1.0f : 0.0f;   // node position in [-1, 1]
+    o[5] = ny > 1 ? 2.0f * (float)y / (float)(ny - 1) - 1.0f : 0.0f;
 }
 
 hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, float tx,
@@ -604,6 +604,87 @@ hipError_t guess_to_state(const float* y, int nx, int ny, int ld, float s_eta, f
     hipLaunchKernelGGL(guess_write_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, y, nx, ny,
                        ld, s_eta, s_q, wall4[0], wall4[1], wall4[2], wall4[3], scratch, eta0, qx0, qy0, eta1, qx1,
                        qy1);
+    return hipGetLastError();
+}
+
+__global__ void sample_sums_kernel(const float* __restrict__ a, int64_t len, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    const float* p = a + (int64_t)blockIdx.x * len;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += 256) s += (double)p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t sample_sums(const float* a, int n, int64_t len, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sample_sums_kernel, dim3(n), dim3(256), 0, s, a, len, out);
+    return hipGetLastError();
+}
+
+__global__ void add_f64_kernel(const double* __restrict__ src, double* __restrict__ dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += *src;
+}
+
+hipError_t add_f64(const double* src, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_f64_kernel, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+constexpr int kNormBlocks = 256;
+
+// part[k][block][2]: partial sums of (a - b)^2 and b^2 over a grid-stride range.
+__global__ void diff_norms_partial_kernel(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
+                                          int64_t stride, double* __restrict__ part)
+{
+    __shared__ double r0[256], r1[256];
+    const int k = blockIdx.y;
+    const float* pa = a + k * stride;
+    const float* pb = b + k * stride;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double d = (double)pa[i] - (double)pb[i];
+        s0 += d * d;
+        s1 += (double)pb[i] * (double)pb[i];
+    }
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+        if ((int)threadIdx.x < m) {
+            r0[threadIdx.x] += r0[threadIdx.x + m];
+            r1[threadIdx.x] += r1[threadIdx.x + m];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[((size_t)k * gridDim.x + blockIdx.x) * 2 + 0] = r0[0];
+        part[((size_t)k * gridDim.x + blockIdx.x) * 2 + 1] = r1[0];
+    }
+}
+
+__global__ void diff_norms_final_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out)
+{
+    const int j = threadIdx.x;   // 0..5: field k = j / 2, sum j % 2
+    if (j >= 6) return;
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[((size_t)(j / 2) * nblk + i) * 2 + (j % 2)];
+    out[j] = s;
+}
+
+hipError_t diff_norms3(const float* a, const float* b, int64_t n, int64_t stride, double* part, double* out,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(diff_norms_partial_kernel, dim3(kNormBlocks, 3), dim3(256), 0, s, a, b, n, stride, part);
+    hipLaunchKernelGGL(diff_norms_final_kernel, dim3(1), dim3(64), 0, s, part, kNormBlocks, out);
     return hipGetLastError();
 }
 

@@ -70,6 +70,27 @@ class AdamWCfg(C.Structure):
                 ("weight_decay", C.c_float)]
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("lr_min", C.c_float),
+                ("warmup_steps", C.c_int32), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float), ("seed", C.c_uint64)]
+
+
+class WarmReport(C.Structure):
+    _fields_ = [("used_guess", C.c_int32), ("fallback", C.c_int32), ("r0_guess", C.c_double),
+                ("r0_cold", C.c_double), ("infer_ms", C.c_double), ("wall_s", C.c_double),
+                ("steps", C.c_int64), ("steps_total", C.c_int64), ("guess_err", C.c_double * 3),
+                ("diag", Diag)]
+
+    def as_dict(self) -> dict:
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("guess_err", "diag")}
+        out["guess_err"] = list(self.guess_err)
+        out["diag"] = self.diag.as_dict()
+        return out
+
+
+WARM_NONE, WARM_NONFINITE_GUESS, WARM_WORSE_THAN_COLD, WARM_DIVERGING = 0, 1, 2, 3
+
 # Every exported symbol of include/mlb.h with its ctypes signature.
 _VP = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -121,6 +142,8 @@ SIGNATURES = {
     "mlb_net_infer": (C.c_int, [_VP, _VP]),
     "mlb_net_save": (C.c_int, [_VP, C.c_char_p]),
     "mlb_net_load": (C.c_int, [_VP, C.c_char_p]),
+    "mlb_net_train": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(TrainCfg), _DP]),
+    "mlb_warm_start_run": (C.c_int, [_VP, _VP, C.c_double, C.c_int64, C.c_int32, C.POINTER(WarmReport)]),
 }
 
 _lib = None
@@ -441,6 +464,26 @@ class Net:
 
     def infer(self, grid):
         _check(lib().mlb_net_infer(self.h, grid.h), "mlb_net_infer")
+
+    def train(self, x, t, n, epochs, batch, lr, lr_min=0.0, warmup_steps=0, beta1=0.9, beta2=0.999,
+              eps=1e-8, weight_decay=0.0, seed=0, mask=None):
+        """AdamW training over device-resident samples; returns the per-epoch mean loss."""
+        cfg = TrainCfg(int(epochs), int(batch), lr, lr_min, int(warmup_steps), beta1, beta2, eps,
+                       weight_decay, int(seed))
+        el = np.zeros(int(epochs))
+        _check(lib().mlb_net_train(self.h, _tensor_ptr(x), _tensor_ptr(t), _tensor_ptr(mask), int(n),
+                                   C.byref(cfg), _dptr(el)), "mlb_net_train")
+        return el
+
+    def warm_start_run(self, grid, tol, max_steps, check_every=100):
+        """Returns (converged, report dict); raises on errors other than
+        MLB_E_NOTCONVERGED."""
+        r = WarmReport()
+        rc = lib().mlb_warm_start_run(grid.h, self.h, tol, int(max_steps), int(check_every), C.byref(r))
+        if rc == -7:
+            return False, r.as_dict()
+        _check(rc, "mlb_warm_start_run")
+        return True, r.as_dict()
 
     def save(self, path):
         _check(lib().mlb_net_save(self.h, path.encode()), "mlb_net_save")

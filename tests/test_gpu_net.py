@@ -251,7 +251,9 @@ def test_features_targets_infer(ctx):
     for k, f in ((1, tx), (2, ty), (3, cb)):
         assert abs(xf[0, 0, k] - (f - mean[k]) / std[k]) <= 1e-5 * (abs(f / std[k]) + 1), k
         assert np.all(xf[..., k] == xf[0, 0, k])
-    assert np.all(xf[..., 4] == 0.0) and np.all(xf[..., 5] == 1.0)
+    lin = np.linspace(-1.0, 1.0, 64)
+    assert np.abs(xf[..., 4] - lin[None, :]).max() <= 1e-6
+    assert np.abs(xf[..., 5] - lin[:, None]).max() <= 1e-6
 
     # targets of a seeded state
     h0, qx0, qy0 = wl.seeded_state(spec, 3)
