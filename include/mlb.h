@@ -169,7 +169,9 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
  * step workgroups per compute unit (fewer concurrent row streams). */
 typedef struct {
     int32_t tile_rows;     /* output rows per wave tile, 4..4096                          */
-    int32_t tblock;        /* sub-steps per kernel pass: 1                                */
+    int32_t tblock;        /* steps per kernel pass: 1, or 2 (temporal blocking: the first
+                            * step's level stays in registers; a call's last step is
+                            * always a one-step pass)                                     */
     int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
     int32_t graph_chunk;   /* steps per captured graph, 2..100000                         */
     int32_t blocks_per_cu; /* 0: no cap; 1..8: at most this many step workgroups per CU   */
@@ -177,14 +179,15 @@ typedef struct {
 mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
 mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
 
-/* Autotuner: times the step for every (tile_rows, blocks_per_cu) pair of a
- * fixed candidate set (tile rows 6..45 x caps 0, 2..5) with HIP events (median of 3 runs of `steps` steps),
- * applies the fastest and returns it in *best (may be NULL).  The grid's
- * state and step counter are restored afterwards (results are bitwise
- * independent of these options).  cache_path (may be NULL): a text file of
- * "key tile_rows blocks_per_cu us" lines; a matching key is applied without
- * timing, a new result is appended.  The key holds the device name and the
- * grid shape. */
+/* Autotuner: times the step for every (tblock, tile_rows, blocks_per_cu)
+ * triple of a fixed candidate set (tblock 1, 2 x tile rows 6..45 x caps 0,
+ * 2..5) with HIP events (median of 3 runs of `steps` steps), applies the
+ * fastest and returns it in *best (may be NULL).  The grid's state and step
+ * counter are restored afterwards (results are bitwise independent of these
+ * options).  cache_path (may be NULL): a text file of
+ * "key tile_rows blocks_per_cu tblock us" lines; a matching key is applied
+ * without timing, a new result is appended.  The key holds the device name
+ * and the grid shape. */
 mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_exec_opts* best);
 
 /* Batches: many grids advanced together by one kernel launch per step over a

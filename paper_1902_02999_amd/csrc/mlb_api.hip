@@ -76,21 +76,25 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     return b;
 }
 
-// Wave tiles of one basin: strips of 62 output columns, tiles of `rows` rows.
-// The last strip / tile is shifted inward so that edge extrapolation always
-// finds its inner nodes in the same tile; it then stores only what it owns.
-void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out)
+// Wave tiles of one basin: strips of `strip` output columns (62 for one step
+// per pass, 60 for two), tiles of `rows` rows.  The last strip / tile is
+// shifted inward so that edge extrapolation always finds its inner nodes in
+// the same tile; it then stores only what it owns.  Two-step tiles never
+// start at row 1: their first stage would then compute row 0 of an open S
+// edge, which waits for rows 1 and 2 (such a tile starts at row 0 instead).
+void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out, int strip)
 {
     const int nx = g->p.nx, ny = g->p.ny;
     const int ty = std::max(4, rows);
     for (int yo = 0; yo < ny; yo += ty) {
-        const int y0 = std::min(yo, std::max(0, ny - ty));
+        int y0 = std::min(yo, std::max(0, ny - ty));
+        if (strip == kStripOut2 && y0 == 1) y0 = 0;
         const int yend = std::min(yo + ty, ny);
-        for (int xo = 0; xo < nx; xo += kStripOut) {
+        for (int xo = 0; xo < nx; xo += strip) {
             TileDev t{};
             t.basin = basin;
             t.xo = xo;
-            t.x0 = std::min(xo, std::max(0, nx - kStripOut));
+            t.x0 = std::min(xo, std::max(0, nx - strip));
             t.yo = yo;
             t.y0 = y0;
             t.rows = yend - y0;
@@ -114,6 +118,11 @@ mlb_status plan_alloc(mlb_ctx* c, Plan& P)
     HIPCHK(hipMalloc(&P.dout, nb * 8 * sizeof(double)));
     HIPCHK(hipHostMalloc(&P.hout, nb * 8 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipMemcpyAsync(P.dt, P.ht.data(), nt * sizeof(TileDev), hipMemcpyHostToDevice, c->stream));
+    if (!P.ht2.empty()) {
+        HIPCHK(hipMalloc(&P.dt2, P.ht2.size() * sizeof(TileDev)));
+        HIPCHK(hipMemcpyAsync(P.dt2, P.ht2.data(), P.ht2.size() * sizeof(TileDev), hipMemcpyHostToDevice,
+                              c->stream));
+    }
     HIPCHK(hipMemcpyAsync(P.db, P.hb.data(), nb * sizeof(BasinDev), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     P.built = true;
@@ -137,9 +146,13 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.hb.assign(1, make_basin(g, g->cur));
         g->plan.parity = 0;
         g->plan.ht.clear();
-        make_tiles(g, 0, g->opts.tile_rows, g->plan.ht);
+        g->plan.ht2.clear();
+        make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
+        if (g->opts.tblock == 2) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
+        g->plan.hb[0].first_tile2 = 0;
+        g->plan.hb[0].ntiles2 = (int)g->plan.ht2.size();
         CHK(plan_alloc(c, g->plan));
         g->stale_plan = false;
         g->dirty = false;
@@ -147,6 +160,8 @@ mlb_status grid_plan(mlb_grid* g)
         BasinDev b = make_basin(g, g->plan.parity ^ g->cur);
         b.first_tile = 0;
         b.ntiles = (int)g->plan.ht.size();
+        b.first_tile2 = 0;
+        b.ntiles2 = (int)g->plan.ht2.size();
         g->plan.hb[0] = b;
         CHK(upload_basins(c, g->plan));
         g->dirty = false;
@@ -166,26 +181,44 @@ unsigned dyn_lds_for(const mlb_ctx* c, const mlb_exec_opts& o)
     return (unsigned)(o.blocks_per_cu + 1) * per > (unsigned)c->lds_per_cu ? per : 0u;
 }
 
-mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n, bool diag_last)
+mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n, bool diag_last,
+                         int64_t* launches)
 {
-    const int ntiles = (int)P.ht.size();
+    const int nt1 = (int)P.ht.size(), nt2 = (int)P.ht2.size();
     const unsigned dyn = dyn_lds_for(c, o);
-    auto eager = [&](bool diag) -> mlb_status {
-        HIPCHK(launch_step(P.db, P.dt, ntiles, P.parity, P.dpart, diag ? 1 : 0, 1, dyn, c->stream));
+    // Two steps per launch when the plan has the two-step tiles; the last step
+    // of a call is always a single one, so the buffer left behind holds the
+    // level before the last (the residual of mlb_diag compares the two).
+    const int kind = (o.tblock == 2 && P.dt2) ? 2 : 1;
+    int64_t nl = 0;
+    auto eager = [&](int k, bool diag) -> mlb_status {
+        HIPCHK(launch_step(P.db, k == 2 ? P.dt2 : P.dt, k == 2 ? nt2 : nt1, P.parity, P.dpart, diag ? 1 : 0, k,
+                           dyn, c->stream));
         P.parity ^= 1;
+        ++nl;
         return MLB_OK;
     };
-    int64_t plain = diag_last ? n - 1 : n;
-    const int chunk = std::max(2, o.graph_chunk & ~1);
-    if (o.use_graph && plain >= chunk) {
-        if (!P.gexec || P.gsteps != chunk || P.gdyn != dyn) {
+    // launches of `kind` before the closing single steps
+    int64_t multi = 0, singles = n;
+    if (kind == 2 && n >= 2) {
+        multi = (n - 1) / 2;
+        singles = n - 2 * multi;
+    } else if (kind == 1) {
+        multi = diag_last ? n - 1 : n;
+        singles = n - multi;
+    }
+    // graphs hold an even number of launches, so the parity they start from recurs
+    const int glaunch = kind == 2 ? std::max(2, (o.graph_chunk / 2) & ~1) : std::max(2, o.graph_chunk & ~1);
+    if (o.use_graph && multi >= glaunch) {
+        if (!P.gexec || P.gsteps != glaunch || P.gkind != kind || P.gdyn != dyn) {
             if (P.gexec) { (void)hipGraphExecDestroy(P.gexec); P.gexec = nullptr; }
             if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             int par = P.parity;
             hipError_t le = hipSuccess;
-            for (int i = 0; i < chunk && le == hipSuccess; ++i) {
-                le = launch_step(P.db, P.dt, ntiles, par, P.dpart, 0, 1, dyn, c->stream);
+            for (int i = 0; i < glaunch && le == hipSuccess; ++i) {
+                le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind, dyn,
+                                 c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -194,21 +227,24 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             if (ee != hipSuccess) return fail(MLB_E_DEVICE, std::string("end capture: ") + hipGetErrorString(ee));
             P.graph = gr;
             HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
-            P.gsteps = chunk;
+            P.gsteps = glaunch;
+            P.gkind = kind;
             P.gparity = P.parity;
             P.gdyn = dyn;
         }
         if (P.parity != P.gparity) {
-            CHK(eager(false));
-            --plain;
+            CHK(eager(kind, false));
+            --multi;
         }
-        while (plain >= chunk) {
+        while (multi >= glaunch) {
             HIPCHK(hipGraphLaunch(P.gexec, c->stream));
-            plain -= chunk;
+            multi -= glaunch;
+            nl += glaunch;
         }
     }
-    for (int64_t i = 0; i < plain; ++i) CHK(eager(false));
-    if (diag_last && n >= 1) CHK(eager(true));
+    for (int64_t i = 0; i < multi; ++i) CHK(eager(kind, false));
+    for (int64_t i = 0; i < singles; ++i) CHK(eager(1, diag_last && i == singles - 1));
+    if (launches) *launches = nl;
     return MLB_OK;
 }
 
@@ -587,7 +623,7 @@ static mlb_status check_opts(const mlb_exec_opts* o)
 {
     if (!o) return fail(MLB_E_INVAL, "opts is NULL");
     if (o->tile_rows < 4 || o->tile_rows > 4096) return fail(MLB_E_INVAL, "tile_rows out of range");
-    if (o->tblock != 1) return fail(MLB_E_INVAL, "tblock must be 1");
+    if (o->tblock != 1 && o->tblock != 2) return fail(MLB_E_INVAL, "tblock must be 1 or 2");
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 8) return fail(MLB_E_INVAL, "blocks_per_cu must be 0..8");
     if (o->use_graph && (o->graph_chunk < 2 || o->graph_chunk > 100000))
         return fail(MLB_E_INVAL, "graph_chunk out of range");
@@ -598,19 +634,16 @@ mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o)
 {
     if (!g) return fail(MLB_E_INVAL, "grid is NULL");
     CHK(check_opts(o));
-    if (o->tile_rows != g->opts.tile_rows) g->stale_plan = true;
+    if (o->tile_rows != g->opts.tile_rows || o->tblock != g->opts.tblock) g->stale_plan = true;
     g->opts = *o;
-    if (g->plan.gexec && g->plan.gsteps != (o->graph_chunk & ~1)) {
-        (void)hipGraphExecDestroy(g->plan.gexec); g->plan.gexec = nullptr;
-        (void)hipGraphDestroy(g->plan.graph); g->plan.graph = nullptr;
-    }
     return MLB_OK;
 }
 
-static void advance_grid(mlb_grid* g, int64_t n)
+// n steps in `launches` launches: each launch swaps the buffers once
+static void advance_grid(mlb_grid* g, int64_t n, int64_t launches)
 {
     g->step += n;
-    if (n & 1) g->cur ^= 1;
+    if (launches & 1) g->cur ^= 1;
 }
 
 mlb_status mlb_step(mlb_grid* g, int64_t n)
@@ -622,10 +655,11 @@ mlb_status mlb_step(mlb_grid* g, int64_t n)
     CHK(grid_plan(g));
     mlb_ctx* c = g->ctx;
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    CHK(enqueue_steps(c, g->plan, g->opts, n, false));
+    int64_t nl = 0;
+    CHK(enqueue_steps(c, g->plan, g->opts, n, false, &nl));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
-    advance_grid(g, n);
+    advance_grid(g, n, nl);
     return MLB_OK;
 }
 
@@ -653,8 +687,9 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
     mlb_diag_t d{};
     while (g->step - start < max_steps) {
         const int64_t n = std::min<int64_t>(check_every, max_steps - (g->step - start));
-        CHK(enqueue_steps(c, g->plan, g->opts, n, true));
-        advance_grid(g, n);
+        int64_t nl = 0;
+        CHK(enqueue_steps(c, g->plan, g->opts, n, true, &nl));
+        advance_grid(g, n, nl);
         CHK(read_diag(c, g->plan));
         fill_diag(g, g->plan.hout, &d);
         if (out) *out = d;
@@ -714,14 +749,18 @@ static mlb_status batch_plan(mlb_batch* b)
     });
     b->plan.hb.assign(n, BasinDev{});
     b->plan.ht.clear();
+    b->plan.ht2.clear();
     b->plan.parity = 0;
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
         mlb_grid* g = b->grids[i];
         BasinDev d = make_basin(g, g->cur);
         d.first_tile = (int)b->plan.ht.size();
-        make_tiles(g, i, b->opts.tile_rows, b->plan.ht);
+        make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
+        d.first_tile2 = (int)b->plan.ht2.size();
+        if (b->opts.tblock == 2) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
+        d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
     }
     CHK(plan_alloc(b->ctx, b->plan));
@@ -758,15 +797,11 @@ mlb_status mlb_batch_set_exec_opts(mlb_batch* b, const mlb_exec_opts* o)
 {
     if (!b) return fail(MLB_E_INVAL, "batch is NULL");
     CHK(check_opts(o));
-    if (o->tile_rows != b->opts.tile_rows) {
+    if (o->tile_rows != b->opts.tile_rows || o->tblock != b->opts.tblock) {
         // rebuild with the current buffers as the starting parity
         b->stale_plan = true;
     }
     b->opts = *o;
-    if (b->plan.gexec && b->plan.gsteps != (o->graph_chunk & ~1)) {
-        (void)hipGraphExecDestroy(b->plan.gexec); b->plan.gexec = nullptr;
-        (void)hipGraphDestroy(b->plan.graph); b->plan.graph = nullptr;
-    }
     return MLB_OK;
 }
 
@@ -779,10 +814,11 @@ mlb_status mlb_batch_step(mlb_batch* b, int64_t n)
     CHK(batch_plan(b));
     mlb_ctx* c = b->ctx;
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    CHK(enqueue_steps(c, b->plan, b->opts, n, false));
+    int64_t nl = 0;
+    CHK(enqueue_steps(c, b->plan, b->opts, n, false, &nl));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
-    for (auto* g : b->grids) advance_grid(g, n);
+    for (auto* g : b->grids) advance_grid(g, n, nl);
     return MLB_OK;
 }
 
@@ -798,8 +834,9 @@ mlb_status mlb_batch_run_steady(mlb_batch* b, double tol, int64_t max_steps, int
     const int n = (int)b->grids.size();
     while (done < max_steps) {
         const int64_t k = std::min<int64_t>(check_every, max_steps - done);
-        CHK(enqueue_steps(c, b->plan, b->opts, k, true));
-        for (auto* g : b->grids) advance_grid(g, k);
+        int64_t nl = 0;
+        CHK(enqueue_steps(c, b->plan, b->opts, k, true, &nl));
+        for (auto* g : b->grids) advance_grid(g, k, nl);
         done += k;
         CHK(read_diag(c, b->plan));
         bool all = true, bad = false;
@@ -838,6 +875,7 @@ namespace {
 
 const int kTuneRows[] = {6, 9, 12, 15, 21, 27, 33, 45};
 const int kTuneCaps[] = {0, 2, 3, 4, 5};
+const int kTuneBlocks[] = {1, 2};
 
 // Device copies of the current fields of some grids, to restore after tuning.
 struct Saved {
@@ -882,11 +920,11 @@ bool cache_lookup(const char* path, const std::string& key, mlb_exec_opts* o)
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char k[256];
-    int tr = 0, bc = 0;
+    int tr = 0, bc = 0, tb = 1;
     double us = 0;
     bool hit = false;
-    while (std::fscanf(f, "%255s %d %d %lf", k, &tr, &bc, &us) == 4)
-        if (key == k) { o->tile_rows = tr; o->blocks_per_cu = bc; hit = true; }
+    while (std::fscanf(f, "%255s %d %d %d %lf", k, &tr, &bc, &tb, &us) == 5)
+        if (key == k) { o->tile_rows = tr; o->blocks_per_cu = bc; o->tblock = tb; hit = true; }
     std::fclose(f);
     return hit;
 }
@@ -896,7 +934,7 @@ void cache_store(const char* path, const std::string& key, const mlb_exec_opts& 
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %.3f\n", key.c_str(), o.tile_rows, o.blocks_per_cu, us);
+    std::fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), o.tile_rows, o.blocks_per_cu, o.tblock, us);
     std::fclose(f);
 }
 
@@ -910,9 +948,11 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
+    for (int tb : kTuneBlocks)
     for (int tr : kTuneRows)
         for (int cap : kTuneCaps) {
             mlb_exec_opts o = base;
+            o.tblock = tb;
             o.tile_rows = tr;
             o.blocks_per_cu = cap;
             o.use_graph = 1;
@@ -920,16 +960,17 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
             *opts = o;
             Plan* P = nullptr;
             CHK(prepare(o, &P));
-            CHK(enqueue_steps(c, *P, o, n, false));  // capture + warm-up
-            for (auto* g : gs) advance_grid(g, n);
+            int64_t nl = 0;
+            CHK(enqueue_steps(c, *P, o, n, false, &nl));  // capture + warm-up
+            for (auto* g : gs) advance_grid(g, n, nl);
             float ms[3];
             for (int rep = 0; rep < 3; ++rep) {
                 HIPCHK(hipEventRecord(c->ev0, c->stream));
-                CHK(enqueue_steps(c, *P, o, n, false));
+                CHK(enqueue_steps(c, *P, o, n, false, &nl));
                 HIPCHK(hipEventRecord(c->ev1, c->stream));
                 HIPCHK(hipEventSynchronize(c->ev1));
                 HIPCHK(hipEventElapsedTime(&ms[rep], c->ev0, c->ev1));
-                for (auto* g : gs) advance_grid(g, n);
+                for (auto* g : gs) advance_grid(g, n, nl);
             }
             std::sort(ms, ms + 3);
             const double us = 1e3 * ms[1] / n;
@@ -966,7 +1007,7 @@ mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_
     double us = 0;
     if (st == MLB_OK)
         st = tune(c, &o, steps, gs, [&](const mlb_exec_opts& oo, Plan** P) -> mlb_status {
-            if (oo.tile_rows != g->opts.tile_rows) g->stale_plan = true;
+            if (oo.tile_rows != g->opts.tile_rows || oo.tblock != g->opts.tblock) g->stale_plan = true;
             g->opts = oo;
             CHK(grid_plan(g));
             *P = &g->plan;
@@ -1004,7 +1045,7 @@ mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_pat
     double us = 0;
     if (st == MLB_OK)
         st = tune(c, &o, steps, b->grids, [&](const mlb_exec_opts& oo, Plan** P) -> mlb_status {
-            if (oo.tile_rows != b->opts.tile_rows) b->stale_plan = true;
+            if (oo.tile_rows != b->opts.tile_rows || oo.tblock != b->opts.tblock) b->stale_plan = true;
             b->opts = oo;
             CHK(batch_plan(b));
             *P = &b->plan;

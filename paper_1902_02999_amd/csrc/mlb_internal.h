@@ -9,6 +9,8 @@ namespace mlb {
 // Output columns per wave strip: a wave's 64 lanes cover columns x0-1 .. x0+62;
 // lanes 1..62 produce outputs, lanes 0 and 63 only supply neighbour values.
 constexpr int kStripOut = 62;
+// Two steps per pass: lanes 0..63 cover x0-2 .. x0+61, lanes 2..61 produce outputs.
+constexpr int kStripOut2 = 60;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;            // 4 independent waves per workgroup
 constexpr int kPartials = 6;           // per-tile FP64 partial sums
@@ -27,7 +29,8 @@ struct BasinDev {
     int32_t per_x, per_y;
     int32_t kind[4];       // W, E, S, N
     int32_t extrap;        // 1 or 2
-    int32_t first_tile, ntiles;
+    int32_t first_tile, ntiles;     // in the one-step tile list
+    int32_t first_tile2, ntiles2;   // in the two-step tile list
     // FP32 constants of the step (computed in FP64 on the host, then rounded)
     float e;               // lattice speed
     float tpx, tpy;        // (dt/2) tau_w / rho
@@ -52,6 +55,8 @@ struct TileDev {
 };
 
 // Host-side launchers (mlb_kernels.hip).
+// tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
+// of kStripOut2 columns, no diag.
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
                        double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s);
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,

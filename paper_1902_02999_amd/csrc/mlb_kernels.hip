@@ -18,13 +18,21 @@
 //     eta' = eta + sum_a Out_a(y_a) - kk + g/(2e^2) sum_a C_a P_a
 //     q'   = (dt/2) F(x) + e sum_a e^_a Out_a(y_a) + g/(2e) sum_a C_a e^_a P_a
 //   where P_a = (h_x + h_y)(eta_y - eta_x).
+//   The sums are formed from partial sums in one fixed association order
+//   (per neighbour row, see Row), so every code path gives the same bits.
 //
-// Execution: each wave walks a strip of 62 output columns down a tile of rows
-// (a column per lane, lanes 0 and 63 are the halo).  Per row it loads
-// eta, qx, qy, H once (coalesced SoA rows), derives the node quantities once,
-// and passes the ones its neighbours need across lanes with DPP wave shifts;
-// a three-row register window gives the 8-neighbour gather.  One wave per
-// tile; the tile list holds the largest basins first.
+// Execution: each wave walks a strip of columns down a tile of rows (a column
+// per lane).  Per row it loads eta, qx, qy, H once (coalesced SoA rows),
+// derives the node quantities once, and passes what its neighbours need
+// across lanes with DPP wave shifts; a three-row register window gives the
+// 8-neighbour gather.  One wave per tile; the tile list holds the largest
+// basins first.
+//   One step per pass: lanes 0 and 63 are the halo, 62 output columns.
+//   Two steps per pass (temporal blocking): a first stage computes time level
+//   n+1 for lanes 0..63 and hands each finished row, in registers, to a
+//   second stage three rows behind it that computes level n+2; only lanes
+//   2..61 (60 columns) are valid after two steps.  HBM traffic per step is
+//   halved; level n+1 never leaves the registers.
 #include "mlb_internal.h"
 
 // Build-time knob (results are bitwise independent of it):
@@ -53,24 +61,32 @@ typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) double gdouble;
 
 // ------------------------------------------------------------------ node arithmetic
-struct Derived {
+struct Node {
     float eta, h, kk, fpx, fpy;
     float o[9];            // o[a] = Out_a(node), a = 1..8
     float H, q0x, q0y;     // the node's stored H and old discharge
 };
 
 // Node quantities from the old state (Eqs. SWE-force, bed-stress, feq-full).
-__device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, float qy, float H,
-                                       Derived& d)
+// FRIC false: no bed friction (C_b = 0); the friction term is then exactly
+// zero for finite states and is not evaluated.
+template <bool FRIC>
+__device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, float qy, float H, Node& d)
 {
     const float h = H + eta;
     const float r = __builtin_amdgcn_rcpf(h);
     const float u = qx * r, v = qy * r;
-    const float s = __builtin_amdgcn_sqrtf(__builtin_fmaf(u, u, v * v));
-    const float fr = B.cfr * s;
     // (dt/2) F = (dt/2) [tau_w/rho - C_b u |u| + Omega (qy, -qx)]
-    const float fpx = __builtin_fmaf(B.omh, qy, __builtin_fmaf(-fr, u, B.tpx));
-    const float fpy = __builtin_fmaf(-B.omh, qx, __builtin_fmaf(-fr, v, B.tpy));
+    float fpx, fpy;
+    if (FRIC) {
+        const float s = __builtin_amdgcn_sqrtf(__builtin_fmaf(u, u, v * v));
+        const float fr = B.cfr * s;
+        fpx = __builtin_fmaf(B.omh, qy, __builtin_fmaf(-fr, u, B.tpx));
+        fpy = __builtin_fmaf(-B.omh, qx, __builtin_fmaf(-fr, v, B.tpy));
+    } else {
+        fpx = __builtin_fmaf(B.omh, qy, B.tpx);
+        fpy = __builtin_fmaf(-B.omh, qx, B.tpy);
+    }
     const float tqx = qx + fpx, tqy = qy + fpy;
     const float pxx = qx * u, pyy = qy * v, pxy = qx * v;
     const float kq = pxx + pyy;
@@ -89,25 +105,6 @@ __device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, f
     d.H = H; d.q0x = qx; d.q0y = qy;
 }
 
-// Eqs. Mac.lb.6 / Mac.lb.7 in increment form from the gathered neighbour
-// equilibria oy[a] = Out_a(y_a) and link products P[a] = (h_x + h_y)(eta_y - eta_x).
-__device__ __forceinline__ void update(const BasinDev& B, const Derived& x, const float* P,
-                                       const float* oy, float& eta_n, float& qx_n, float& qy_n)
-{
-    const float so = ((oy[1] + oy[2]) + (oy[3] + oy[4])) + ((oy[5] + oy[6]) + (oy[7] + oy[8]));
-    const float pa = (P[1] + P[3]) + (P[5] + P[7]);
-    const float pd = (P[2] + P[4]) + (P[6] + P[8]);
-    const float mp = __builtin_fmaf(B.cma, pa, B.cmd * pd);
-    eta_n = x.eta + ((so - x.kk) + mp);
-    const float o26 = oy[2] - oy[6], p26 = P[2] - P[6];
-    const float mxo = (oy[1] - oy[5]) + (o26 + (oy[8] - oy[4]));
-    const float myo = (oy[3] - oy[7]) + (o26 + (oy[4] - oy[8]));
-    const float pxm = __builtin_fmaf(B.cqa, P[1] - P[5], B.cqd * (p26 + (P[8] - P[4])));
-    const float pym = __builtin_fmaf(B.cqa, P[3] - P[7], B.cqd * (p26 + (P[4] - P[8])));
-    qx_n = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
-    qy_n = x.fpy + __builtin_fmaf(B.e, myo, pym);
-}
-
 // Link product of node x with neighbour y: (h_x + h_y)(eta_y - eta_x).  The
 // same link seen from y is exactly its negative, so each node computes its
 // E, N, NE and NW links and takes the other four from its neighbours.
@@ -116,28 +113,114 @@ __device__ __forceinline__ float link(float hx, float ex, float hy, float ey)
     return (hx + hy) * (ey - ex);
 }
 
-// What one row of the window keeps: own values and the neighbours' values
-// received across lanes.
+// What one row of the window passes on: own depth and surface, the lane
+// neighbours' (for the links), and the partial sums of the particles it sends
+// to other rows, in the fixed order the update uses:
+//   to the row above  S1 = (o2(x-1) + o3(x)) + o4(x+1),  S2 = o2(x-1) - o4(x+1)
+//   to the row below  N1 = (o6(x+1) + o7(x)) + o8(x-1),  N2 = o8(x-1) - o6(x+1)
+//   along the row     E1 = o1(x-1) + o5(x+1),            E2 = o1(x-1) - o5(x+1)
+// Edge tiles keep the individual particles instead (bounced links replace
+// some of them) and form the same sums at the receiving node.
 struct Row {
-    float eta, h, o3, o7;          // own
-    float el, hl, o1l, o2l, o8l;   // from the lane on the left  (x - 1)
-    float er, hr, o4r, o5r, o6r;   // from the lane on the right (x + 1)
+    float eta, h, el, hl, er, hr;
+    float S1, S2, N1, N2, E1, E2;
+    float o1l, o5r, o2l, o3, o4r, o6r, o7, o8l;
 };
 
-__device__ __forceinline__ void exchange(const Derived& d, Row& R)
+template <bool EDGE>
+__device__ __forceinline__ void exchange(const Node& d, Row& R)
 {
-    R.eta = d.eta; R.h = d.h; R.o3 = d.o[3]; R.o7 = d.o[7];
-    R.el = from_left(d.eta);   R.hl = from_left(d.h);
-    R.o1l = from_left(d.o[1]); R.o2l = from_left(d.o[2]); R.o8l = from_left(d.o[8]);
-    R.er = from_right(d.eta);  R.hr = from_right(d.h);
-    R.o4r = from_right(d.o[4]); R.o5r = from_right(d.o[5]); R.o6r = from_right(d.o[6]);
+    R.eta = d.eta; R.h = d.h;
+    R.el = from_left(d.eta);  R.hl = from_left(d.h);
+    R.er = from_right(d.eta); R.hr = from_right(d.h);
+    const float o1l = from_left(d.o[1]), o5r = from_right(d.o[5]);
+    const float o2l = from_left(d.o[2]), o4r = from_right(d.o[4]);
+    const float o6r = from_right(d.o[6]), o8l = from_left(d.o[8]);
+    if (EDGE) {
+        R.o1l = o1l; R.o5r = o5r; R.o2l = o2l; R.o3 = d.o[3]; R.o4r = o4r;
+        R.o6r = o6r; R.o7 = d.o[7]; R.o8l = o8l;
+        R.S1 = R.S2 = R.N1 = R.N2 = R.E1 = R.E2 = 0.0f;
+    } else {
+        R.S1 = (o2l + d.o[3]) + o4r; R.S2 = o2l - o4r;
+        R.N1 = (o6r + d.o[7]) + o8l; R.N2 = o8l - o6r;
+        R.E1 = o1l + o5r;            R.E2 = o1l - o5r;
+        R.o1l = R.o5r = R.o2l = R.o3 = R.o4r = R.o6r = R.o7 = R.o8l = 0.0f;
+    }
+}
+
+// Links a row passes to the row above: its N link at x and its NE / NW links
+// as the node above at x receives them (from x-1 and x+1).  Interior tiles
+// keep their sum and difference, edge tiles the two values.
+struct Carry { float cN, cBd, cBx, cNEl, cNWr; };
+
+template <bool EDGE>
+__device__ __forceinline__ void carry_from(float lN, float lNE, float lNW, Carry& c)
+{
+    const float a = from_left(lNE), b = from_right(lNW);
+    c.cN = lN;
+    if (EDGE) { c.cNEl = a; c.cNWr = b; c.cBd = 0.0f; c.cBx = 0.0f; }
+    else { c.cBd = a + b; c.cBx = b - a; c.cNEl = 0.0f; c.cNWr = 0.0f; }
+}
+
+// Eqs. Mac.lb.6 / Mac.lb.7 in increment form, interior node.  With the link
+// products P_1..P_8 (W SW S SE E NE N NW) of node x:
+//   P1 = -lE(x-1), P2 = -lNE(x-1, row below), P3 = -lN(row below),
+//   P4 = -lNW(x+1, row below), P5..P8 = lE, lNE, lN, lNW of x,
+// the terms are the partial sums
+//   Ha = P1 + P5, Hx = P1 - P5, Bd = P2 + P4, Bx = P2 - P4, Ud = P6 + P8, Ux = P8 - P6,
+//   pa = (Ha + P3) + P7, pd = Bd + Ud,
+//   mass: g/(6e^2) pa + g/(24e^2) pd,
+//   x: g/(6e) Hx + g/(24e) (Bx + Ux),  y: g/(6e) (P3 - P7) + g/(24e) (Bd - Ud);
+// update_edge forms exactly these from the eight values, update_fast from
+// the shared partial sums (equal bits: only exact negations differ).
+__device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, const Row& S, const Row& C,
+                                            const Row& N, const Carry& cy, float lE, float lN, float lNE,
+                                            float lNW, float& en, float& qxn, float& qyn)
+{
+    const float lEl = from_left(lE);
+    const float Ha = lE - lEl, Hs = lEl + lE;          // Ha, -Hx
+    const float Ud = lNE + lNW, Ux = lNW - lNE;
+    const float pa = (Ha - cy.cN) + lN;
+    const float pd = Ud - cy.cBd;                      // Bd = -cBd
+    const float mp = __builtin_fmaf(B.cma, pa, B.cmd * pd);
+    const float pxm = __builtin_fmaf(B.cqa, -Hs, B.cqd * (cy.cBx + Ux));
+    const float pym = __builtin_fmaf(B.cqa, -(cy.cN + lN), B.cqd * -(cy.cBd + Ud));
+    const float so = (C.E1 + S.S1) + N.N1;
+    const float mxo = (C.E2 + S.S2) + N.N2;
+    const float myo = S.S1 - N.N1;
+    en = x.eta + ((so - x.kk) + mp);
+    qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
+    qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
+}
+
+// The same from the link products P[a] and gathered equilibria oy[a] = Out_a(y_a).
+__device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, const float* P, const float* oy,
+                                            float& en, float& qxn, float& qyn)
+{
+    const float Ha = P[1] + P[5], Hx = P[1] - P[5];
+    const float Bd = P[2] + P[4], Bx = P[2] - P[4];
+    const float Ud = P[6] + P[8], Ux = P[8] - P[6];
+    const float pa = (Ha + P[3]) + P[7];
+    const float pd = Bd + Ud;
+    const float mp = __builtin_fmaf(B.cma, pa, B.cmd * pd);
+    const float pxm = __builtin_fmaf(B.cqa, Hx, B.cqd * (Bx + Ux));
+    const float pym = __builtin_fmaf(B.cqa, P[3] - P[7], B.cqd * (Bd - Ud));
+    const float E1 = oy[1] + oy[5], E2 = oy[1] - oy[5];
+    const float S1 = (oy[2] + oy[3]) + oy[4], S2 = oy[2] - oy[4];
+    const float N1 = (oy[6] + oy[7]) + oy[8], N2 = oy[8] - oy[6];
+    const float so = (E1 + S1) + N1;
+    const float mxo = (E2 + S2) + N2;
+    const float myo = S1 - N1;
+    en = x.eta + ((so - x.kk) + mp);
+    qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
+    qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
 }
 
 struct Raw { float eta, qx, qy, H; };
 
 // Index of a column / row to load: wrapped on periodic axes (lanes of a strip
-// can reach up to 63 columns past the first one, more than n on narrow
-// grids), clamped otherwise (values there only feed bounced links' lanes).
+// can reach past the grid on narrow grids), clamped otherwise (values there
+// only feed bounced links' lanes).
 __device__ __forceinline__ int wrap_or_clamp(int r, int n, int periodic)
 {
     if (periodic) {
@@ -149,113 +232,11 @@ __device__ __forceinline__ int wrap_or_clamp(int r, int n, int periodic)
 
 __device__ __forceinline__ bool is_open(int k) { return k == EDGE_DEPTH || k == EDGE_DISCHARGE; }
 
-// ------------------------------------------------------------------ tile
 // h = h_mean + amp - amp sin(omega t + phase), FP64
 __device__ __forceinline__ double depth_bc(const BasinDev& B, int k, double tn)
 {
     return B.bc_hmean[k] + B.bc_amp[k] - B.bc_amp[k] * sin(B.bc_om[k] * tn + B.bc_phase[k]);
 }
-
-// One output row r from window rows S (r-1), C (r), N (r+1).  WN holds the
-// raw values of row r+1 and is refilled with row r+4.  Expanded three times
-// in run_tile with rotated names (a macro rather than a function or lambda:
-// every operand stays a plain local, so the whole window lives in registers).
-#define MLB_ROW(r, WN, S, C, N, DC, DN)                                                           \
-    do {                                                                                          \
-        derive(B, WN.eta, WN.qx, WN.qy, WN.H, DN);                                                \
-        exchange(DN, N);                                                                          \
-        /* prefetch row r+4; rows past r1 are never needed (clamped: cache hits) */             \
-        WN = load_raw(E0, QX0, QY0, HH,                                                           \
-                      (uint32_t)(wrap_or_clamp(min((r) + 4, r1), ny, per_y) * ld) + (uint32_t)xl); \
-        /* own links of row r (E, N, NE, NW) and the four received ones */                   \
-        const float lE = link(DC.h, DC.eta, C.hr, C.er), lN = link(DC.h, DC.eta, N.h, N.eta);     \
-        const float lNE = link(DC.h, DC.eta, N.hr, N.er), lNW = link(DC.h, DC.eta, N.hl, N.el);   \
-        const float lWx = from_left(lE);                                                          \
-        float P[9], oy[9];                                                                        \
-        P[1] = -lWx; P[2] = -cNEl; P[3] = -cN; P[4] = -cNWr;                                      \
-        P[5] = lE;   P[6] = lNE;   P[7] = lN;  P[8] = lNW;                                        \
-        cN = lN; cNEl = from_left(lNE); cNWr = from_right(lNW); /* for row r+1 */                 \
-        oy[1] = C.o1l; oy[2] = S.o2l; oy[3] = S.o3;  oy[4] = S.o4r;  /* W SW S SE */              \
-        oy[5] = C.o5r; oy[6] = N.o6r; oy[7] = N.o7;  oy[8] = N.o8l;  /* E NE N NW */              \
-        if (EDGE) {                                                                               \
-            /* bounced link a: no bed term, A_a(y) = A_abar(x) */                                 \
-            const bool sout = !per_y && (r) == 0, nout = !per_y && (r) == ny - 1;                 \
-            const bool b2 = wout || sout, b4 = eout || sout, b6 = eout || nout, b8 = wout || nout; \
-            P[1] = wout ? 0.0f : P[1]; oy[1] = wout ? DC.o[5] : oy[1];                            \
-            P[2] = b2 ? 0.0f : P[2];   oy[2] = b2 ? DC.o[6] : oy[2];                              \
-            P[3] = sout ? 0.0f : P[3]; oy[3] = sout ? DC.o[7] : oy[3];                            \
-            P[4] = b4 ? 0.0f : P[4];   oy[4] = b4 ? DC.o[8] : oy[4];                              \
-            P[5] = eout ? 0.0f : P[5]; oy[5] = eout ? DC.o[1] : oy[5];                            \
-            P[6] = b6 ? 0.0f : P[6];   oy[6] = b6 ? DC.o[2] : oy[6];                              \
-            P[7] = nout ? 0.0f : P[7]; oy[7] = nout ? DC.o[3] : oy[7];                            \
-            P[8] = b8 ? 0.0f : P[8];   oy[8] = b8 ? DC.o[4] : oy[8];                              \
-        }                                                                                         \
-        float en, qxn, qyn;                                                                       \
-        update(B, DC, P, oy, en, qxn, qyn);                                                       \
-        bool store = own_col && (r) >= T.yo && (r) < r1;                                          \
-        if (EDGE) {                                                                               \
-            /* pre-override values of the x-neighbours (inward normals of W / E) */               \
-            float re1 = 0.f, rx1 = 0.f, ry1 = 0.f, re2 = 0.f, rx2 = 0.f, ry2 = 0.f;               \
-            float le1 = 0.f, lx1 = 0.f, ly1 = 0.f, le2 = 0.f, lx2 = 0.f, ly2 = 0.f;               \
-            if (open_x) {                                                                         \
-                re1 = from_right(en); rx1 = from_right(qxn); ry1 = from_right(qyn);               \
-                re2 = from_right(re1); rx2 = from_right(rx1); ry2 = from_right(ry1);              \
-                le1 = from_left(en); lx1 = from_left(qxn); ly1 = from_left(qyn);                  \
-                le2 = from_left(le1); lx2 = from_left(lx1); ly2 = from_left(ly1);                 \
-            }                                                                                     \
-            const bool onS = !per_y && (r) == 0, onN = !per_y && (r) == ny - 1;                   \
-            const bool wall = wall_x || (onS && kS == EDGE_WALL) || (onN && kN == EDGE_WALL);     \
-            float fe = en, fx = qxn, fy = qyn;                                                    \
-            if (wall) {                                                                           \
-                fx = 0.0f; fy = 0.0f;                                                             \
-            } else {                                                                              \
-                /* a node lies on at most one open edge (adjacent open edges are rejected) */     \
-                const bool oN = onN && is_open(kN);                                               \
-                if (ox_lane || oN) {                                                              \
-                    const float n1e = oW ? re1 : (oE ? le1 : h1e), n2e = oW ? re2 : (oE ? le2 : h2e); \
-                    const float n1x = oW ? rx1 : (oE ? lx1 : h1x), n2x = oW ? rx2 : (oE ? lx2 : h2x); \
-                    const float n1y = oW ? ry1 : (oE ? ly1 : h1y), n2y = oW ? ry2 : (oE ? ly2 : h2y); \
-                    const float xe = two ? __builtin_fmaf(2.0f, n1e, -n2e) : n1e;                 \
-                    const float xx = two ? __builtin_fmaf(2.0f, n1x, -n2x) : n1x;                 \
-                    const float xy = two ? __builtin_fmaf(2.0f, n1y, -n2y) : n1y;                 \
-                    const bool dep = oN ? kN == EDGE_DEPTH : dep_x;                               \
-                    if (dep) {                                                                    \
-                        fe = (float)((oN ? hbN : hb_x) - (double)DC.H); fx = xx; fy = xy;         \
-                    } else {                                                                      \
-                        fe = xe; fx = oN ? bqxN : bqx_x; fy = oN ? bqyN : bqy_x;                  \
-                    }                                                                             \
-                }                                                                                 \
-            }                                                                                     \
-            if (open_s) {                                                                         \
-                if ((r) == 0) { /* row 0 waits for rows 1 (and 2) of this step */                 \
-                    pe = en; pqx = qxn; pqy = qyn; pH = DC.H; poqx = DC.q0x; poqy = DC.q0y;       \
-                    store = false;                                                                \
-                } else if ((r) == extrap) {                                                       \
-                    const float m1e = two ? h1e : en, m1x = two ? h1x : qxn, m1y = two ? h1y : qyn; \
-                    const float ve = two ? __builtin_fmaf(2.0f, m1e, -en) : m1e;                  \
-                    const float vx = two ? __builtin_fmaf(2.0f, m1x, -qxn) : m1x;                 \
-                    const float vy = two ? __builtin_fmaf(2.0f, m1y, -qyn) : m1y;                 \
-                    /* row-0 lanes are S-edge nodes or wall corners */                            \
-                    float ge = pe, gx = pqx, gy = pqy;                                            \
-                    if (wall_x) { gx = 0.0f; gy = 0.0f; }                                         \
-                    else if (kS == EDGE_DEPTH) { ge = (float)(hbS - (double)pH); gx = vx; gy = vy; } \
-                    else { ge = ve; gx = bqxS; gy = bqyS; }                                       \
-                    if (own_col) {                                                                \
-                        E1[x] = ge; QX1[x] = gx; QY1[x] = gy;                                     \
-                        if (DIAG) account(sums, ge, gx, gy, pH, poqx, poqy);                      \
-                    }                                                                             \
-                }                                                                                 \
-            }                                                                                     \
-            h2e = h1e; h2x = h1x; h2y = h1y;                                                      \
-            h1e = en;  h1x = qxn; h1y = qyn;                                                      \
-            en = fe; qxn = fx; qyn = fy;                                                          \
-        }                                                                                         \
-        if (store) {                                                                              \
-            const uint32_t o = ((uint32_t)((r) * ld) + (uint32_t)x) * 4u;                         \
-            stf(E1, o, en); stf(QX1, o, qxn); stf(QY1, o, qyn);                                   \
-            if (DIAG) account(sums, en, qxn, qyn, DC.H, DC.q0x, DC.q0y);                          \
-        }                                                                                         \
-    } while (0)
 
 // Field access as SGPR base + 32-bit VGPR byte offset (one offset per row
 // serves all fields).  Offsets fit in 32 bits: a plane holds < 2^30 floats.
@@ -305,16 +286,187 @@ __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn,
     }
 }
 
-// One wave's tile: the software-pipelined walk down the strip.
-template <bool EDGE, bool DIAG>
+// Per-stage state of the walk: links carried to the next row, pre-override
+// values of the two previous rows (open N edge), the deferred row 0 (open S
+// edge) and the depth boundary values of the stage's time level.
+struct Stage {
+    Carry cy;
+    float h1e, h1x, h1y, h2e, h2x, h2y;
+    float pe, pqx, pqy, pH, poqx, poqy;
+    double hbS, hbN, hb_x;
+};
+
+// Lane and tile constants shared by the stages of one wave.
+struct Lane {
+    int x, xl;
+    bool own_col, wout, eout, wall_x, oW, oE, ox_lane, dep_x, open_x, open_s, two;
+    int kS, kN;
+    float bqx_x, bqy_x, bqxS, bqyS, bqxN, bqyN;
+};
+
+template <bool EDGE>
+__device__ __forceinline__ Lane lane_setup(const BasinDev& B, const TileDev& T, int x, bool own_lane, int xlo,
+                                           int xhi)
+{
+    Lane L;
+    const int nx = B.nx;
+    L.x = x;
+    L.xl = wrap_or_clamp(x, nx, B.per_x);
+    L.own_col = own_lane && x >= T.xo && x < nx;
+    const int kW = B.kind[0], kE = B.kind[1];
+    L.kS = B.kind[2]; L.kN = B.kind[3];
+    L.two = B.extrap == 2;
+    L.wout = EDGE && !B.per_x && x == 0;
+    L.eout = EDGE && !B.per_x && x == nx - 1;
+    L.wall_x = (L.wout && kW == EDGE_WALL) || (L.eout && kE == EDGE_WALL);
+    L.oW = L.wout && is_open(kW);
+    L.oE = L.eout && is_open(kE);
+    L.ox_lane = L.oW || L.oE;
+    L.dep_x = (L.oW && kW == EDGE_DEPTH) || (L.oE && kE == EDGE_DEPTH);
+    // some lane with valid values (columns xlo .. xhi) lies on an open W / E edge
+    L.open_x = EDGE && ((is_open(kW) && xlo <= 0) || (is_open(kE) && xhi >= nx - 1));
+    L.open_s = EDGE && is_open(L.kS) && T.y0 == 0;
+    L.bqx_x = L.oW ? B.bc_qx[0] : B.bc_qx[1];
+    L.bqy_x = L.oW ? B.bc_qy[0] : B.bc_qy[1];
+    L.bqxS = B.bc_qx[2]; L.bqyS = B.bc_qy[2]; L.bqxN = B.bc_qx[3]; L.bqyN = B.bc_qy[3];
+    return L;
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, double tn, Stage& V)
+{
+    V.h1e = V.h1x = V.h1y = V.h2e = V.h2x = V.h2y = 0.0f;
+    V.pe = V.pqx = V.pqy = V.pH = V.poqx = V.poqy = 0.0f;
+    V.hbS = V.hbN = V.hb_x = 0.0;
+    if (EDGE) {
+        const int kW = B.kind[0], kE = B.kind[1];
+        if (L.kS == EDGE_DEPTH) V.hbS = depth_bc(B, 2, tn);
+        if (L.kN == EDGE_DEPTH) V.hbN = depth_bc(B, 3, tn);
+        if (L.oW && kW == EDGE_DEPTH) V.hb_x = depth_bc(B, 0, tn);
+        if (L.oE && kE == EDGE_DEPTH) V.hb_x = depth_bc(B, 1, tn);
+    }
+}
+
+// Links of window row S towards row C (the first row of a walk).
+template <bool EDGE>
+__device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& cy)
+{
+    carry_from<EDGE>(link(dS.h, dS.eta, C.h, C.eta), link(dS.h, dS.eta, C.hr, C.er),
+                     link(dS.h, dS.eta, C.hl, C.el), cy);
+}
+
+// One output row r of a stage V from window rows S (r-1), C (r), N (r+1).
+// RAWN holds the raw values of row r+1; LOADNEXT refills it (or nothing).
+// EMIT(en, qxn, qyn, DC) receives the row's new values and its old node
+// (lanes decide ownership);
+// EMIT0(ge, gx, gy) the deferred row 0 of an open S edge, once rows 1 (and 2)
+// exist.  A macro rather than a function or lambda: every operand stays a
+// plain local, so the whole window lives in registers.
+#define MLB_ROW(V, r, RAWN, S, C, N, DC, DN, LOADNEXT, EMIT, EMIT0)                                 \
+    do {                                                                                          \
+        derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
+        exchange<EDGE>(DN, N);                                                                    \
+        LOADNEXT;                                                                                 \
+        const float lE = link(DC.h, DC.eta, C.hr, C.er), lN = link(DC.h, DC.eta, N.h, N.eta);     \
+        const float lNE = link(DC.h, DC.eta, N.hr, N.er), lNW = link(DC.h, DC.eta, N.hl, N.el);   \
+        float en, qxn, qyn;                                                                       \
+        if (EDGE) {                                                                               \
+            float P[9], oy[9];                                                                    \
+            P[1] = -from_left(lE); P[2] = -V.cy.cNEl; P[3] = -V.cy.cN; P[4] = -V.cy.cNWr;         \
+            P[5] = lE;             P[6] = lNE;        P[7] = lN;       P[8] = lNW;                \
+            oy[1] = C.o1l; oy[2] = S.o2l; oy[3] = S.o3;  oy[4] = S.o4r;  /* W SW S SE */          \
+            oy[5] = C.o5r; oy[6] = N.o6r; oy[7] = N.o7;  oy[8] = N.o8l;  /* E NE N NW */          \
+            /* bounced link a: no bed term, A_a(y) = A_abar(x) */                                 \
+            const bool sout = !per_y && (r) == 0, nout = !per_y && (r) == ny - 1;                 \
+            const bool bb2_ = L.wout || sout, bb4_ = L.eout || sout, bb6_ = L.eout || nout,             \
+                       bb8_ = L.wout || nout;                                                       \
+            P[1] = L.wout ? 0.0f : P[1]; oy[1] = L.wout ? DC.o[5] : oy[1];                        \
+            P[2] = bb2_ ? 0.0f : P[2];     oy[2] = bb2_ ? DC.o[6] : oy[2];                            \
+            P[3] = sout ? 0.0f : P[3];   oy[3] = sout ? DC.o[7] : oy[3];                          \
+            P[4] = bb4_ ? 0.0f : P[4];     oy[4] = bb4_ ? DC.o[8] : oy[4];                            \
+            P[5] = L.eout ? 0.0f : P[5]; oy[5] = L.eout ? DC.o[1] : oy[5];                        \
+            P[6] = bb6_ ? 0.0f : P[6];     oy[6] = bb6_ ? DC.o[2] : oy[6];                            \
+            P[7] = nout ? 0.0f : P[7];   oy[7] = nout ? DC.o[3] : oy[7];                          \
+            P[8] = bb8_ ? 0.0f : P[8];     oy[8] = bb8_ ? DC.o[4] : oy[8];                            \
+            update_edge(B, DC, P, oy, en, qxn, qyn);                                              \
+        } else {                                                                                  \
+            update_fast(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, qxn, qyn);                    \
+        }                                                                                         \
+        carry_from<EDGE>(lN, lNE, lNW, V.cy); /* for row r+1 */                                   \
+        /* keep the row's arithmetic ahead of the ownership branch of EMIT */                     \
+        asm volatile("" ::"v"(en), "v"(qxn), "v"(qyn));                                           \
+        bool emit = true;                                                                         \
+        if (EDGE) {                                                                               \
+            /* pre-override values of the x-neighbours (inward normals of W / E) */               \
+            float re1 = 0.f, rx1 = 0.f, ry1 = 0.f, re2 = 0.f, rx2 = 0.f, ry2 = 0.f;               \
+            float le1 = 0.f, lx1 = 0.f, ly1 = 0.f, le2 = 0.f, lx2 = 0.f, ly2 = 0.f;               \
+            if (L.open_x) {                                                                       \
+                re1 = from_right(en); rx1 = from_right(qxn); ry1 = from_right(qyn);               \
+                re2 = from_right(re1); rx2 = from_right(rx1); ry2 = from_right(ry1);              \
+                le1 = from_left(en); lx1 = from_left(qxn); ly1 = from_left(qyn);                  \
+                le2 = from_left(le1); lx2 = from_left(lx1); ly2 = from_left(ly1);                 \
+            }                                                                                     \
+            const bool onS = !per_y && (r) == 0, onN = !per_y && (r) == ny - 1;                   \
+            const bool wall = L.wall_x || (onS && L.kS == EDGE_WALL) || (onN && L.kN == EDGE_WALL); \
+            float fe = en, fx = qxn, fy = qyn;                                                    \
+            if (wall) {                                                                           \
+                fx = 0.0f; fy = 0.0f;                                                             \
+            } else {                                                                              \
+                /* a node lies on at most one open edge (adjacent open edges are rejected) */     \
+                const bool oN = onN && is_open(L.kN);                                             \
+                if (L.ox_lane || oN) {                                                            \
+                    const float n1e = L.oW ? re1 : (L.oE ? le1 : V.h1e);                          \
+                    const float n2e = L.oW ? re2 : (L.oE ? le2 : V.h2e);                          \
+                    const float n1x = L.oW ? rx1 : (L.oE ? lx1 : V.h1x);                          \
+                    const float n2x = L.oW ? rx2 : (L.oE ? lx2 : V.h2x);                          \
+                    const float n1y = L.oW ? ry1 : (L.oE ? ly1 : V.h1y);                          \
+                    const float n2y = L.oW ? ry2 : (L.oE ? ly2 : V.h2y);                          \
+                    const float xe = L.two ? __builtin_fmaf(2.0f, n1e, -n2e) : n1e;               \
+                    const float xx = L.two ? __builtin_fmaf(2.0f, n1x, -n2x) : n1x;               \
+                    const float xy = L.two ? __builtin_fmaf(2.0f, n1y, -n2y) : n1y;               \
+                    const bool dep = oN ? L.kN == EDGE_DEPTH : L.dep_x;                           \
+                    if (dep) {                                                                    \
+                        fe = (float)((oN ? V.hbN : V.hb_x) - (double)DC.H); fx = xx; fy = xy;     \
+                    } else {                                                                      \
+                        fe = xe; fx = oN ? L.bqxN : L.bqx_x; fy = oN ? L.bqyN : L.bqy_x;          \
+                    }                                                                             \
+                }                                                                                 \
+            }                                                                                     \
+            if (L.open_s) {                                                                       \
+                if ((r) == 0) { /* row 0 waits for rows 1 (and 2) of this step */                 \
+                    V.pe = en; V.pqx = qxn; V.pqy = qyn; V.pH = DC.H; V.poqx = DC.q0x; V.poqy = DC.q0y; \
+                    emit = false;                                                                 \
+                } else if ((r) == extrap) {                                                       \
+                    const float m1e = L.two ? V.h1e : en, m1x = L.two ? V.h1x : qxn;              \
+                    const float m1y = L.two ? V.h1y : qyn;                                        \
+                    const float ve = L.two ? __builtin_fmaf(2.0f, m1e, -en) : m1e;                \
+                    const float vx = L.two ? __builtin_fmaf(2.0f, m1x, -qxn) : m1x;               \
+                    const float vy = L.two ? __builtin_fmaf(2.0f, m1y, -qyn) : m1y;               \
+                    /* row-0 lanes are S-edge nodes or wall corners */                            \
+                    float ge = V.pe, gx = V.pqx, gy = V.pqy;                                      \
+                    if (L.wall_x) { gx = 0.0f; gy = 0.0f; }                                       \
+                    else if (L.kS == EDGE_DEPTH) { ge = (float)(V.hbS - (double)V.pH); gx = vx; gy = vy; } \
+                    else { ge = ve; gx = L.bqxS; gy = L.bqyS; }                                   \
+                    EMIT0(ge, gx, gy);                                                            \
+                }                                                                                 \
+            }                                                                                     \
+            V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                          \
+            V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                            \
+            en = fe; qxn = fx; qyn = fy;                                                          \
+        }                                                                                         \
+        if (emit) { EMIT(en, qxn, qyn, DC); }                                                         \
+    } while (0)
+
+#define MLB_NOTHING(...) do { } while (0)
+
+// ------------------------------------------------------------------ one step per pass
+template <bool EDGE, bool DIAG, bool FRIC>
 __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd,
                                          double* __restrict__ part)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int nx = B.nx, ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
-    const int x = T.x0 + lane - 1;
-    const int xl = wrap_or_clamp(x, nx, B.per_x);
-    const bool own_col = lane >= 1 && lane <= kStripOut && x >= T.xo && x < nx;
+    const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
+    const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
     const int wr = rd ^ 1;
     // fields are device (global) memory: typed so, loads and stores are
     // global_* instructions with exact wait counts rather than flat ones
@@ -325,66 +477,61 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     gfloat* __restrict__ E1 = (gfloat*)B.eta[wr];
     gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
-
-    // boundary data of this lane (edge tiles only)
-    const int kW = B.kind[0], kE = B.kind[1], kS = B.kind[2], kN = B.kind[3];
-    const bool two = extrap == 2;
-    const bool wout = EDGE && !B.per_x && x == 0, eout = EDGE && !B.per_x && x == nx - 1;
-    const bool wall_x = (wout && kW == EDGE_WALL) || (eout && kE == EDGE_WALL);
-    const bool oW = wout && is_open(kW), oE = eout && is_open(kE), ox_lane = oW || oE;
-    const bool dep_x = (oW && kW == EDGE_DEPTH) || (oE && kE == EDGE_DEPTH);
-    double hbW = 0.0, hbE = 0.0, hbS = 0.0, hbN = 0.0;
-    bool open_x = false, open_s = false;
-    if (EDGE) {
-        const double tn = (double)(B.stepc[rd] + 1) * B.dt;
-        if (kW == EDGE_DEPTH) hbW = depth_bc(B, 0, tn);
-        if (kE == EDGE_DEPTH) hbE = depth_bc(B, 1, tn);
-        if (kS == EDGE_DEPTH) hbS = depth_bc(B, 2, tn);
-        if (kN == EDGE_DEPTH) hbN = depth_bc(B, 3, tn);
-        open_x = (is_open(kW) && T.x0 == 0) || (is_open(kE) && T.x0 + kStripOut >= nx);
-        open_s = is_open(kS) && T.y0 == 0;
-    }
-    const double hb_x = oW ? hbW : hbE;
-    const float bqx_x = oW ? B.bc_qx[0] : B.bc_qx[1], bqy_x = oW ? B.bc_qy[0] : B.bc_qy[1];
-    const float bqxS = B.bc_qx[2], bqyS = B.bc_qy[2], bqxN = B.bc_qx[3], bqyN = B.bc_qy[3];
-    // pre-override values of rows r-1, r-2 (open N edge) and the deferred row 0 (open S edge)
-    float h1e = 0.f, h1x = 0.f, h1y = 0.f, h2e = 0.f, h2x = 0.f, h2y = 0.f;
-    float pe = 0.f, pqx = 0.f, pqy = 0.f, pH = 0.f, poqx = 0.f, poqy = 0.f;
+    Stage V;
+    stage_setup<EDGE>(B, L, (double)(B.stepc[rd] + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
+#define MLB_LD(row) load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
     // Software pipeline: a row's raw values are loaded three rows before they
     // are derived.  Raw slots, window rows and derived nodes rotate with
     // period 3, so the loop is unrolled by 3 and the rotation is a renaming
     // (no register copy ever waits on a load in flight).
-    Raw wa = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 1, r1), ny, per_y) * ld) + (uint32_t)xl);
-    Raw wb = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 2, r1), ny, per_y) * ld) + (uint32_t)xl);
-    Raw wc = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 + 3, r1), ny, per_y) * ld) + (uint32_t)xl);
-    Derived d0, d1, d2;
+    Raw wa = MLB_LD(r0 + 1), wb = MLB_LD(r0 + 2), wc = MLB_LD(r0 + 3);
+    Node d0, d1, d2;
     Row R0, R1, R2;
     {
-        const Raw w = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0 - 1, r1), ny, per_y) * ld) + (uint32_t)xl);
-        derive(B, w.eta, w.qx, w.qy, w.H, d0);
-        exchange(d0, R0);
+        const Raw w = MLB_LD(r0 - 1);
+        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d0);
+        exchange<EDGE>(d0, R0);
     }
     {
-        const Raw w = load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min(r0, r1), ny, per_y) * ld) + (uint32_t)xl);
-        derive(B, w.eta, w.qx, w.qy, w.H, d1);
-        exchange(d1, R1);
+        const Raw w = MLB_LD(r0);
+        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d1);
+        exchange<EDGE>(d1, R1);
     }
-    // links of row r0-1 towards row r0, as row r0 receives them
-    float cN = link(d0.h, d0.eta, R1.h, R1.eta);
-    float cNEl = from_left(link(d0.h, d0.eta, R1.hr, R1.er));
-    float cNWr = from_right(link(d0.h, d0.eta, R1.hl, R1.el));
+    carry_init<EDGE>(d0, R1, V.cy);
+    int r = r0;
+#define MLB_STORE1(en_, qx_, qy_, D_)                                                             \
+    do {                                                                                          \
+        if (L.own_col && r >= T.yo && r < r1) {                                                   \
+            const uint32_t o = ((uint32_t)(r * ld) + (uint32_t)L.x) * 4u;                         \
+            stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
+            if (DIAG) account(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y);                         \
+        }                                                                                         \
+    } while (0)
+#define MLB_STORE0(ge_, gx_, gy_)                                                                 \
+    do {                                                                                          \
+        if (L.own_col) {                                                                          \
+            const uint32_t o = (uint32_t)L.x * 4u;                                                \
+            stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
+            if (DIAG) account(sums, ge_, gx_, gy_, V.pH, V.poqx, V.poqy);                         \
+        }                                                                                         \
+    } while (0)
     // single-exit counted loop: the tile's rows are rounded up to a multiple
     // of 3 and the pad rows (r >= r1) are computed but never stored
     const int nk = (T.rows + 2) / 3;
-    int r = r0;
-    for (int k = 0; k < nk; ++k, r += 3) {
-        MLB_ROW(r, wa, R0, R1, R2, d1, d2);
-        MLB_ROW(r + 1, wb, R1, R2, R0, d2, d0);
-        MLB_ROW(r + 2, wc, R2, R0, R1, d0, d1);
+    for (int k = 0; k < nk; ++k) {
+        MLB_ROW(V, r, wa, R0, R1, R2, d1, d2, wa = MLB_LD(r + 4), MLB_STORE1, MLB_STORE0);
+        ++r;
+        MLB_ROW(V, r, wb, R1, R2, R0, d2, d0, wb = MLB_LD(r + 4), MLB_STORE1, MLB_STORE0);
+        ++r;
+        MLB_ROW(V, r, wc, R2, R0, R1, d0, d1, wc = MLB_LD(r + 4), MLB_STORE1, MLB_STORE0);
+        ++r;
     }
+#undef MLB_STORE1
+#undef MLB_STORE0
+#undef MLB_LD
     if (DIAG) {
         // wave reduction in fixed order (xor butterfly), one partial set per tile
 #pragma unroll
@@ -402,14 +549,123 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
         }
     }
 }
+
+// ------------------------------------------------------------------ two steps per pass
+// Stage A computes level n+1 for rows r0-1 .. (lanes 0..63, valid 1..62) and
+// leaves each row in a queue slot; stage B, three rows behind, computes
+// level n+2 for rows r0 .. r1-1 from the queue and stores lanes 2..61.
+// Queue slot of A's row ra: (ra - r0 + 1) mod 3.  A's row 0 of an open S edge
+// is final only after A's row `extrap`, so B starts once A has done row r0+2.
+template <bool EDGE, bool FRIC>
+__device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
+    const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
+                                    T.x0 + kStripOut2);
+    const int wr = rd ^ 1;
+    const gfloat* __restrict__ E0 = (const gfloat*)B.eta[rd];
+    const gfloat* __restrict__ QX0 = (const gfloat*)B.qx[rd];
+    const gfloat* __restrict__ QY0 = (const gfloat*)B.qy[rd];
+    const gfloat* __restrict__ HH = (const gfloat*)B.H;
+    gfloat* __restrict__ E1 = (gfloat*)B.eta[wr];
+    gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
+    gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
+    const double tn0 = (double)B.stepc[rd] * B.dt;
+    Stage SA, SB;
+    stage_setup<EDGE>(B, L, tn0 + B.dt, SA);
+    stage_setup<EDGE>(B, L, tn0 + 2.0 * B.dt, SB);
+
+    const int r0 = T.y0, r1 = T.y0 + T.rows;
+    const int alast = r1 + 1;     // last level-n row stage A reads
+#define MLB_LD(row) load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+    // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
+    Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
+    Node a0, a1, a2;
+    Row A0, A1, A2;
+    {
+        const Raw w = MLB_LD(r0 - 2);
+        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a0);
+        exchange<EDGE>(a0, A0);
+    }
+    {
+        const Raw w = MLB_LD(r0 - 1);
+        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a1);
+        exchange<EDGE>(a1, A1);
+    }
+    carry_init<EDGE>(a0, A1, SA.cy);
+    Raw q0, q1, q2;               // level n+1 rows handed from A to B
+    Node b0, b1, b2;
+    Row B0, B1, B2;
+    int ra = r0 - 1;
+#define MLB_Q0(en_, qx_, qy_, D_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; } while (0)
+#define MLB_Q1(en_, qx_, qy_, D_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; } while (0)
+#define MLB_Q2(en_, qx_, qy_, D_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; } while (0)
+    // A's deferred row 0 (open S edge: r0 == 0, so its slot is q1)
+#define MLB_A0(ge_, gx_, gy_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; } while (0)
+    MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0-1
+    ++ra;
+    // B's window row r0-1
+    derive<FRIC>(B, q0.eta, q0.qx, q0.qy, q0.H, b0);
+    exchange<EDGE>(b0, B0);
+    MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_A0);   // row r0
+    ++ra;
+    MLB_ROW(SA, ra, wc, A2, A0, A1, a0, a1, wc = MLB_LD(ra + 4), MLB_Q2, MLB_A0);   // row r0+1
+    ++ra;
+    MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0+2
+    ++ra;
+    // B's window row r0 (final now) and its links towards row r0-1
+    derive<FRIC>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
+    exchange<EDGE>(b1, B1);
+    carry_init<EDGE>(b0, B1, SB.cy);
+
+    int rb = r0;
+#define MLB_STORE2(en_, qx_, qy_, D_)                                                              \
+    do {                                                                                          \
+        if (L.own_col && rb >= T.yo && rb < r1) {                                                 \
+            const uint32_t o = ((uint32_t)(rb * ld) + (uint32_t)L.x) * 4u;                        \
+            stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
+        }                                                                                         \
+    } while (0)
+#define MLB_STORE20(ge_, gx_, gy_)                                                                \
+    do {                                                                                          \
+        if (L.own_col) {                                                                          \
+            const uint32_t o = (uint32_t)L.x * 4u;                                                \
+            stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
+        }                                                                                         \
+    } while (0)
+    // B row rb consumes A's row rb+1; then A computes row rb+3.  Rows of A
+    // past the tile read the clamped last row and are never used for stores.
+    const int nk = (T.rows + 2) / 3;
+    for (int k = 0; k < nk; ++k) {
+        MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
+        ++rb;
+        MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_NOTHING);
+        ++ra;
+        MLB_ROW(SB, rb, q0, B1, B2, B0, b2, b0, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
+        ++rb;
+        MLB_ROW(SA, ra, wc, A2, A0, A1, a0, a1, wc = MLB_LD(ra + 4), MLB_Q2, MLB_NOTHING);
+        ++ra;
+        MLB_ROW(SB, rb, q1, B2, B0, B1, b0, b1, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
+        ++rb;
+        MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_NOTHING);
+        ++ra;
+    }
+#undef MLB_STORE2
+#undef MLB_STORE20
+#undef MLB_Q0
+#undef MLB_Q1
+#undef MLB_Q2
+#undef MLB_A0
+#undef MLB_LD
+}
 #undef MLB_ROW
 
 // ------------------------------------------------------------------ kernels
 template <bool DIAG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIAG ? 4 : 5)))
-void step_kernel(const BasinDev* __restrict__ basins,
-                                                      const TileDev* __restrict__ tiles, int ntiles,
-                                                      int parity, double* __restrict__ partials)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
+                 int parity, double* __restrict__ partials)
 {
     // One wave per tile, tiles in list order (largest basins first): the
     // hardware dispatcher hands out workgroups in index order, so the list is
@@ -428,9 +684,42 @@ void step_kernel(const BasinDev* __restrict__ basins,
     const bool edge = (!B.per_x && (T.x0 == 0 || T.x0 + kStripOut >= B.nx)) ||
                       (!B.per_y && (T.y0 == 0 || T.y0 + T.rows >= B.ny));
     double* part = partials + (size_t)t * kPartials;
-    if (edge) run_tile<true, DIAG>(B, T, rd, part);
-    else run_tile<false, DIAG>(B, T, rd, part);
+    if (B.cfr != 0.0f) {
+        if (edge) run_tile<true, DIAG, true>(B, T, rd, part);
+        else run_tile<false, DIAG, true>(B, T, rd, part);
+    } else {
+        if (edge) run_tile<true, DIAG, false>(B, T, rd, part);
+        else run_tile<false, DIAG, false>(B, T, rd, part);
+    }
 }
+
+// Two steps per launch over tiles of 60-column strips.  A tile needs the
+// boundary logic when stage A's rows r0-1 .. r1 or lanes 1..62 touch an edge.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
+                  int parity)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
+    if (t >= ntiles) return;
+    const TileDev T = tiles[t];
+    const BasinDev& B = basins[T.basin];
+    const int rd = parity ^ B.swap;
+    if (t == B.first_tile2 && lane == 0) {
+        volatile int64_t* sc = B.stepc;
+        sc[rd ^ 1] = sc[rd] + 2;
+    }
+    const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
+                      (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
+    if (B.cfr != 0.0f) {
+        if (edge) run_tile2<true, true>(B, T, rd);
+        else run_tile2<false, true>(B, T, rd);
+    } else {
+        if (edge) run_tile2<true, false>(B, T, rd);
+        else run_tile2<false, false>(B, T, rd);
+    }
+}
+
 
 // Reduction of the current state (no step): same partial layout as the step.
 __global__ __launch_bounds__(kBlock) void reduce_state_kernel(const BasinDev* __restrict__ basins,
@@ -540,10 +829,12 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
                        double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
-    if (diag)
+    if (tblock == 2)
+        hipLaunchKernelGGL(step2_kernel, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
+    else if (diag)
         hipLaunchKernelGGL(step_kernel<true>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
                            ntiles, parity, d_partials);
     else

@@ -37,9 +37,11 @@ namespace mlb {
 // reduction partials, and an optional captured chunk of steps.
 struct Plan {
     std::vector<BasinDev> hb;
-    std::vector<TileDev> ht;
+    std::vector<TileDev> ht;       // one step per pass
+    std::vector<TileDev> ht2;      // two steps per pass (empty unless tblock 2)
     BasinDev* db = nullptr;
     TileDev* dt = nullptr;
+    TileDev* dt2 = nullptr;
     double* dpart = nullptr;
     double* dout = nullptr;
     double* hout = nullptr;  // pinned
@@ -48,6 +50,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     int gparity = -1;
     int gsteps = 0;
+    int gkind = 0;             // steps per launch in the captured graph
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool built = false;
 
@@ -55,11 +58,11 @@ struct Plan {
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
-        gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0;
-        (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dpart);
+        gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0; gkind = 0;
+        (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dt2); (void)hipFree(dpart);
         (void)hipFree(dout);
         if (hout) (void)hipHostFree(hout);
-        db = nullptr; dt = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
+        db = nullptr; dt = nullptr; dt2 = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
         built = false;
     }
 };

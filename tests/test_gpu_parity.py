@@ -160,6 +160,98 @@ def test_tile_rows_and_graphs_bitwise(ctx):
                 assert np.array_equal(a, b)
 
 
+def _two_step_cases():
+    """(name, spec, state, steps, tile_rows): every edge kind, extrapolation
+    order, narrow and odd strips, tiles shifted to row 1, odd step counts."""
+    cases = []
+    sp = closed_spec(64, 64, 0)
+    cases.append(("closed64", sp, wl.seeded_state(sp, 0, q_amp=0.1), 131, 15))
+    sp = closed_spec(125, 70, 1)
+    cases.append(("closed125x70_rows21", sp, wl.seeded_state(sp, 1, q_amp=0.1), 64, 21))
+    for nx, ny, rows in ((5, 4, 4), (4, 133, 9), (61, 9, 6), (121, 22, 21), (59, 31, 30), (60, 25, 12)):
+        sp = closed_spec(nx, ny, nx + ny)
+        cases.append(("closed%dx%d_rows%d" % (nx, ny, rows), sp, wl.seeded_state(sp, 2, q_amp=0.1), 37, rows))
+    sp = wl.Spec("periodic", 70, 40, 1.0, 10.0 / 6.0, bumpy(70, 40, 5), 2.0,
+                 edges=(wl.PERIODIC,) * 4, wind_speed=(5.0, 3.0), chezy=50.0, omega=1e-3)
+    cases.append(("periodic70x40", sp, wl.seeded_state(sp, 5, q_amp=0.2), 101, 9))
+    sp = wl.Spec("periodic_narrow", 3, 5, 1.0, 10.0 / 6.0, bumpy(3, 5, 6), 2.0,
+                 edges=(wl.PERIODIC,) * 4, wind_speed=(5.0, 3.0))
+    cases.append(("periodic3x5", sp, wl.seeded_state(sp, 6, q_amp=0.2), 40, 4))
+    for order in (1, 2):
+        sp = wl.bump_channel(150, 67, sigma=12.0)
+        sp.extrap_order = order
+        cases.append(("channel_order%d" % order, sp, None, 120, 15))
+        sp = wl.bump_channel(181, 22, sigma=6.0)
+        sp.extrap_order = order
+        cases.append(("channel181x22_rows21_order%d" % order, sp, None, 77, 21))
+    nx, ny = 40, 90
+    for order in (1, 2):
+        sp = wl.Spec("ychannel", nx, ny, 1.0, 25.0 / 6.0, bumpy(nx, ny, 7, amp=0.2), 2.0,
+                     edges=(wl.PERIODIC, wl.PERIODIC, wl.DISCHARGE, wl.DEPTH), extrap_order=order,
+                     depth_bc={wl.N: (2.0, 0.05, 30.0, 0.0)}, discharge_bc={wl.S: (0.1, 1.5)},
+                     qy0=np.full((ny, nx), 1.5))
+        cases.append(("ychannel_order%d" % order, sp, None, 99, 12))
+    sp = wl.Spec("ydepth", 70, 46, 1.0, 25.0 / 6.0, bumpy(70, 46, 9, amp=0.2), 2.0,
+                 edges=(wl.WALL, wl.WALL, wl.DEPTH, wl.DISCHARGE), extrap_order=2,
+                 depth_bc={wl.S: (2.0, 0.03, 20.0, 0.5)}, discharge_bc={wl.N: (0.0, 0.5)})
+    cases.append(("ydepth_walls", sp, None, 66, 15))
+    cases.append(("tidal_strip", wl.tidal_strip(), None, 500, 15))
+    return cases
+
+
+_TB2 = _two_step_cases()
+
+
+@pytest.mark.parametrize("case", _TB2, ids=[c[0] for c in _TB2])
+def test_two_step_passes_bitwise(ctx, case):
+    """Two steps per pass (temporal blocking) give the bits of one step per pass."""
+    name, spec, state, steps, rows = case
+    say("two-step case", name, spec.nx, spec.ny, "steps", steps, "rows", rows)
+    one = run_gpu(ctx, spec, steps, state, opts={"tile_rows": rows, "tblock": 1})
+    for opts in ({"tile_rows": rows, "tblock": 2},
+                 {"tile_rows": rows, "tblock": 2, "use_graph": True, "graph_chunk": 8}):
+        two = run_gpu(ctx, spec, steps, state, opts=opts)
+        for a, b in zip(two, one):
+            assert np.array_equal(a, b), (name, opts)
+
+
+def test_two_step_diag_and_steady_match(ctx):
+    """Residual, mass and the converged state agree bit for bit with tblock 1."""
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(90, 70, 4)
+    res = []
+    for tb in (1, 2):
+        g = mlb.grid_from_spec(ctx, spec)
+        g.set_exec_opts(tblock=tb, tile_rows=12)
+        ok, d = g.run_steady(1e-5, 200000, 100)
+        g.step(3)
+        res.append((ok, d, g.diag(), g.get_state()))
+        g.close()
+    (ok1, d1, e1, s1), (ok2, d2, e2, s2) = res
+    assert ok1 and ok2
+    for k in ("step", "mass", "residual", "max_speed", "nonfinite"):
+        assert d1[k] == d2[k] and e1[k] == e2[k], k
+    for a, b in zip(s1, s2):
+        assert np.array_equal(a, b)
+
+
+def test_two_step_batch_bitwise(ctx):
+    from paper_1902_02999_amd import mlb
+    specs = [closed_spec(n, m, s) for (n, m, s) in ((64, 64, 0), (200, 97, 1), (33, 150, 2))]
+    specs.append(wl.bump_channel(130, 60, sigma=10.0))
+    solo = [run_gpu(ctx, s, 77) for s in specs]
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    b = mlb.Batch(ctx, grids)
+    b.set_exec_opts(tile_rows=15, tblock=2, graph_chunk=8)
+    say("two-step batch of", len(grids))
+    b.step(77)
+    b.close()
+    for g, ref in zip(grids, solo):
+        for a, r in zip(g.get_state(), ref):
+            assert np.array_equal(a, r)
+        g.close()
+
+
 def test_batch_equals_solo_bitwise(ctx):
     from paper_1902_02999_amd import mlb
     specs = [closed_spec(n, m, s) for (n, m, s) in ((64, 64, 0), (200, 97, 1), (33, 150, 2))]
@@ -267,6 +359,23 @@ def test_full_size_bump_channel_sampled(ctx):
     g.close()
 
 
+def test_full_size_two_step_bitwise(ctx):
+    """4096 x 4096 channel: two steps per pass give the bits of one step per
+    pass (whose single steps the sampled oracle test checks)."""
+    from paper_1902_02999_amd import mlb
+    spec = wl.bump_channel(4096)
+    outs = []
+    for tb in (1, 2):
+        say("full size tblock", tb)
+        g = mlb.grid_from_spec(ctx, spec)
+        g.set_exec_opts(tile_rows=15, tblock=tb, blocks_per_cu=3)
+        g.step(21)
+        outs.append(g.get_state())
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 # ----------------------------------------------------------------------------- tuning
 def test_blocks_per_cu_bitwise(ctx):
     spec = wl.bump_channel(200, 130, sigma=12.0)
@@ -286,12 +395,13 @@ def test_autotune_keeps_state_and_caches(ctx, tmp_path):
     say("autotune", spec.name)
     best = g.autotune(steps=8, cache_path=cache)
     assert best["tile_rows"] in (6, 9, 12, 15, 21, 27, 33, 45) and best["blocks_per_cu"] in (0, 2, 3, 4, 5)
+    assert best["tblock"] in (1, 2)
     after = g.get_state()
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
     assert g.diag()["step"] == 5
     lines = open(cache).read().split()
-    assert len(lines) == 4 and lines[0].endswith("_g300x170")
+    assert len(lines) == 5 and lines[0].endswith("_g300x170") and int(lines[3]) in (1, 2)
     # second call: served from the cache, same choice
     assert g.autotune(steps=8, cache_path=cache) == g.exec_opts().as_dict()
     # stepping after tuning equals stepping an untuned copy
