@@ -41,7 +41,8 @@ typedef enum {
     MLB_E_UNSTABLE = -4,       /* g * H_max > e^2: the step is unstable      */
     MLB_E_NONFINITE = -5,      /* a check found a non-finite value or h <= 0 */
     MLB_E_STATE = -6,          /* call not allowed in the object's state     */
-    MLB_E_NOTCONVERGED = -7    /* max_steps reached before the tolerance     */
+    MLB_E_NOTCONVERGED = -7,   /* max_steps reached before the tolerance     */
+    MLB_E_STALLED = -8         /* residual stopped falling (see mlb_set_stall_checks) */
 } mlb_status;
 
 /* Edge kinds.  Edges are indexed W=0 (i = 0), E=1 (i = nx-1), S=2 (j = 0),
@@ -102,6 +103,13 @@ mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out);
 mlb_status mlb_ctx_destroy(mlb_ctx* ctx);
 /* Blocks until the context's stream is idle. */
 mlb_status mlb_ctx_sync(mlb_ctx* ctx);
+/* Stall rule of the steady-state runs on this context (mlb_run_steady,
+ * mlb_warm_start_run): with checks > 0 a run stops with MLB_E_STALLED once
+ * the smallest residual seen so far is within a factor 10 of the tolerance
+ * and `checks` consecutive checks have not lowered it.  FP32 fields put a
+ * noise floor under the residual that can sit at a tolerance like 1e-6; the
+ * state is then as steady as FP32 holds it.  0 (default): off. */
+mlb_status mlb_set_stall_checks(mlb_ctx* ctx, int32_t checks);
 
 /* Device bytes of a grid's fields (two copies of eta, qx, qy; the still-water
  * depth; the step counter) for a caller-owned workspace.  The small tile list
@@ -159,7 +167,8 @@ mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out);
 /* Steps until the residual of a checked step is <= tol.  Checks every
  * check_every steps (the checked step is reduced in the same kernel pass).
  * MLB_E_NONFINITE on a non-finite value or h <= 0, MLB_E_NOTCONVERGED after
- * max_steps.  out (may be NULL) receives the last check. */
+ * max_steps, MLB_E_STALLED under the context's stall rule.  out (may be NULL)
+ * receives the last check. */
 mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t check_every,
                           mlb_diag_t* out);
 
@@ -224,10 +233,16 @@ mlb_status mlb_copy_probe(mlb_ctx* ctx, size_t bytes, int32_t reps, double* gbps
  * convolutions + ReLU (2x2 average pool between levels); per decoder level a
  * nearest x2 upsample, a 3x3 conv + ReLU, concatenation with the encoder
  * level's output, two 3x3 convs + ReLU; a 1x1 head to 3 channels.  The input
- * has in_ch channels (6 features, the rest zero): normalised still-water
- * depth, tau_x/rho, tau_y/rho, C_b, and the node position x, y mapped to
- * [-1, 1] (the steady surface of a closed basin depends on where a node lies
- * relative to the walls, which a finite receptive field cannot see).  Convolutions run on BF16
+ * has in_ch channels (MLB_NET_FEATURES = 8 features, the rest zero):
+ *   0  normalised still-water depth H
+ *   1, 2  wind stress over density: its direction (unit vector, 0 without
+ *         wind) when tau_ref > 0, else normalised tau_x/rho, tau_y/rho
+ *   3  normalised |tau|/rho
+ *   4  normalised C_b
+ *   5, 6  node position x, y mapped to [-1, 1] (the steady surface of a
+ *         closed basin depends on where a node lies relative to the walls,
+ *         which a finite receptive field cannot see)
+ *   7  1 (marks the image edges through the convolutions' zero padding)  Convolutions run on BF16
  * MFMA with FP32 accumulation; FP32 master parameters.  Parameters are ordered
  * layer by layer in forward order, each 3x3 weight [Cout][3][3][Cin] then its
  * bias; the head weight [3][base_ch] then its bias.
@@ -242,9 +257,12 @@ typedef struct {
     int32_t levels;          /* >= 2                                                   */
     int32_t max_batch;       /* samples per forward / backward call                    */
 } mlb_net_cfg;
+#define MLB_NET_FEATURES 8
 typedef struct {
-    float in_mean[4], in_std[4]; /* still-water depth, tau_x/rho, tau_y/rho, C_b       */
-    float s_eta, s_q;            /* output scales: eta = s_eta y0, q = s_q (y1, y2)     */
+    float in_mean[5], in_std[5]; /* H, tau_x/rho, tau_y/rho, |tau|/rho, C_b            */
+    float s_eta, s_q;            /* output scales: eta = s_eta f y0, q = s_q f (y1, y2) */
+    float tau_ref;               /* > 0: f = |tau|/rho / tau_ref per basin (steady set-up
+                                  * and circulation grow with the stress); 0: f = 1    */
 } mlb_net_norm;
 typedef struct { float lr, beta1, beta2, eps, weight_decay; } mlb_adamw_cfg;
 
@@ -257,7 +275,7 @@ mlb_status mlb_net_get_params(mlb_net* net, float* host, int64_t n);
 mlb_status mlb_net_set_params(mlb_net* net, const float* host, int64_t n);
 mlb_status mlb_net_set_norm(mlb_net* net, const mlb_net_norm* norm);
 mlb_status mlb_net_get_norm(const mlb_net* net, mlb_net_norm* norm);
-/* Forward pass: x [n][height][width][6] FP32 (device) -> y [n][height][width][3] FP32 (device). */
+/* Forward pass: x [n][height][width][MLB_NET_FEATURES] FP32 (device) -> y [n][height][width][3] FP32 (device). */
 mlb_status mlb_net_forward(mlb_net* net, const float* x_dev, int32_t n, float* y_dev);
 /* Forward + backward of the masked MSE against targets t [n][h][w][3] (device);
  * mask [n][h][w] (device, may be NULL = all ones) with mask_count = its sum.
@@ -268,8 +286,9 @@ mlb_status mlb_net_loss_grad(mlb_net* net, const float* x_dev, const float* t_de
 /* One AdamW step (decoupled weight decay) with the last gradient. */
 mlb_status mlb_net_adamw(mlb_net* net, const mlb_adamw_cfg* cfg);
 /* Features of a grid (its still-water depth and forcing, normalised) into
- * x_dev [height][width][6]; targets (its current state, normalised) into
- * t_dev [height][width][3].  The grid must be height x width. */
+ * x_dev [height][width][MLB_NET_FEATURES]; targets (its current state
+ * divided by the output scales; 0 when f = 0) into t_dev [height][width][3].
+ * The grid must be height x width. */
 mlb_status mlb_net_features(mlb_net* net, mlb_grid* g, float* x_dev);
 mlb_status mlb_net_targets(mlb_net* net, mlb_grid* g, float* t_dev);
 /* Warm start: writes the net's guess into the grid's state.  The guess's mean
@@ -280,7 +299,7 @@ mlb_status mlb_net_infer(mlb_net* net, mlb_grid* g);
 mlb_status mlb_net_save(const mlb_net* net, const char* path);
 mlb_status mlb_net_load(mlb_net* net, const char* path);
 
-/* Training over a dataset resident in device memory: x [n][height][width][6],
+/* Training over a dataset resident in device memory: x [n][height][width][MLB_NET_FEATURES],
  * t [n][height][width][3], optional mask [n][height][width] (NULL = all ones).
  * Each epoch visits the samples in a fresh random order (seeded) in
  * minibatches of `batch` (the last, smaller one included); each minibatch is
@@ -311,6 +330,8 @@ mlb_status mlb_net_train(mlb_net* net, const float* x_dev, const float* t_dev, c
  *      step counter) and run with mlb_run_steady;
  *   4. on convergence, guess_err receives the relative L2 distance of the
  *      guess to the converged state per field (eta, hu, hv).
+ * A stall (mlb_set_stall_checks) of the run from the guess is not a
+ * fallback: the guess led to the same steady state, held at FP32's floor.
  * Returns MLB_OK when converged, else the status of the last run. */
 typedef enum {
     MLB_WARM_NONE = 0,            /* the guess was used                              */

@@ -361,6 +361,7 @@ const char* mlb_status_str(mlb_status s)
     case MLB_E_NONFINITE: return "non-finite value or dry node";
     case MLB_E_STATE: return "invalid state for this call";
     case MLB_E_NOTCONVERGED: return "not converged";
+    case MLB_E_STALLED: return "residual stalled";
     }
     return "unknown status";
 }
@@ -408,6 +409,13 @@ mlb_status mlb_ctx_destroy(mlb_ctx* c)
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_stall_checks(mlb_ctx* c, int32_t checks)
+{
+    if (!c || checks < 0) return fail(MLB_E_INVAL, "bad stall setting");
+    c->stall_checks = checks;
     return MLB_OK;
 }
 
@@ -685,6 +693,8 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
     mlb_ctx* c = g->ctx;
     const int64_t start = g->step;
     mlb_diag_t d{};
+    double best = INFINITY;
+    int since = 0;
     while (g->step - start < max_steps) {
         const int64_t n = std::min<int64_t>(check_every, max_steps - (g->step - start));
         int64_t nl = 0;
@@ -695,6 +705,9 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
         if (out) *out = d;
         if (d.nonfinite) return fail(MLB_E_NONFINITE, "non-finite value or dry node");
         if (d.residual <= tol) return MLB_OK;
+        if (d.residual < best) { best = d.residual; since = 0; }
+        else if (c->stall_checks > 0 && best <= kStallBand * tol && ++since >= c->stall_checks)
+            return fail(MLB_E_STALLED, "residual stalled");
     }
     return fail(MLB_E_NOTCONVERGED, "max_steps reached");
 }

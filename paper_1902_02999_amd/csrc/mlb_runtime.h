@@ -12,6 +12,11 @@ namespace mlb {
 // Sets the calling thread's last error message and returns s.
 mlb_status fail(mlb_status s, const std::string& msg);
 
+// Stall rule of steady-state runs: it counts checks without a new lowest
+// residual only once that lowest residual is within this factor of the
+// tolerance (a run from rest passes through transient minima far above it).
+constexpr double kStallBand = 10.0;
+
 // Sets a grid's step counter (host and device copies); syncs the stream.
 mlb_status grid_set_step(mlb_grid* g, int64_t s);
 
@@ -79,6 +84,7 @@ struct mlb_ctx {
     std::string arch;          // gcnArchName, for autotuner cache keys
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
+    int stall_checks = 0;      // 0: off
 };
 
 struct mlb_grid {

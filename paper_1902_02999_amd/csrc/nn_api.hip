@@ -194,7 +194,7 @@ mlb_status build(mlb_net* n)
     CHK(dalloc(n, &n->cpart, (size_t)256 * std::max(n->ch(Lv - 1), c.out_ch)));
     CHK(dalloc(n, &n->lpart, (px(0) * c.out_ch + 255) / 256 + 1));
     CHK(dalloc(n, &n->dloss, 1));
-    CHK(dalloc(n, &n->xstage, (size_t)c.height * c.width * 6));
+    CHK(dalloc(n, &n->xstage, (size_t)c.height * c.width * nn::kNetFeatures));
     const size_t hw = (size_t)c.height * c.width;
     CHK(dalloc(n, &n->cold, 3 * hw));
     CHK(dalloc(n, &n->guess, 3 * hw));
@@ -263,7 +263,7 @@ mlb_status forward(mlb_net* n, const float* x, int nb)
     const int Lv = c.levels;
     hipStream_t s = n->ctx->stream;
     const int64_t P0 = (int64_t)nb * c.height * c.width;
-    HIPCHK(nn::pack_input(x, P0, 6, c.in_ch, n->xin, s));
+    HIPCHK(nn::pack_input(x, P0, nn::kNetFeatures, c.in_ch, n->xin, s));
     for (int l = 0; l < Lv; ++l) {
         const __bf16* in = n->xin;
         int ldin = c.in_ch;
@@ -326,6 +326,13 @@ mlb_status backward(mlb_net* n, int nb)
     return MLB_OK;
 }
 
+// Per-basin output factor f: |tau|/rho / tau_ref, or 1 without stress scaling.
+double out_factor(const mlb_net* n, const mlb_grid* g)
+{
+    if (!(n->norm.tau_ref > 0)) return 1.0;
+    return std::sqrt(g->tx * g->tx + g->ty * g->ty) / (double)n->norm.tau_ref;
+}
+
 mlb_status check_grid(const mlb_net* n, const mlb_grid* g)
 {
     if (!g) return fail(MLB_E_INVAL, "grid is NULL");
@@ -354,9 +361,10 @@ mlb_status mlb_net_create(mlb_ctx* ctx, const mlb_net_cfg* cfg, uint64_t seed, m
     if (!n) return fail(MLB_E_NOMEM, "net");
     n->ctx = ctx;
     n->cfg = c;
-    for (int k = 0; k < 4; ++k) { n->norm.in_mean[k] = 0.f; n->norm.in_std[k] = 1.f; }
+    for (int k = 0; k < 5; ++k) { n->norm.in_mean[k] = 0.f; n->norm.in_std[k] = 1.f; }
     n->norm.s_eta = 1.f;
     n->norm.s_q = 1.f;
+    n->norm.tau_ref = 0.f;
     mlb_status st = build(n);
     if (st != MLB_OK) { net_free(n); delete n; return st; }
     // He-normal weights (Box-Muller on a splitmix stream), zero biases
@@ -420,9 +428,10 @@ mlb_status mlb_net_set_params(mlb_net* n, const float* host, int64_t cnt)
 mlb_status mlb_net_set_norm(mlb_net* n, const mlb_net_norm* nm)
 {
     if (!n || !nm) return fail(MLB_E_INVAL, "NULL argument");
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 5; ++k)
         if (!(nm->in_std[k] > 0)) return fail(MLB_E_INVAL, "in_std must be positive");
     if (!(nm->s_eta > 0) || !(nm->s_q > 0)) return fail(MLB_E_INVAL, "output scales must be positive");
+    if (!(nm->tau_ref >= 0)) return fail(MLB_E_INVAL, "tau_ref must be >= 0");
     n->norm = *nm;
     return MLB_OK;
 }
@@ -485,8 +494,8 @@ mlb_status mlb_net_features(mlb_net* n, mlb_grid* g, float* x)
     if (!n || !x) return fail(MLB_E_INVAL, "NULL argument");
     CHK(check_grid(n, g));
     HIPCHK(hipSetDevice(n->ctx->device));
-    HIPCHK(nn::features(g->H, g->p.nx, g->p.ny, g->ld, n->norm.in_mean, n->norm.in_std, (float)g->tx, (float)g->ty,
-                        (float)g->cb, x, n->ctx->stream));
+    HIPCHK(nn::features(g->H, g->p.nx, g->p.ny, g->ld, n->norm.in_mean, n->norm.in_std, g->tx, g->ty, g->cb,
+                        n->norm.tau_ref, x, n->ctx->stream));
     return MLB_OK;
 }
 
@@ -495,8 +504,10 @@ mlb_status mlb_net_targets(mlb_net* n, mlb_grid* g, float* t)
     if (!n || !t) return fail(MLB_E_INVAL, "NULL argument");
     CHK(check_grid(n, g));
     HIPCHK(hipSetDevice(n->ctx->device));
-    HIPCHK(nn::targets(g->eta[g->cur], g->qx[g->cur], g->qy[g->cur], g->p.nx, g->p.ny, g->ld, n->norm.s_eta,
-                       n->norm.s_q, t, n->ctx->stream));
+    const double f = out_factor(n, g);
+    HIPCHK(nn::targets(g->eta[g->cur], g->qx[g->cur], g->qy[g->cur], g->p.nx, g->p.ny, g->ld,
+                       f > 0 ? (float)(1.0 / (n->norm.s_eta * f)) : 0.0f,
+                       f > 0 ? (float)(1.0 / (n->norm.s_q * f)) : 0.0f, t, n->ctx->stream));
     return MLB_OK;
 }
 
@@ -506,12 +517,14 @@ mlb_status mlb_net_infer(mlb_net* n, mlb_grid* g)
     CHK(check_grid(n, g));
     HIPCHK(hipSetDevice(n->ctx->device));
     hipStream_t s = n->ctx->stream;
-    HIPCHK(nn::features(g->H, g->p.nx, g->p.ny, g->ld, n->norm.in_mean, n->norm.in_std, (float)g->tx, (float)g->ty,
-                        (float)g->cb, n->xstage, s));
+    HIPCHK(nn::features(g->H, g->p.nx, g->p.ny, g->ld, n->norm.in_mean, n->norm.in_std, g->tx, g->ty, g->cb,
+                        n->norm.tau_ref, n->xstage, s));
     CHK(forward(n, n->xstage, 1));
     int wall4[4];
     for (int k = 0; k < 4; ++k) wall4[k] = g->p.edge[k] == MLB_EDGE_WALL;
-    HIPCHK(nn::guess_to_state(n->yout, g->p.nx, g->p.ny, g->ld, n->norm.s_eta, n->norm.s_q, wall4, n->dloss,
+    const double f = out_factor(n, g);
+    HIPCHK(nn::guess_to_state(n->yout, g->p.nx, g->p.ny, g->ld, (float)(n->norm.s_eta * f),
+                              (float)(n->norm.s_q * f), wall4, n->dloss,
                               g->eta[0], g->qx[0], g->qy[0], g->eta[1], g->qx[1], g->qy[1], s));
     return MLB_OK;
 }
@@ -523,7 +536,7 @@ mlb_status mlb_net_save(const mlb_net* n, const char* path)
     CHK(mlb_net_get_params(const_cast<mlb_net*>(n), th.data(), n->np));
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(MLB_E_INVAL, std::string("cannot open ") + path);
-    const char magic[8] = {'M', 'L', 'B', 'N', 'E', 'T', '1', 0};
+    const char magic[8] = {'M', 'L', 'B', 'N', 'E', 'T', '2', 0};
     bool ok = std::fwrite(magic, 8, 1, f) == 1 && std::fwrite(&n->cfg, sizeof(n->cfg), 1, f) == 1 &&
               std::fwrite(&n->norm, sizeof(n->norm), 1, f) == 1 && std::fwrite(&n->np, sizeof(n->np), 1, f) == 1 &&
               std::fwrite(th.data(), sizeof(float), th.size(), f) == th.size();
@@ -540,7 +553,7 @@ mlb_status mlb_net_load(mlb_net* n, const char* path)
     mlb_net_cfg c{};
     mlb_net_norm nm{};
     int64_t np = 0;
-    bool ok = std::fread(magic, 8, 1, f) == 1 && std::memcmp(magic, "MLBNET1", 8) == 0 &&
+    bool ok = std::fread(magic, 8, 1, f) == 1 && std::memcmp(magic, "MLBNET2", 8) == 0 &&
               std::fread(&c, sizeof(c), 1, f) == 1 && std::fread(&nm, sizeof(nm), 1, f) == 1 &&
               std::fread(&np, sizeof(np), 1, f) == 1;
     std::vector<float> th;
@@ -568,7 +581,7 @@ mlb_status mlb_net_train(mlb_net* n, const float* x, const float* t, const float
     HIPCHK(hipSetDevice(n->ctx->device));
     hipStream_t s = n->ctx->stream;
     const size_t hw = (size_t)n->cfg.height * n->cfg.width;
-    const size_t sx = hw * 6, st = hw * 3;
+    const size_t sx = hw * nn::kNetFeatures, st = hw * 3;
     const int B = c.batch;
     // staging of one minibatch, per-sample mask sums, per-epoch loss sums
     float *xb = nullptr, *tb = nullptr, *mb = nullptr;
@@ -650,7 +663,7 @@ mlb_status probe(mlb_grid* g, double tol, int64_t steps, int32_t check_every, ml
 {
     const mlb_status st = mlb_run_steady(g, tol, steps, check_every, d);
     *converged = st == MLB_OK;
-    if (st == MLB_E_NOTCONVERGED || st == MLB_OK || st == MLB_E_NONFINITE) return MLB_OK;
+    if (st == MLB_E_NOTCONVERGED || st == MLB_OK || st == MLB_E_NONFINITE || st == MLB_E_STALLED) return MLB_OK;
     return st;
 }
 
@@ -710,9 +723,11 @@ mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* n, double tol, int64_t max_s
 
     // 3. the warm run, watched for divergence
     int64_t used = 1;
+    bool stalled = false;
     if (reason == MLB_WARM_NONE && !conv) {
-        double first = -1.0, prev = d.residual;
-        int rises = 0;
+        double first = -1.0, prev = d.residual, best = d.residual;
+        int rises = 0, since = 0;
+        const int stall = n->ctx->stall_checks;
         while (used < max_steps) {
             const int64_t chunk = std::min<int64_t>(check_every, max_steps - used);
             CHK(probe(g, tol, chunk, check_every, &d, &conv));
@@ -724,13 +739,16 @@ mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* n, double tol, int64_t max_s
             rises = d.residual > prev ? rises + 1 : 0;
             prev = d.residual;
             if (rises >= 3 && d.residual > first) { reason = MLB_WARM_DIVERGING; break; }
+            if (d.residual < best) { best = d.residual; since = 0; }
+            else if (stall > 0 && best <= kStallBand * tol && ++since >= stall) { stalled = true; break; }
         }
     }
     mlb_status result = MLB_OK;
     if (reason == MLB_WARM_NONE) {
         rep->used_guess = 1;
         rep->steps = used;
-        if (!conv) result = fail(MLB_E_NOTCONVERGED, "max_steps reached");
+        if (stalled) result = fail(MLB_E_STALLED, "residual stalled");
+        else if (!conv) result = fail(MLB_E_NOTCONVERGED, "max_steps reached");
     } else {
         // 4. fallback: the cold start again
         CHK(mlb_set_state_device(g, n->cold, n->cold + hw, n->cold + 2 * hw));

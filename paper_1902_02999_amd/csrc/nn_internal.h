@@ -7,6 +7,8 @@
 namespace mlb {
 namespace nn {
 
+constexpr int kNetFeatures = 8;   // input features per pixel (MLB_NET_FEATURES)
+
 // 3x3 "same" convolution, stride 1, as an implicit GEMM.  Requirements:
 // w % 32 == 0, cin % 32 == 0, cout % 32 == 0, channel strides / offsets % 8 == 0.
 struct ConvArgs {
@@ -55,11 +57,12 @@ hipError_t f32_to_bf16(const float* src, int64_t n, __bf16* dst, hipStream_t s);
 hipError_t pack_input(const float* x, int64_t npix, int nin, int ldc, __bf16* y, hipStream_t s);
 // Features of a basin for the net: [p][6] = ((H - m0)/s0, (tx - m1)/s1, (ty - m2)/s2,
 // (cb - m3)/s3, inflow 0, wet mask 1) from the FP32 still-water depth plane (pitch ld).
-hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, float tx,
-                    float ty, float cb, float* out, hipStream_t s);
+hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, double tx,
+                    double ty, double cb, float tau_ref, float* out, hipStream_t s);
 // Targets [p][3] = (eta / s_eta, qx / s_q, qy / s_q) from the state planes (pitch ld).
-hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, int ny, int ld, float s_eta,
-                   float s_q, float* out, hipStream_t s);
+// t = (eta, qx, qy) x (inv_eta, inv_q, inv_q)
+hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, int ny, int ld, float inv_eta,
+                   float inv_q, float* out, hipStream_t s);
 // Guess from the net output [p][3]: eta = s_eta y0 - mean, q = s_q (y1, y2), q = 0 on
 // wall nodes; written into both state buffers (pitch ld).  mean over all nodes (FP64).
 // Per-sample sums of a [n][len] FP32 array in FP64 (one block per sample, fixed order).

@@ -12,6 +12,8 @@
 //   A (16 x 32):  lane holds A[l16][8 lq .. 8 lq + 7]
 //   B (32 x 16):  lane holds B[8 lq .. 8 lq + 7][l16]
 //   D (16 x 16):  lane holds D[4 lq .. 4 lq + 3][l16]
+#include <cmath>
+
 #include "nn_internal.h"
 
 namespace mlb {
@@ -524,24 +526,35 @@ namespace mlb {
 namespace nn {
 
 __global__ void features_kernel(const float* __restrict__ H, int nx, int ny, int ld, float m0, float s0,
-                                float f1, float f2, float f3, float* __restrict__ out)
+                                float f1, float f2, float f3, float f4, float* __restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)nx * ny) return;
     const int x = (int)(i % nx), y = (int)(i / nx);
-    float* o = out + i * 6;
+    float* o = out + i * kNetFeatures;
     o[0] = (H[(size_t)y * ld + x] - m0) / s0;
-    o[1] = f1; o[2] = f2; o[3] = f3;
-    o[4] = nx > 1 ? 2.0f * (float)x / (float)(nx - 1) - 1.0f : 0.0f;   // node position in [-1, 1]
-    o[5] = ny > 1 ? 2.0f * (float)y / (float)(ny - 1) - 1.0f : 0.0f;
+    o[1] = f1; o[2] = f2; o[3] = f3; o[4] = f4;
+    o[5] = nx > 1 ? 2.0f * (float)x / (float)(nx - 1) - 1.0f : 0.0f;   // node position in [-1, 1]
+    o[6] = ny > 1 ? 2.0f * (float)y / (float)(ny - 1) - 1.0f : 0.0f;
+    o[7] = 1.0f;
 }
 
-hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, float tx,
-                    float ty, float cb, float* out, hipStream_t s)
+// Per-basin channels 1..4 are uniform: computed here in FP64 and rounded once.
+hipError_t features(const float* H, int nx, int ny, int ld, const float* mean, const float* stdv, double tx,
+                    double ty, double cb, float tau_ref, float* out, hipStream_t s)
 {
+    const double mag = std::sqrt(tx * tx + ty * ty);
+    double f1, f2;
+    if (tau_ref > 0.0f) {
+        f1 = mag > 0.0 ? tx / mag : 0.0;
+        f2 = mag > 0.0 ? ty / mag : 0.0;
+    } else {
+        f1 = (tx - mean[1]) / stdv[1];
+        f2 = (ty - mean[2]) / stdv[2];
+    }
+    const double f3 = (mag - mean[3]) / stdv[3], f4 = (cb - mean[4]) / stdv[4];
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, H, nx, ny, ld,
-                       mean[0], stdv[0], (tx - mean[1]) / stdv[1], (ty - mean[2]) / stdv[2],
-                       (cb - mean[3]) / stdv[3], out);
+                       mean[0], stdv[0], (float)f1, (float)f2, (float)f3, (float)f4, out);
     return hipGetLastError();
 }
 
@@ -557,11 +570,11 @@ __global__ void targets_kernel(const float* __restrict__ eta, const float* __res
     out[i * 3 + 2] = qy[o] * iq;
 }
 
-hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, int ny, int ld, float s_eta,
-                   float s_q, float* out, hipStream_t s)
+hipError_t targets(const float* eta, const float* qx, const float* qy, int nx, int ny, int ld, float inv_eta,
+                   float inv_q, float* out, hipStream_t s)
 {
     hipLaunchKernelGGL(targets_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, eta, qx, qy, nx,
-                       ny, ld, 1.0f / s_eta, 1.0f / s_q, out);
+                       ny, ld, inv_eta, inv_q, out);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ W, E, S, N = 0, 1, 2, 3
 
 STATUS = {0: "MLB_OK", -1: "MLB_E_INVAL", -2: "MLB_E_NOMEM", -3: "MLB_E_DEVICE",
           -4: "MLB_E_UNSTABLE", -5: "MLB_E_NONFINITE", -6: "MLB_E_STATE",
-          -7: "MLB_E_NOTCONVERGED"}
+          -7: "MLB_E_NOTCONVERGED", -8: "MLB_E_STALLED"}
 
 
 class MlbError(RuntimeError):
@@ -61,8 +61,12 @@ class NetCfg(C.Structure):
                 ("base_ch", C.c_int32), ("levels", C.c_int32), ("max_batch", C.c_int32)]
 
 
+NET_FEATURES = 8   # MLB_NET_FEATURES
+
+
 class NetNorm(C.Structure):
-    _fields_ = [("in_mean", C.c_float * 4), ("in_std", C.c_float * 4), ("s_eta", C.c_float), ("s_q", C.c_float)]
+    _fields_ = [("in_mean", C.c_float * 5), ("in_std", C.c_float * 5), ("s_eta", C.c_float), ("s_q", C.c_float),
+                ("tau_ref", C.c_float)]
 
 
 class AdamWCfg(C.Structure):
@@ -144,6 +148,7 @@ SIGNATURES = {
     "mlb_net_load": (C.c_int, [_VP, C.c_char_p]),
     "mlb_net_train": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(TrainCfg), _DP]),
     "mlb_warm_start_run": (C.c_int, [_VP, _VP, C.c_double, C.c_int64, C.c_int32, C.POINTER(WarmReport)]),
+    "mlb_set_stall_checks": (C.c_int, [_VP, C.c_int32]),
 }
 
 _lib = None
@@ -202,6 +207,11 @@ class Context:
 
     def sync(self):
         _check(lib().mlb_ctx_sync(self.h), "mlb_ctx_sync")
+
+    def set_stall_checks(self, checks: int):
+        """Steady-state runs stop (stalled) after `checks` checks without a
+        new lowest residual; 0 turns the rule off."""
+        _check(lib().mlb_set_stall_checks(self.h, int(checks)), "mlb_set_stall_checks")
 
     def last_step_ms(self) -> float:
         v = C.c_double()
@@ -332,10 +342,14 @@ class Grid:
         """Returns (converged, diag dict); raises on non-finite values."""
         d = Diag()
         rc = lib().mlb_run_steady(self.h, tol, int(max_steps), int(check_every), C.byref(d))
-        if rc == -7:
-            return False, d.as_dict()
+        if rc in (-7, -8):
+            out = d.as_dict()
+            out["stalled"] = rc == -8
+            return False, out
         _check(rc, "mlb_run_steady")
-        return True, d.as_dict()
+        out = d.as_dict()
+        out["stalled"] = False
+        return True, out
 
     def close(self):
         if self.h:
@@ -427,17 +441,19 @@ class Net:
         _check(lib().mlb_net_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
                "mlb_net_set_params")
 
-    def set_norm(self, in_mean, in_std, s_eta, s_q):
+    def set_norm(self, in_mean, in_std, s_eta, s_q, tau_ref=0.0):
+        """in_mean / in_std: H, tau_x/rho, tau_y/rho, |tau|/rho, C_b."""
         nm = NetNorm()
-        for k in range(4):
+        for k in range(5):
             nm.in_mean[k], nm.in_std[k] = float(in_mean[k]), float(in_std[k])
-        nm.s_eta, nm.s_q = float(s_eta), float(s_q)
+        nm.s_eta, nm.s_q, nm.tau_ref = float(s_eta), float(s_q), float(tau_ref)
         _check(lib().mlb_net_set_norm(self.h, C.byref(nm)), "mlb_net_set_norm")
 
     def get_norm(self) -> dict:
         nm = NetNorm()
         _check(lib().mlb_net_get_norm(self.h, C.byref(nm)), "mlb_net_get_norm")
-        return {"in_mean": list(nm.in_mean), "in_std": list(nm.in_std), "s_eta": nm.s_eta, "s_q": nm.s_q}
+        return {"in_mean": list(nm.in_mean), "in_std": list(nm.in_std), "s_eta": nm.s_eta, "s_q": nm.s_q,
+                "tau_ref": nm.tau_ref}
 
     def forward(self, x, n, y):
         _check(lib().mlb_net_forward(self.h, _tensor_ptr(x), int(n), _tensor_ptr(y)), "mlb_net_forward")
@@ -480,10 +496,14 @@ class Net:
         MLB_E_NOTCONVERGED."""
         r = WarmReport()
         rc = lib().mlb_warm_start_run(grid.h, self.h, tol, int(max_steps), int(check_every), C.byref(r))
-        if rc == -7:
-            return False, r.as_dict()
+        if rc in (-7, -8):
+            out = r.as_dict()
+            out["stalled"] = rc == -8
+            return False, out
         _check(rc, "mlb_warm_start_run")
-        return True, r.as_dict()
+        out = r.as_dict()
+        out["stalled"] = False
+        return True, out
 
     def save(self, path):
         _check(lib().mlb_net_save(self.h, path.encode()), "mlb_net_save")

@@ -9,9 +9,10 @@ holds the device tensors and keeps the bookkeeping.
 Data: closed square basins drawn from the ensemble distributions (random
 bumps, wind speed and heading, Chezy coefficient), solved from rest to a
 per-step discharge residual <= tol in one batched launch per step.  Inputs:
-still-water depth, wind stress over density, bed coefficient, node position;
-targets: the steady (eta, hu, hv), each normalised by statistics of the
-training set.
+still-water depth, wind stress direction and magnitude, bed coefficient,
+node position; targets: the steady (eta, hu, hv) divided per basin by the
+stress magnitude (set-up and circulation grow with it) and by the spread of
+the training set.
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ class Dataset:
     grids: List[mlb.Grid]
     steps: List[int]
     solve_s: float
-    x: object = None      # torch CUDA [n, h, w, 6]
+    x: object = None      # torch CUDA [n, h, w, mlb.NET_FEATURES]
     t: object = None      # torch CUDA [n, h, w, 3]
     norm: dict = field(default_factory=dict)
 
@@ -85,34 +86,42 @@ def _fill(ctx, net, grids, x, t):
     ctx.sync()
 
 
-def fit_norm(ctx: mlb.Context, net: mlb.Net, grids: List[mlb.Grid], x, t, sub: int = 4) -> dict:
-    """Normalisation from raw features / targets of the training grids
-    (identity normalisation first, statistics of a strided host copy)."""
-    net.set_norm([0, 0, 0, 0], [1, 1, 1, 1], 1.0, 1.0)
+def fit_norm(ctx: mlb.Context, net: mlb.Net, grids: List[mlb.Grid], x, t, sub: int = 4,
+             stress_scaled: bool = True) -> dict:
+    """Normalisation from raw features / targets of the training grids:
+    identity normalisation first (raw H, tau_x, tau_y, |tau|, C_b in channels
+    0..4), statistics of a strided host copy.  With stress_scaled, targets
+    are divided per basin by |tau| / tau_ref (tau_ref = mean |tau|) before
+    their spread is taken."""
+    net.set_norm([0] * 5, [1] * 5, 1.0, 1.0, 0.0)
     _fill(ctx, net, grids, x, t)
-    xs = x[:, ::sub, ::sub, :4].cpu().numpy().astype(np.float64)
+    xs = x[:, ::sub, ::sub, :5].cpu().numpy().astype(np.float64)
+    mean = [float(xs[..., k].mean()) for k in range(5)]
+    std = [float(max(xs[..., k].std(), 1e-12)) for k in range(5)]
+    tau_ref = float(max(xs[..., 3].mean(), 1e-12)) if stress_scaled else 0.0
+    net.set_norm(mean, std, 1.0, 1.0, tau_ref)
+    _fill(ctx, net, grids, x, t)
     ts = t[:, ::sub, ::sub, :].cpu().numpy().astype(np.float64)
-    mean = [float(xs[..., k].mean()) for k in range(4)]
-    std = [float(max(xs[..., k].std(), 1e-12)) for k in range(4)]
     s_eta = float(max(ts[..., 0].std(), 1e-12))
     s_q = float(max(ts[..., 1:].std(), 1e-12))
-    norm = {"in_mean": mean, "in_std": std, "s_eta": s_eta, "s_q": s_q}
-    net.set_norm(mean, std, s_eta, s_q)
+    norm = {"in_mean": mean, "in_std": std, "s_eta": s_eta, "s_q": s_q, "tau_ref": tau_ref}
+    net.set_norm(mean, std, s_eta, s_q, tau_ref)
     return norm
 
 
 def build_dataset(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: float = 1e-6,
-                  check_every: int = 200, norm: Optional[dict] = None, log=print) -> Dataset:
+                  check_every: int = 200, norm: Optional[dict] = None, stress_scaled: bool = True,
+                  log=print) -> Dataset:
     import torch
     grids, steps, solve_s = solve_steady(ctx, specs, tol, check_every=check_every)
     log("solved %d basins in %.1f s (steps %d..%d)" % (len(specs), solve_s, min(steps), max(steps)))
     n, h, w = len(specs), specs[0].ny, specs[0].nx
-    x = torch.empty((n, h, w, 6), dtype=torch.float32, device="cuda")
+    x = torch.empty((n, h, w, mlb.NET_FEATURES), dtype=torch.float32, device="cuda")
     t = torch.empty((n, h, w, 3), dtype=torch.float32, device="cuda")
     if norm is None:
-        norm = fit_norm(ctx, net, grids, x, t)
+        norm = fit_norm(ctx, net, grids, x, t, stress_scaled=stress_scaled)
     else:
-        net.set_norm(norm["in_mean"], norm["in_std"], norm["s_eta"], norm["s_q"])
+        net.set_norm(norm["in_mean"], norm["in_std"], norm["s_eta"], norm["s_q"], norm.get("tau_ref", 0.0))
     _fill(ctx, net, grids, x, t)
     return Dataset(specs, grids, steps, solve_s, x, t, norm)
 
@@ -128,9 +137,13 @@ def train(net: mlb.Net, data: Dataset, ts: TrainSpec, log=print) -> List[float]:
 
 
 def evaluate(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: float = 1e-6,
-             max_steps: int = 2_000_000, check_every: int = 100, log=print) -> List[dict]:
+             max_steps: int = 2_000_000, check_every: int = 100, stall_checks: int = 100,
+             log=print) -> List[dict]:
     """Per basin: cold run from rest (mlb_run_steady) and warm run
-    (mlb_warm_start_run, inference included), single-basin graph mode."""
+    (mlb_warm_start_run, inference included), single-basin graph mode.  Both
+    stop at R <= tol or under the same stall rule (`stall_checks` checks
+    without a new lowest residual: the FP32 noise floor of a weak flow)."""
+    ctx.set_stall_checks(stall_checks)
     out = []
     for s in specs:
         g = mlb.grid_from_spec(ctx, s)
@@ -144,7 +157,9 @@ def evaluate(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: float = 
         ok_w, rep = net.warm_start_run(g, tol, max_steps, check_every)
         g.close()
         r = {"name": s.name, "cold_s": cold_s, "cold_steps": int(dc["step"]), "cold_ok": ok_c,
+             "cold_stalled": dc["stalled"], "cold_residual": dc["residual"],
              "warm_s": rep["wall_s"], "warm_steps": int(rep["steps_total"]), "warm_ok": ok_w,
+             "warm_stalled": rep["stalled"], "warm_residual": rep["diag"]["residual"],
              "used_guess": int(rep["used_guess"]), "fallback": int(rep["fallback"]),
              "infer_ms": rep["infer_ms"], "r0_guess": rep["r0_guess"], "r0_cold": rep["r0_cold"],
              "guess_err": rep["guess_err"]}
@@ -163,6 +178,8 @@ def summary(rows: List[dict]) -> dict:
             "cold_steps_median": float(np.median([r["cold_steps"] for r in rows])),
             "warm_steps_median": float(np.median([r["warm_steps"] for r in rows])),
             "fallbacks": int(sum(1 for r in rows if not r["used_guess"])),
+            "stalled_cold": int(sum(1 for r in rows if r["cold_stalled"])),
+            "stalled_warm": int(sum(1 for r in rows if r["warm_stalled"])),
             "guess_err_median": [float(v) for v in np.nanmedian(ge, axis=0)],
             "infer_ms_median": float(np.median([r["infer_ms"] for r in rows]))}
 
@@ -179,6 +196,8 @@ def main(argv=None):
     ap.add_argument("--save", default=None, help="write the trained net here")
     ap.add_argument("--load", default=None, help="skip training: load this net (its normalisation included)")
     ap.add_argument("--out", default=None, help="write the JSON summary here")
+    ap.add_argument("--global-scales", action="store_true",
+                    help="scale targets by global spreads only (no per-basin stress scaling)")
     args = ap.parse_args(argv)
 
     def log(*a):
@@ -192,7 +211,8 @@ def main(argv=None):
     if args.load:
         net.load(args.load)
     else:
-        data = build_dataset(ctx, net, wl.learned_set(args.train, 2999, n=args.n), args.tol, log=log)
+        data = build_dataset(ctx, net, wl.learned_set(args.train, 2999, n=args.n), args.tol,
+                             stress_scaled=not args.global_scales, log=log)
         result["train_solve_s"] = data.solve_s
         result["train_steps_median"] = float(np.median(data.steps))
         result["norm"] = data.norm

@@ -18,6 +18,8 @@ from paper_1902_02999_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
+NF = 8   # input features per pixel (MLB_NET_FEATURES)
+
 CFGS = [dict(H=64, W=64, in_ch=32, base=32, levels=2, N=2),
         dict(H=32, W=128, in_ch=32, base=32, levels=3, N=3)]
 
@@ -56,11 +58,11 @@ def make_net(ctx, cfg, seed=5, max_batch=None):
 def inputs(cfg, seed=7):
     rng = np.random.default_rng(seed)
     N, H, W = cfg["N"], cfg["H"], cfg["W"]
-    x6 = bf16_round(rng.standard_normal((N, H, W, 6))).astype(np.float64)
+    x6 = bf16_round(rng.standard_normal((N, H, W, NF))).astype(np.float64)
     t = rng.standard_normal((N, H, W, 3))
     mask = (rng.uniform(size=(N, H, W)) > 0.25).astype(np.float64)
     xo = np.zeros((N, H, W, cfg["in_ch"]))
-    xo[..., :6] = x6
+    xo[..., :NF] = x6
     return x6, xo, t, mask
 
 
@@ -199,7 +201,7 @@ def test_training_reduces_loss(ctx):
 def test_save_load_roundtrip(ctx, tmp_path):
     cfg = CFGS[0]
     net, th = make_net(ctx, cfg)
-    net.set_norm([1.0, 2.0, 3.0, 4.0], [0.5, 0.25, 2.0, 8.0], 0.125, 3.0)
+    net.set_norm([1.0, 2.0, 3.0, 4.0, 5.0], [0.5, 0.25, 2.0, 8.0, 4.0], 0.125, 3.0, 1e-4)
     p = str(tmp_path / "net.bin")
     net.save(p)
     other, _ = make_net(ctx, cfg, seed=99)
@@ -229,62 +231,92 @@ def test_bad_configs_rejected(ctx):
 
 def test_features_targets_infer(ctx):
     """Features of a grid, targets from its state, and the warm-start write
-    (mean surface perturbation removed, zero discharge on walls)."""
+    (mean surface perturbation removed, zero discharge on walls), with and
+    without per-basin stress scaling."""
     import torch
     import oracle
-    from paper_1902_02999_amd import mlb
     spec = wl.learned_set(1, 4242, n=64)[0]
-    g = mlb.grid_from_spec(ctx, spec)
-    net, _ = make_net(ctx, dict(H=64, W=64, in_ch=32, base=32, levels=2), max_batch=1)
-    mean = [2.0, 1e-4, -2e-4, 0.003]
-    std = [0.1, 3e-4, 5e-4, 0.002]
-    net.set_norm(mean, std, 0.01, 0.05)
-    x = torch.empty((64, 64, 6), dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    net.features(g, x)
-    ctx.sync()
-    xf = x.cpu().numpy().astype(np.float64)
     H = spec.H
     tx, ty = oracle.wind_stress(*spec.wind_speed)
     cb = oracle.bed_coeff(spec.chezy)
-    assert np.abs(xf[..., 0] - (H - mean[0]) / std[0]).max() <= 1e-5 * np.abs(H / std[0]).max()
-    for k, f in ((1, tx), (2, ty), (3, cb)):
-        assert abs(xf[0, 0, k] - (f - mean[k]) / std[k]) <= 1e-5 * (abs(f / std[k]) + 1), k
-        assert np.all(xf[..., k] == xf[0, 0, k])
-    lin = np.linspace(-1.0, 1.0, 64)
-    assert np.abs(xf[..., 4] - lin[None, :]).max() <= 1e-6
-    assert np.abs(xf[..., 5] - lin[:, None]).max() <= 1e-6
+    mag = np.hypot(tx, ty)
+    mean = [2.0, 1e-4, -2e-4, 3e-4, 0.003]
+    std = [0.1, 3e-4, 5e-4, 2e-4, 0.002]
+    for tau_ref in (0.0, 2.5e-4):
+        from paper_1902_02999_amd import mlb
+        g = mlb.grid_from_spec(ctx, spec)
+        net, _ = make_net(ctx, dict(H=64, W=64, in_ch=32, base=32, levels=2), max_batch=1)
+        net.set_norm(mean, std, 0.01, 0.05, tau_ref)
+        f = mag / tau_ref if tau_ref > 0 else 1.0
+        x = torch.empty((64, 64, NF), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        net.features(g, x)
+        ctx.sync()
+        xf = x.cpu().numpy().astype(np.float64)
+        assert np.abs(xf[..., 0] - (H - mean[0]) / std[0]).max() <= 1e-5 * np.abs(H / std[0]).max()
+        exp = [(tx / mag, ty / mag) if tau_ref > 0 else ((tx - mean[1]) / std[1], (ty - mean[2]) / std[2])]
+        exp = list(exp[0]) + [(mag - mean[3]) / std[3], (cb - mean[4]) / std[4]]
+        for k, v in zip((1, 2, 3, 4), exp):
+            assert abs(xf[0, 0, k] - v) <= 1e-6 * (abs(v) + 1), (tau_ref, k, xf[0, 0, k], v)
+            assert np.all(xf[..., k] == xf[0, 0, k])
+        lin = np.linspace(-1.0, 1.0, 64)
+        assert np.abs(xf[..., 5] - lin[None, :]).max() <= 1e-6
+        assert np.abs(xf[..., 6] - lin[:, None]).max() <= 1e-6
+        assert np.all(xf[..., 7] == 1.0)
 
-    # targets of a seeded state
-    h0, qx0, qy0 = wl.seeded_state(spec, 3)
-    g.set_state(h0, qx0, qy0)
-    t = torch.empty((64, 64, 3), dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    net.targets(g, t)
-    ctx.sync()
-    tf = t.cpu().numpy().astype(np.float64)
-    assert np.abs(tf[..., 0] - (h0 - H) / 0.01).max() <= 1e-4 * np.abs((h0 - H) / 0.01).max() + 1e-3
-    assert np.abs(tf[..., 1] - qx0 / 0.05).max() <= 1e-5 * np.abs(qx0 / 0.05).max() + 1e-6
-    assert np.abs(tf[..., 2] - qy0 / 0.05).max() <= 1e-5 * np.abs(qy0 / 0.05).max() + 1e-6
+        # targets of a seeded state
+        h0, qx0, qy0 = wl.seeded_state(spec, 3)
+        g.set_state(h0, qx0, qy0)
+        t = torch.empty((64, 64, 3), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        net.targets(g, t)
+        ctx.sync()
+        tf = t.cpu().numpy().astype(np.float64)
+        se, sq = 0.01 * f, 0.05 * f
+        assert np.abs(tf[..., 0] - (h0 - H) / se).max() <= 1e-4 * np.abs((h0 - H) / se).max() + 1e-3
+        assert np.abs(tf[..., 1] - qx0 / sq).max() <= 1e-5 * np.abs(qx0 / sq).max() + 1e-6
+        assert np.abs(tf[..., 2] - qy0 / sq).max() <= 1e-5 * np.abs(qy0 / sq).max() + 1e-6
 
-    # inference: y = net(features); eta = s_eta y0 - mean, q = s_q y12, walls q = 0
-    y = torch.empty((1, 64, 64, 3), dtype=torch.float32, device="cuda")
-    net.forward(x.reshape(1, 64, 64, 6), 1, y)
-    ctx.sync()
-    yf = y.cpu().numpy()[0].astype(np.float64)
+        # inference: y = net(features); eta = s_eta f y0 - mean, q = s_q f y12, walls q = 0
+        y = torch.empty((1, 64, 64, 3), dtype=torch.float32, device="cuda")
+        net.forward(x.reshape(1, 64, 64, NF), 1, y)
+        ctx.sync()
+        yf = y.cpu().numpy()[0].astype(np.float64)
+        net.infer(g)
+        h, qx, qy = g.get_state()
+        eta_exp = se * yf[..., 0]
+        eta_exp -= eta_exp.mean()
+        assert np.abs((h - H) - eta_exp).max() <= 1e-5 * (np.abs(eta_exp).max() + 1e-3 * se)
+        # volume kept: sum of eta is zero to FP32 rounding of the stored fields
+        assert abs((h - H).sum()) <= 64 * 64 * 1e-6 * (np.abs(eta_exp).max() + 2.0)
+        inner = (slice(1, -1), slice(1, -1))
+        assert np.abs(qx[inner] - sq * yf[..., 1][inner]).max() <= 1e-6 * (np.abs(yf[..., 1]).max() * sq + 1e-6)
+        for a in (qx, qy):
+            assert np.all(a[0, :] == 0) and np.all(a[-1, :] == 0) and np.all(a[:, 0] == 0) and np.all(a[:, -1] == 0)
+        # the written state steps finitely
+        g.step(10)
+        assert not g.diag()["nonfinite"]
+        net.close()
+        g.close()
+
+
+def test_no_wind_guess_is_still_water(ctx):
+    """With stress scaling, a basin without wind gets the exact still-water guess."""
+    import torch
+    from paper_1902_02999_amd import mlb
+    spec = wl.learned_set(1, 4243, n=64)[0]
+    spec.wind_speed = (0.0, 0.0)
+    g = mlb.grid_from_spec(ctx, spec)
+    net, _ = make_net(ctx, dict(H=64, W=64, in_ch=32, base=32, levels=2), max_batch=1)
+    net.set_norm([2.0, 0, 0, 3e-4, 0.003], [0.1, 1, 1, 2e-4, 0.002], 0.01, 0.05, 2.5e-4)
+    g.set_state(*wl.seeded_state(spec, 4))
     net.infer(g)
     h, qx, qy = g.get_state()
-    eta_exp = 0.01 * yf[..., 0]
-    eta_exp -= eta_exp.mean()
-    assert np.abs((h - H) - eta_exp).max() <= 1e-5 * (np.abs(eta_exp).max() + 1e-3)
-    # volume kept: sum of eta is zero to FP32 rounding of the stored fields
-    assert abs((h - H).sum()) <= 64 * 64 * 1e-6 * (np.abs(eta_exp).max() + 2.0)
-    inner = (slice(1, -1), slice(1, -1))
-    assert np.abs(qx[inner] - 0.05 * yf[..., 1][inner]).max() <= 1e-6 * (np.abs(yf[..., 1]).max() * 0.05 + 1e-6)
-    for a in (qx, qy):
-        assert np.all(a[0, :] == 0) and np.all(a[-1, :] == 0) and np.all(a[:, 0] == 0) and np.all(a[:, -1] == 0)
-    # the written state steps finitely
-    g.step(10)
-    assert not g.diag()["nonfinite"]
+    assert np.all(qx == 0) and np.all(qy == 0)
+    assert np.abs(h - spec.H).max() == 0.0
+    t = torch.empty((64, 64, 3), dtype=torch.float32, device="cuda")
+    net.targets(g, t)
+    ctx.sync()
+    assert torch.all(t == 0)
     net.close()
     g.close()

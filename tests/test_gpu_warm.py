@@ -57,7 +57,8 @@ def test_training_lowers_loss_and_is_reproducible(ctx, trained):
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0], losses
     other = small_net(ctx)
-    other.set_norm(data.norm["in_mean"], data.norm["in_std"], data.norm["s_eta"], data.norm["s_q"])
+    other.set_norm(data.norm["in_mean"], data.norm["in_std"], data.norm["s_eta"], data.norm["s_q"],
+                   data.norm["tau_ref"])
     l2 = ws.train(other, data, ws.TrainSpec(epochs=30, batch=4, lr=2e-3, lr_min=1e-4, warmup_steps=10), log=say)
     assert l2 == losses
     assert np.array_equal(other.get_params(), net.get_params())
@@ -136,10 +137,10 @@ def test_fallback_is_the_cold_run(ctx, trained, kind):
     nm = data.norm
     if kind == "nan_weights":
         bad.set_params(np.full(bad.nparam, np.nan, np.float32))
-        bad.set_norm(nm["in_mean"], nm["in_std"], nm["s_eta"], nm["s_q"])
+        bad.set_norm(nm["in_mean"], nm["in_std"], nm["s_eta"], nm["s_q"], nm["tau_ref"])
     else:
         bad.set_params(net0.get_params())
-        bad.set_norm(nm["in_mean"], nm["in_std"], 5000.0 * max(nm["s_eta"], 0.01), nm["s_q"])
+        bad.set_norm(nm["in_mean"], nm["in_std"], 5000.0 * max(nm["s_eta"], 0.01), nm["s_q"], nm["tau_ref"])
     spec = wl.learned_set(1, 3002, n=N)[0]
     dc, (hc, qxc, qyc) = cold_run(ctx, spec)
     g = mlb.grid_from_spec(ctx, spec)
@@ -185,3 +186,45 @@ def test_warm_run_argument_errors(ctx, trained):
         net.warm_start_run(g, TOL, 1000, 100)    # grid inside a live batch
     b.close()
     g.close()
+
+
+def test_stall_rule_stops_at_the_noise_floor(ctx, trained):
+    """A tolerance under FP32's noise floor (but within the stall band of it)
+    stalls instead of running to max_steps; the warm run reports the stall
+    without falling back.  The floor is measured first: the lowest residual
+    of 50 checks once the flow has settled."""
+    from paper_1902_02999_amd import mlb
+    net = trained[0]
+    spec = wl.learned_set(1, 3005, n=N)[0]
+    g = mlb.grid_from_spec(ctx, spec)
+    ok, d = g.run_steady(1e-6, 500_000, 100)
+    assert ok
+    res = []
+    for _ in range(50):
+        ok, d = g.run_steady(0.0, 100, 100)
+        res.append(d["residual"])
+    g.close()
+    tol = min(res) / 8.0
+    say("floor", min(res), max(res), "tol", tol)
+    ctx.set_stall_checks(20)
+    try:
+        g = mlb.grid_from_spec(ctx, spec)
+        ok, d = g.run_steady(tol, 500_000, 100)
+        say("cold stall at", d["step"], d["residual"])
+        assert not ok and d["stalled"] and d["step"] < 500_000
+        g.close()
+        g = mlb.grid_from_spec(ctx, spec)
+        ok, rep = net.warm_start_run(g, tol, 500_000, 100)
+        say("warm stall at", rep["steps_total"], rep["diag"]["residual"])
+        assert not ok and rep["stalled"] and rep["used_guess"] == 1 and rep["fallback"] == mlb.WARM_NONE
+        assert rep["steps_total"] < 500_000
+        g.close()
+        # a tolerance far below the floor never enters the band: plain max_steps
+        g = mlb.grid_from_spec(ctx, spec)
+        ok, d = g.run_steady(1e-12, 20_000, 100)
+        assert not ok and not d["stalled"] and d["step"] == 20_000
+        g.close()
+    finally:
+        ctx.set_stall_checks(0)
+    with pytest.raises(mlb.MlbError):
+        ctx.set_stall_checks(-1)
