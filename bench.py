@@ -90,9 +90,14 @@ def main():
                     help="steps per kernel pass when not autotuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default it picks tile rows and the CU cap before timing)")
-    ap.add_argument("--workload", default="bump", choices=["bump", "ensemble", "lake_steady"],
+    ap.add_argument("--workload", default="bump", choices=["bump", "ensemble", "lake_steady", "warm_start"],
                     help="bump: 4096^2 channel (default line); ensemble: 512 basins 64^2..512^2 in "
-                         "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6")
+                         "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6; "
+                         "warm_start: learned warm start vs cold start on held-out 256^2 basins")
+    ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
+    ap.add_argument("--ws-train", type=int, default=512, help="warm_start: training basins")
+    ap.add_argument("--ws-epochs", type=int, default=40, help="warm_start: training epochs")
+    ap.add_argument("--ws-held-out", type=int, default=20, help="warm_start: held-out basins timed")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the step runs on a single MI355X); "
@@ -113,6 +118,8 @@ def main():
         return bench_ensemble(args, ctx, copy_gbps)
     if args.workload == "lake_steady":
         return bench_lake_steady(args, ctx)
+    if args.workload == "warm_start":
+        return bench_warm_start(args, ctx)
     spec = wl.bump_channel(args.n)
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
@@ -242,6 +249,43 @@ def bench_lake_steady(args, ctx):
                       "higher_is_better": False, "converged": ok, "steps": d["step"],
                       "residual": d["residual"], "t_model_s": d["t"],
                       "config": {"workload": spec.name, "nodes": spec.nodes}}), flush=True)
+
+
+def bench_warm_start(args, ctx):
+    """Wall seconds to R <= 1e-6 on held-out 256^2 basins (seed 3000): cold
+    start from rest vs the learned warm start (inference included), one basin
+    at a time in graph mode, both under the same stall rule."""
+    from paper_1902_02999_amd import mlb, warmstart as ws, workloads as wl
+    spec = ws.NetSpec()
+    net = mlb.Net(ctx, spec.n, spec.n, base_ch=spec.base_ch, levels=spec.levels, in_ch=spec.in_ch,
+                  max_batch=spec.max_batch, seed=2999)
+    train = {}
+    if args.net:
+        net.load(args.net)
+        train["loaded"] = os.path.basename(args.net)
+    else:
+        data = ws.build_dataset(ctx, net, wl.learned_set(args.ws_train, 2999, n=spec.n), 1e-6,
+                                log=lambda *a: print(*a, file=sys.stderr, flush=True))
+        for g in data.grids:
+            g.close()
+        data.grids = []
+        t0 = time.perf_counter()
+        losses = ws.train(net, data, ws.TrainSpec(epochs=args.ws_epochs), log=lambda *a: None)
+        train = {"basins": args.ws_train, "epochs": args.ws_epochs, "solve_s": round(data.solve_s, 1),
+                 "train_s": round(time.perf_counter() - t0, 1), "loss_first": round(losses[0], 4),
+                 "loss_last": round(losses[-1], 4)}
+        del data
+    rows = ws.evaluate(ctx, net, wl.learned_set(args.ws_held_out, 3000, n=spec.n), 1e-6,
+                       log=lambda *a: None)
+    sm = ws.summary(rows)
+    net.close()
+    ctx.close()
+    print(json.dumps({"metric": "wall_s_to_residual_1e-6_warm", "value": round(sm["warm_s_total"], 3), "unit": "s",
+                      "higher_is_better": False, "cold_s": round(sm["cold_s_total"], 3),
+                      "speedup": round(sm["speedup_total"], 3), "speedup_median": round(sm["speedup_median"], 3),
+                      "n_gpus": 1, "dtype": "f32 step, bf16 net (fp32 accumulation)", "data": "synthetic",
+                      "config": {"workload": "learned_warm_start_256", "held_out": args.ws_held_out,
+                                 "train": train, "summary": sm}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -291,10 +291,12 @@ mlb_status mlb_net_adamw(mlb_net* net, const mlb_adamw_cfg* cfg);
  * The grid must be height x width. */
 mlb_status mlb_net_features(mlb_net* net, mlb_grid* g, float* x_dev);
 mlb_status mlb_net_targets(mlb_net* net, mlb_grid* g, float* t_dev);
-/* Warm start: writes the net's guess into the grid's state.  The guess's mean
- * surface perturbation is removed so the basin holds its still-water volume
- * (closed basins conserve it, so the steady state has that volume), and
- * discharge is zero on wall nodes. */
+/* Warm start: writes the net's guess into the grid's state.  The net output
+ * is smoothed by the 3x3 binomial filter (edges clamped; it removes
+ * grid-scale content the step damps only slowly), its mean surface
+ * perturbation is removed so the basin holds its still-water volume (closed
+ * basins conserve it, so the steady state has that volume), and discharge
+ * is zero on wall nodes. */
 mlb_status mlb_net_infer(mlb_net* net, mlb_grid* g);
 mlb_status mlb_net_save(const mlb_net* net, const char* path);
 mlb_status mlb_net_load(mlb_net* net, const char* path);

@@ -74,7 +74,7 @@ hipError_t add_f64(const double* src, double* dst, hipStream_t s);
 hipError_t diff_norms3(const float* a, const float* b, int64_t n, int64_t stride, double* part, double* out,
                        hipStream_t s);
 hipError_t guess_to_state(const float* y, int nx, int ny, int ld, float s_eta, float s_q, const int* wall4,
-                          double* scratch, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
+                          double* scratch, float* ys, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
                           float* qy1, hipStream_t s);
 
 }  // namespace nn

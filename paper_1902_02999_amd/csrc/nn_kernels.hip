@@ -609,10 +609,32 @@ __global__ void guess_write_kernel(const float* __restrict__ y, int nx, int ny, 
     eta1[o] = e; qx1[o] = a; qy1[o] = b;
 }
 
+// ys = y smoothed by the 3x3 binomial filter (1 2 1)^T (1 2 1) / 16, edges
+// clamped: it removes the grid-scale (checkerboard) content of a guess, which
+// the step damps only slowly and which in FP32 can settle into a cycle whose
+// per-step change keeps the residual above a tight tolerance.
+__global__ void guess_smooth_kernel(const float* __restrict__ y, int nx, int ny, float* __restrict__ ys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nx * ny) return;
+    const int x = (int)(i % nx), yy = (int)(i / nx);
+    const int xm = x > 0 ? x - 1 : 0, xp = x < nx - 1 ? x + 1 : nx - 1;
+    const int ym = yy > 0 ? yy - 1 : 0, yp = yy < ny - 1 ? yy + 1 : ny - 1;
+    for (int c = 0; c < 3; ++c) {
+        auto at = [&](int a, int b) { return y[((int64_t)b * nx + a) * 3 + c]; };
+        const float r0 = (at(xm, ym) + 2.0f * at(x, ym)) + at(xp, ym);
+        const float r1 = (at(xm, yy) + 2.0f * at(x, yy)) + at(xp, yy);
+        const float r2 = (at(xm, yp) + 2.0f * at(x, yp)) + at(xp, yp);
+        ys[i * 3 + c] = 0.0625f * ((r0 + 2.0f * r1) + r2);
+    }
+}
+
 hipError_t guess_to_state(const float* y, int nx, int ny, int ld, float s_eta, float s_q, const int* wall4,
-                          double* scratch, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
+                          double* scratch, float* ys, float* eta0, float* qx0, float* qy0, float* eta1, float* qx1,
                           float* qy1, hipStream_t s)
 {
+    hipLaunchKernelGGL(guess_smooth_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, y, nx, ny, ys);
+    y = ys;
     hipLaunchKernelGGL(guess_mean_kernel, dim3(1), dim3(256), 0, s, y, (int64_t)nx * ny, s_eta, scratch);
     hipLaunchKernelGGL(guess_write_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0, s, y, nx, ny,
                        ld, s_eta, s_q, wall4[0], wall4[1], wall4[2], wall4[3], scratch, eta0, qx0, qy0, eta1, qx1,

@@ -127,13 +127,22 @@ def build_dataset(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: flo
 
 
 def train(net: mlb.Net, data: Dataset, ts: TrainSpec, log=print) -> List[float]:
+    """One mlb_net_train call per epoch: step size constant within an epoch,
+    cosine decay from lr to lr_min across epochs, linear warm-up over the
+    first warmup_steps steps; a fresh sample order per epoch."""
     t0 = time.perf_counter()
-    losses = net.train(data.x, data.t, len(data.specs), ts.epochs, ts.batch, ts.lr, ts.lr_min, ts.warmup_steps,
-                       weight_decay=ts.weight_decay, seed=ts.seed)
+    losses = []
+    for e in range(ts.epochs):
+        lr_e = ts.lr_min + 0.5 * (ts.lr - ts.lr_min) * (1.0 + np.cos(np.pi * e / ts.epochs))
+        el = net.train(data.x, data.t, len(data.specs), 1, ts.batch, lr_e, lr_e,
+                       ts.warmup_steps if e == 0 else 0, weight_decay=ts.weight_decay, seed=ts.seed + e)
+        losses.append(float(el[0]))
+        log("epoch %d/%d loss %.4g lr %.2e (%.1f s)" % (e + 1, ts.epochs, losses[-1], lr_e,
+                                                      time.perf_counter() - t0))
     net.ctx.sync()
     log("trained %d epochs in %.1f s; loss %.4g -> %.4g" % (ts.epochs, time.perf_counter() - t0, losses[0],
                                                            losses[-1]))
-    return [float(v) for v in losses]
+    return losses
 
 
 def evaluate(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: float = 1e-6,
