@@ -239,16 +239,19 @@ def bench_lake_steady(args, ctx):
     from paper_1902_02999_amd import mlb, workloads as wl
     spec = wl.wind_lake(256)
     g = mlb.grid_from_spec(ctx, spec)
+    tuned = None if args.no_autotune else g.autotune(steps=40)
     g.set_exec_opts(graph_chunk=98)
+    ctx.sync()
     t0 = time.perf_counter()
     ok, d = g.run_steady(1e-6, 3_000_000, 100)
     wall = time.perf_counter() - t0
+    g_opts = g.exec_opts().as_dict()
     g.close()
     ctx.close()
     print(json.dumps({"metric": "wall_s_to_residual_1e-6", "value": round(wall, 4), "unit": "s",
                       "higher_is_better": False, "converged": ok, "steps": d["step"],
                       "residual": d["residual"], "t_model_s": d["t"],
-                      "config": {"workload": spec.name, "nodes": spec.nodes}}), flush=True)
+                      "config": {"workload": spec.name, "nodes": spec.nodes, "exec": g_opts}}), flush=True)
 
 
 def bench_warm_start(args, ctx):

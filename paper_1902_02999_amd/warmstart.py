@@ -153,15 +153,22 @@ def evaluate(ctx: mlb.Context, net: mlb.Net, specs: List[wl.Spec], tol: float = 
     stop at R <= tol or under the same stall rule (`stall_checks` checks
     without a new lowest residual: the FP32 noise floor of a weak flow)."""
     ctx.set_stall_checks(stall_checks)
+    # launch options tuned once for the basin shape, used by both runs
+    g = mlb.grid_from_spec(ctx, specs[0])
+    opts = g.autotune(steps=40)
+    g.close()
+    log("exec options %s" % json.dumps(opts))
     out = []
     for s in specs:
         g = mlb.grid_from_spec(ctx, s)
+        g.set_exec_opts(**opts)
         ctx.sync()
         t0 = time.perf_counter()
         ok_c, dc = g.run_steady(tol, max_steps, check_every)
         cold_s = time.perf_counter() - t0
         g.close()
         g = mlb.grid_from_spec(ctx, s)
+        g.set_exec_opts(**opts)
         ctx.sync()
         ok_w, rep = net.warm_start_run(g, tol, max_steps, check_every)
         g.close()
