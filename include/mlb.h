@@ -184,17 +184,24 @@ typedef struct {
     int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
     int32_t graph_chunk;   /* steps per captured graph, 2..100000                         */
     int32_t blocks_per_cu; /* 0: no cap; 1..8: at most this many step workgroups per CU   */
+    int32_t persistent;    /* 1: run a call's passes in one cooperative launch with a grid
+                            * barrier between passes, when every tile fits on the device
+                            * at once (else ordinary launches); for small grids, where
+                            * launches dominate.  A barrier that times out stops the
+                            * launch; the next mlb_diag / mlb_run_steady reports
+                            * MLB_E_DEVICE and the state must be set again             */
 } mlb_exec_opts;
 mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
 mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
 
 /* Autotuner: times the step for every (tblock, tile_rows, blocks_per_cu)
  * triple of a fixed candidate set (tblock 1, 2 x tile rows 6..45 x caps 0,
- * 2..5) with HIP events (median of 3 runs of `steps` steps), applies the
+ * 2..5; plus persistent launches where every tile fits on the device at
+ * once) with HIP events (median of 3 runs of `steps` steps), applies the
  * fastest and returns it in *best (may be NULL).  The grid's state and step
  * counter are restored afterwards (results are bitwise independent of these
  * options).  cache_path (may be NULL): a text file of
- * "key tile_rows blocks_per_cu tblock us" lines; a matching key is applied
+ * "key tile_rows blocks_per_cu tblock persistent us" lines; a matching key is applied
  * without timing, a new result is appended.  The key holds the device name
  * and the grid shape. */
 mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_exec_opts* best);

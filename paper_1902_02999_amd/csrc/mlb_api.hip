@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -117,6 +118,11 @@ mlb_status plan_alloc(mlb_ctx* c, Plan& P)
     HIPCHK(hipMalloc(&P.dpart, nt * kPartials * sizeof(double)));
     HIPCHK(hipMalloc(&P.dout, nb * 8 * sizeof(double)));
     HIPCHK(hipHostMalloc(&P.hout, nb * 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipMalloc(&P.dsync, sizeof(SyncState)));
+    HIPCHK(hipHostMalloc(&P.herr, sizeof(int32_t), hipHostMallocDefault));
+    HIPCHK(hipMemsetAsync(P.dsync, 0, sizeof(SyncState), c->stream));
+    P.sync_base = 0;
+    P.coop_failed = false;
     HIPCHK(hipMemcpyAsync(P.dt, P.ht.data(), nt * sizeof(TileDev), hipMemcpyHostToDevice, c->stream));
     if (!P.ht2.empty()) {
         HIPCHK(hipMalloc(&P.dt2, P.ht2.size() * sizeof(TileDev)));
@@ -206,6 +212,29 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     } else if (kind == 1) {
         multi = diag_last ? n - 1 : n;
         singles = n - multi;
+    }
+    // persistent: all `multi` passes in cooperative launches with grid barriers
+    if (o.persistent && multi > 0 && !P.coop_failed) {
+        const int nt = kind == 2 ? nt2 : nt1;
+        const int nblk = (nt + kBlock / kWave - 1) / (kBlock / kWave);
+        if (persistent_capacity(kind, c->ncu) < nblk) {
+            P.coop_failed = true;
+        } else {
+            while (multi > 0) {
+                const int np = (int)std::min<int64_t>(multi, 1 << 12);
+                const hipError_t e = launch_persistent(P.db, kind == 2 ? P.dt2 : P.dt, nt, P.parity, np, kind,
+                                                       P.dsync, P.sync_base, c->spin_limit, c->stream);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    P.coop_failed = true;   // ordinary launches for the rest
+                    break;
+                }
+                P.sync_base += (uint64_t)np * (uint64_t)nblk;
+                P.parity ^= np & 1;
+                nl += np;
+                multi -= np;
+            }
+        }
     }
     // graphs hold an even number of launches, so the parity they start from recurs
     const int glaunch = kind == 2 ? std::max(2, (o.graph_chunk / 2) & ~1) : std::max(2, o.graph_chunk & ~1);
@@ -331,7 +360,15 @@ mlb_status read_diag(mlb_ctx* c, Plan& P)
     HIPCHK(launch_finalize(P.db, (int)P.hb.size(), P.dpart, P.dout, c->stream));
     HIPCHK(hipMemcpyAsync(P.hout, P.dout, P.hb.size() * 8 * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
+    HIPCHK(hipMemcpyAsync(P.herr, &P.dsync->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (*P.herr) {
+        // a persistent launch gave up at a barrier: its passes are incomplete
+        HIPCHK(hipMemsetAsync(P.dsync, 0, sizeof(SyncState), c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        P.sync_base = 0;
+        return fail(MLB_E_DEVICE, "a persistent launch timed out at a pass barrier; the state is incomplete");
+    }
     return MLB_OK;
 }
 
@@ -395,6 +432,12 @@ mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out)
     for (auto& ch : c->arch) if (ch == ' ' || ch == ':') ch = '_';
     (void)hipEventCreate(&c->ev0);
     (void)hipEventCreate(&c->ev1);
+    // bounded wait of persistent launches (polls); a small value forces the
+    // timeout path from the host
+    if (const char* sl = std::getenv("MLB_SPIN_LIMIT")) {
+        const long v = std::strtol(sl, nullptr, 10);
+        if (v >= 0 && v < (1L << 30)) c->spin_limit = (int)v;
+    }
     *out = c;
     return MLB_OK;
 }
@@ -635,6 +678,7 @@ static mlb_status check_opts(const mlb_exec_opts* o)
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 8) return fail(MLB_E_INVAL, "blocks_per_cu must be 0..8");
     if (o->use_graph && (o->graph_chunk < 2 || o->graph_chunk > 100000))
         return fail(MLB_E_INVAL, "graph_chunk out of range");
+    if (o->persistent != 0 && o->persistent != 1) return fail(MLB_E_INVAL, "persistent must be 0 or 1");
     return MLB_OK;
 }
 
@@ -933,11 +977,11 @@ bool cache_lookup(const char* path, const std::string& key, mlb_exec_opts* o)
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char k[256];
-    int tr = 0, bc = 0, tb = 1;
+    int tr = 0, bc = 0, tb = 1, ps = 0;
     double us = 0;
     bool hit = false;
-    while (std::fscanf(f, "%255s %d %d %d %lf", k, &tr, &bc, &tb, &us) == 5)
-        if (key == k) { o->tile_rows = tr; o->blocks_per_cu = bc; o->tblock = tb; hit = true; }
+    while (std::fscanf(f, "%255s %d %d %d %d %lf", k, &tr, &bc, &tb, &ps, &us) == 6)
+        if (key == k) { o->tile_rows = tr; o->blocks_per_cu = bc; o->tblock = tb; o->persistent = ps; hit = true; }
     std::fclose(f);
     return hit;
 }
@@ -947,8 +991,22 @@ void cache_store(const char* path, const std::string& key, const mlb_exec_opts& 
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), o.tile_rows, o.blocks_per_cu, o.tblock, us);
+    std::fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), o.tile_rows, o.blocks_per_cu, o.tblock, o.persistent, us);
     std::fclose(f);
+}
+
+// Whether the tiles of these grids at (rows, tblock) fit on the device at once.
+bool fits_persistent(mlb_ctx* c, const std::vector<mlb_grid*>& gs, int rows, int tb)
+{
+    int64_t tiles = 0;
+    const int strip = tb == 2 ? kStripOut2 : kStripOut;
+    for (auto* g : gs) {
+        std::vector<TileDev> t;
+        make_tiles(g, 0, rows, t, strip);
+        tiles += (int64_t)t.size();
+    }
+    const int64_t nblk = (tiles + kBlock / kWave - 1) / (kBlock / kWave);
+    return nblk <= persistent_capacity(tb, c->ncu);
 }
 
 // Times `steps` steps of each candidate; `prepare` rebuilds the plan for the
@@ -961,10 +1019,14 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
+    for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : kTuneRows)
         for (int cap : kTuneCaps) {
+            // persistent launches need every tile resident: no workgroup cap
+            if (ps && (cap != 0 || !fits_persistent(c, gs, tr, tb))) continue;
             mlb_exec_opts o = base;
+            o.persistent = ps;
             o.tblock = tb;
             o.tile_rows = tr;
             o.blocks_per_cu = cap;

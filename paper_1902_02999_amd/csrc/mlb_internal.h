@@ -46,6 +46,13 @@ struct BasinDev {
     double bc_hmean[4], bc_amp[4], bc_om[4], bc_phase[4];
 };
 
+// Grid barrier state of persistent launches (device memory, zeroed once).
+struct SyncState {
+    uint64_t count;        // arrivals, accumulated over launches
+    int32_t err;           // set when a bounded wait gave up
+    int32_t pad;
+};
+
 // One wave's work item: a strip of up to 62 columns and `rows` rows.
 struct TileDev {
     int32_t basin;
@@ -59,6 +66,13 @@ struct TileDev {
 // of kStripOut2 columns, no diag.
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
                        double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s);
+// npasses passes of `kind` steps in one cooperative launch (all tiles
+// resident); base = sync->count at launch.  Fails (no launch) when the grid
+// cannot be co-resident.
+hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity0,
+                             int npasses, int kind, SyncState* sync, uint64_t base, int spin_limit, hipStream_t s);
+// Workgroups of the persistent kernel that fit on the device at once.
+int persistent_capacity(int kind, int ncu);
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);

@@ -461,7 +461,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 
 // ------------------------------------------------------------------ one step per pass
 template <bool EDGE, bool DIAG, bool FRIC>
-__device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd,
+__device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd, int64_t step,
                                          double* __restrict__ part)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -478,7 +478,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
     Stage V;
-    stage_setup<EDGE>(B, L, (double)(B.stepc[rd] + 1) * B.dt, V);
+    stage_setup<EDGE>(B, L, (double)(step + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
@@ -557,7 +557,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // Queue slot of A's row ra: (ra - r0 + 1) mod 3.  A's row 0 of an open S edge
 // is final only after A's row `extrap`, so B starts once A has done row r0+2.
 template <bool EDGE, bool FRIC>
-__device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd)
+__device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
@@ -571,7 +571,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     gfloat* __restrict__ E1 = (gfloat*)B.eta[wr];
     gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
-    const double tn0 = (double)B.stepc[rd] * B.dt;
+    const double tn0 = (double)step * B.dt;
     Stage SA, SB;
     stage_setup<EDGE>(B, L, tn0 + B.dt, SA);
     stage_setup<EDGE>(B, L, tn0 + 2.0 * B.dt, SB);
@@ -662,64 +662,126 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 #undef MLB_ROW
 
 // ------------------------------------------------------------------ kernels
+// One wave's share of a pass: tile t advances its basin by one step (KIND 1,
+// with the fused reduction when DIAG) or two (KIND 2).  `step` reads the
+// basin's step counter at buffer rd; the basin's first tile advances it.
+template <int KIND, bool DIAG, class StepRead>
+__device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles,
+                                          int t, int parity, double* __restrict__ partials, StepRead step_at)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const TileDev T = tiles[t];
+    const BasinDev& B = basins[T.basin];
+    const int rd = parity ^ B.swap;
+    const int64_t step = step_at(B, rd);
+    if (t == (KIND == 2 ? B.first_tile2 : B.first_tile) && lane == 0) {
+        // the counter advances once per pass; nobody else reads [rd ^ 1] now
+        volatile int64_t* sc = B.stepc;
+        sc[rd ^ 1] = step + KIND;
+    }
+    if (KIND == 1) {
+        const bool edge = (!B.per_x && (T.x0 == 0 || T.x0 + kStripOut >= B.nx)) ||
+                          (!B.per_y && (T.y0 == 0 || T.y0 + T.rows >= B.ny));
+        double* part = partials + (size_t)t * kPartials;
+        if (B.cfr != 0.0f) {
+            if (edge) run_tile<true, DIAG, true>(B, T, rd, step, part);
+            else run_tile<false, DIAG, true>(B, T, rd, step, part);
+        } else {
+            if (edge) run_tile<true, DIAG, false>(B, T, rd, step, part);
+            else run_tile<false, DIAG, false>(B, T, rd, step, part);
+        }
+    } else {
+        // a two-step tile needs the boundary logic when stage A's rows
+        // r0-1 .. r1 or lanes 1..62 touch an edge
+        const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
+                          (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
+        if (B.cfr != 0.0f) {
+            if (edge) run_tile2<true, true>(B, T, rd, step);
+            else run_tile2<false, true>(B, T, rd, step);
+        } else {
+            if (edge) run_tile2<true, false>(B, T, rd, step);
+            else run_tile2<false, false>(B, T, rd, step);
+        }
+    }
+}
+
+struct PlainStep {
+    __device__ int64_t operator()(const BasinDev& B, int rd) const { return B.stepc[rd]; }
+};
+
+// The counter of the previous pass of a persistent launch was written by
+// another workgroup: read it as an agent-scope atomic (a vector load).
+struct CoherentStep {
+    __device__ int64_t operator()(const BasinDev& B, int rd) const
+    {
+        return __hip_atomic_load(B.stepc + rd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// One pass of one step.  One wave per tile, tiles in list order (largest
+// basins first): the hardware dispatcher hands out workgroups in index
+// order, so the list is consumed as a queue without a software loop.
 template <bool DIAG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                  int parity, double* __restrict__ partials)
 {
-    // One wave per tile, tiles in list order (largest basins first): the
-    // hardware dispatcher hands out workgroups in index order, so the list is
-    // consumed as a queue without a software loop.
-    const int lane = threadIdx.x & (kWave - 1);
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    const TileDev T = tiles[t];
-    const BasinDev& B = basins[T.basin];
-    const int rd = parity ^ B.swap;
-    if (t == B.first_tile && lane == 0) {
-        // the step counter advances once per launch; nobody else reads [rd ^ 1] now
-        volatile int64_t* sc = B.stepc;
-        sc[rd ^ 1] = sc[rd] + 1;
-    }
-    const bool edge = (!B.per_x && (T.x0 == 0 || T.x0 + kStripOut >= B.nx)) ||
-                      (!B.per_y && (T.y0 == 0 || T.y0 + T.rows >= B.ny));
-    double* part = partials + (size_t)t * kPartials;
-    if (B.cfr != 0.0f) {
-        if (edge) run_tile<true, DIAG, true>(B, T, rd, part);
-        else run_tile<false, DIAG, true>(B, T, rd, part);
-    } else {
-        if (edge) run_tile<true, DIAG, false>(B, T, rd, part);
-        else run_tile<false, DIAG, false>(B, T, rd, part);
-    }
+    pass_tile<1, DIAG>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
-// Two steps per launch over tiles of 60-column strips.  A tile needs the
-// boundary logic when stage A's rows r0-1 .. r1 or lanes 1..62 touch an edge.
+// One pass of two steps, over tiles of 60-column strips.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                   int parity)
 {
-    const int lane = threadIdx.x & (kWave - 1);
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    const TileDev T = tiles[t];
-    const BasinDev& B = basins[T.basin];
-    const int rd = parity ^ B.swap;
-    if (t == B.first_tile2 && lane == 0) {
-        volatile int64_t* sc = B.stepc;
-        sc[rd ^ 1] = sc[rd] + 2;
-    }
-    const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
-                      (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
-    if (B.cfr != 0.0f) {
-        if (edge) run_tile2<true, true>(B, T, rd);
-        else run_tile2<false, true>(B, T, rd);
-    } else {
-        if (edge) run_tile2<true, false>(B, T, rd);
-        else run_tile2<false, false>(B, T, rd);
-    }
+    pass_tile<2, false>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
+// Many passes in one cooperative launch, every tile's wave resident: a grid
+// barrier on a device counter separates the passes, so small grids do not
+// pay a launch per pass.  Every workgroup arrives once per pass (idle waves
+// included).  Waiting is bounded: after spin_limit polls, or once another
+// workgroup has given up, the error flag is set and every workgroup leaves
+// the loop at that barrier, so the grid always drains.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
+                       int parity0, int npasses, SyncState* __restrict__ sync, uint64_t base, int spin_limit)
+{
+    __shared__ int abort_flag;
+    const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
+    const uint64_t nblk = gridDim.x;
+    // an earlier launch gave up: do nothing until the host has reset the state
+    if (threadIdx.x == 0) abort_flag = __hip_atomic_load(&sync->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (abort_flag) return;
+    for (int p = 0; p < npasses; ++p) {
+        if (t < ntiles) pass_tile<KIND, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
+        __threadfence();   // release: this wave's stores, device-wide
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&sync->count, (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t target = base + (uint64_t)(p + 1) * nblk;
+            int spins = 0;
+            while (__hip_atomic_load(&sync->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(&sync->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    ++spins > spin_limit) {
+                    __hip_atomic_store(&sync->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort_flag = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        __threadfence();   // acquire: the other workgroups' stores of this pass
+        if (abort_flag) break;
+    }
+}
 
 // Reduction of the current state (no step): same partial layout as the step.
 __global__ __launch_bounds__(kBlock) void reduce_state_kernel(const BasinDev* __restrict__ basins,
@@ -841,6 +903,28 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
         hipLaunchKernelGGL(step_kernel<false>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
                            ntiles, parity, d_partials);
     return hipGetLastError();
+}
+
+hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity0,
+                             int npasses, int kind, SyncState* sync, uint64_t base, int spin_limit, hipStream_t s)
+{
+    const int per = kBlock / kWave;
+    const dim3 grid((ntiles + per - 1) / per);
+    void* args[] = {(void*)&d_basins, (void*)&d_tiles, (void*)&ntiles, (void*)&parity0, (void*)&npasses,
+                    (void*)&sync, (void*)&base, (void*)&spin_limit};
+    if (kind == 2)
+        return hipLaunchCooperativeKernel((const void*)persistent_kernel<2>, grid, dim3(kBlock), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)persistent_kernel<1>, grid, dim3(kBlock), args, 0, s);
+}
+
+int persistent_capacity(int kind, int ncu)
+{
+    int n = 0;
+    if (kind == 2)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<2>, kBlock, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<1>, kBlock, 0);
+    return n * ncu;
 }
 
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,

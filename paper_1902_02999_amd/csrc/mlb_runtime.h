@@ -56,6 +56,10 @@ struct Plan {
     int gparity = -1;
     int gsteps = 0;
     int gkind = 0;             // steps per launch in the captured graph
+    SyncState* dsync = nullptr;  // grid barrier state of persistent launches
+    int32_t* herr = nullptr;     // pinned copy of dsync->err
+    uint64_t sync_base = 0;      // dsync->count when the next persistent launch starts
+    bool coop_failed = false;    // a persistent launch was refused: use ordinary ones
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool built = false;
 
@@ -65,6 +69,9 @@ struct Plan {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0; gkind = 0;
         (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dt2); (void)hipFree(dpart);
+        (void)hipFree(dsync);
+        if (herr) (void)hipHostFree(herr);
+        dsync = nullptr; herr = nullptr; sync_base = 0; coop_failed = false;
         (void)hipFree(dout);
         if (hout) (void)hipHostFree(hout);
         db = nullptr; dt = nullptr; dt2 = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
@@ -85,6 +92,7 @@ struct mlb_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     int stall_checks = 0;      // 0: off
+    int spin_limit = 1 << 22;  // polls of a persistent launch's barrier wait (MLB_SPIN_LIMIT)
 };
 
 struct mlb_grid {
@@ -109,7 +117,7 @@ struct mlb_grid {
     double bc_hmean[4] = {0, 0, 0, 0}, bc_amp[4] = {0, 0, 0, 0}, bc_om[4] = {0, 0, 0, 0},
            bc_phase[4] = {0, 0, 0, 0}, bc_qx[4] = {0, 0, 0, 0}, bc_qy[4] = {0, 0, 0, 0};
     mlb_batch* batch = nullptr;
-    mlb_exec_opts opts{15, 1, 1, 64, 3};
+    mlb_exec_opts opts{15, 1, 1, 64, 3, 0};
     mlb::Plan plan;
     bool dirty = true;         // descriptor must be re-uploaded
     bool stale_plan = true;    // tiles / allocation must be rebuilt
@@ -118,7 +126,7 @@ struct mlb_grid {
 struct mlb_batch {
     mlb_ctx* ctx = nullptr;
     std::vector<mlb_grid*> grids;
-    mlb_exec_opts opts{15, 1, 1, 64, 3};
+    mlb_exec_opts opts{15, 1, 1, 64, 3, 0};
     mlb::Plan plan;
     bool stale_plan = true;
 };

@@ -50,7 +50,7 @@ class Diag(C.Structure):
 
 class ExecOpts(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("tblock", C.c_int32), ("use_graph", C.c_int32),
-                ("graph_chunk", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("graph_chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("persistent", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -314,13 +314,14 @@ class Grid:
         return o
 
     def set_exec_opts(self, tile_rows=None, tblock=None, use_graph=None, graph_chunk=None,
-                      blocks_per_cu=None):
+                      blocks_per_cu=None, persistent=None):
         o = self.exec_opts()
         if tile_rows is not None: o.tile_rows = tile_rows
         if tblock is not None: o.tblock = tblock
         if use_graph is not None: o.use_graph = int(use_graph)
         if graph_chunk is not None: o.graph_chunk = graph_chunk
         if blocks_per_cu is not None: o.blocks_per_cu = blocks_per_cu
+        if persistent is not None: o.persistent = int(persistent)
         _check(lib().mlb_set_exec_opts(self.h, C.byref(o)), "mlb_set_exec_opts")
 
     def autotune(self, steps: int = 40, cache_path: Optional[str] = None) -> dict:
@@ -368,8 +369,9 @@ class Batch:
         _check(lib().mlb_batch_create(ctx.h, arr, len(grids), C.byref(h)), "mlb_batch_create")
         self.h = h
 
-    def set_exec_opts(self, tile_rows=27, tblock=1, use_graph=True, graph_chunk=64, blocks_per_cu=3):
-        o = ExecOpts(tile_rows, tblock, int(use_graph), graph_chunk, blocks_per_cu)
+    def set_exec_opts(self, tile_rows=27, tblock=1, use_graph=True, graph_chunk=64, blocks_per_cu=3,
+                      persistent=0):
+        o = ExecOpts(tile_rows, tblock, int(use_graph), graph_chunk, blocks_per_cu, int(persistent))
         _check(lib().mlb_batch_set_exec_opts(self.h, C.byref(o)), "mlb_batch_set_exec_opts")
 
     def autotune(self, steps: int = 20, cache_path: Optional[str] = None) -> dict:

@@ -252,6 +252,80 @@ def test_two_step_batch_bitwise(ctx):
         g.close()
 
 
+_PERSIST = [c for c in _TB2 if c[0] in ("closed64", "closed61x9_rows6", "periodic70x40", "channel_order2",
+                                          "ychannel_order2", "ydepth_walls", "tidal_strip")]
+
+
+@pytest.mark.parametrize("case", _PERSIST, ids=[c[0] for c in _PERSIST])
+def test_persistent_launches_bitwise(ctx, case):
+    """All passes of a call in one cooperative launch with grid barriers give
+    the bits of one launch per pass, for one and two steps per pass."""
+    name, spec, state, steps, rows = case
+    say("persistent case", name, spec.nx, spec.ny, "steps", steps)
+    for tb in (1, 2):
+        ref = run_gpu(ctx, spec, steps, state, opts={"tile_rows": rows, "tblock": tb})
+        got = run_gpu(ctx, spec, steps, state, opts={"tile_rows": rows, "tblock": tb, "persistent": 1})
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (name, tb)
+
+
+def test_persistent_steady_and_batch(ctx):
+    from paper_1902_02999_amd import mlb
+    spec = closed_spec(90, 70, 4)
+    res = []
+    for ps in (0, 1):
+        g = mlb.grid_from_spec(ctx, spec)
+        g.set_exec_opts(tblock=2, tile_rows=6, persistent=ps)
+        ok, d = g.run_steady(1e-5, 200000, 100)
+        res.append((ok, d, g.get_state()))
+        g.close()
+    assert res[0][0] and res[1][0]
+    for k in ("step", "mass", "residual"):
+        assert res[0][1][k] == res[1][1][k], k
+    for a, b in zip(res[0][2], res[1][2]):
+        assert np.array_equal(a, b)
+    specs = [closed_spec(n, m, s) for (n, m, s) in ((64, 64, 0), (100, 37, 1), (33, 150, 2))]
+    solo = [run_gpu(ctx, s, 45) for s in specs]
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    b = mlb.Batch(ctx, grids)
+    b.set_exec_opts(tile_rows=9, tblock=2, persistent=1)
+    b.step(45)
+    b.close()
+    for g, ref in zip(grids, solo):
+        for x, y in zip(g.get_state(), ref):
+            assert np.array_equal(x, y)
+        g.close()
+
+
+def test_persistent_barrier_timeout_is_reported(ctx, monkeypatch):
+    """A barrier wait forced to give up at once (spin limit 0, set from the
+    host) ends the launch; the next check reports it, and the grid works
+    again once its state is set."""
+    from paper_1902_02999_amd import mlb
+    monkeypatch.setenv("MLB_SPIN_LIMIT", "0")
+    c = mlb.Context(0)
+    monkeypatch.delenv("MLB_SPIN_LIMIT")
+    spec = closed_spec(64, 64, 0)
+    state = wl.seeded_state(spec, 0, q_amp=0.1)
+    g = mlb.grid_from_spec(c, spec)
+    g.set_state(*state)
+    g.set_exec_opts(tile_rows=4, tblock=1, persistent=1)   # 32 tiles, 8 workgroups
+    g.step(20)
+    with pytest.raises(mlb.MlbError) as ei:
+        g.diag()
+    assert ei.value.name == "MLB_E_DEVICE"
+    # recovered: ordinary launches from a fresh state match a fresh grid
+    g.set_state(*state)
+    g.set_exec_opts(tile_rows=4, tblock=1, persistent=0)
+    g.step(20)
+    got = g.get_state()
+    g.close()
+    c.close()
+    ref = run_gpu(ctx, spec, 20, state)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
 def test_batch_equals_solo_bitwise(ctx):
     from paper_1902_02999_amd import mlb
     specs = [closed_spec(n, m, s) for (n, m, s) in ((64, 64, 0), (200, 97, 1), (33, 150, 2))]
@@ -401,7 +475,8 @@ def test_autotune_keeps_state_and_caches(ctx, tmp_path):
         assert np.array_equal(a, b)
     assert g.diag()["step"] == 5
     lines = open(cache).read().split()
-    assert len(lines) == 5 and lines[0].endswith("_g300x170") and int(lines[3]) in (1, 2)
+    assert len(lines) == 6 and lines[0].endswith("_g300x170") and int(lines[3]) in (1, 2)
+    assert int(lines[4]) in (0, 1)
     # second call: served from the cache, same choice
     assert g.autotune(steps=8, cache_path=cache) == g.exec_opts().as_dict()
     # stepping after tuning equals stepping an untuned copy
