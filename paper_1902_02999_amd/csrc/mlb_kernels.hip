@@ -121,8 +121,11 @@ __device__ __forceinline__ float link(float hx, float ex, float hy, float ey)
 //   along the row     E1 = o1(x-1) + o5(x+1),            E2 = o1(x-1) - o5(x+1)
 // Edge tiles keep the individual particles instead (bounced links replace
 // some of them) and form the same sums at the receiving node.
+// Lane shifts are written at each use (not stored), so the compiler folds
+// each into the add or subtract that consumes it (a DPP source operand)
+// instead of spending a separate move.
 struct Row {
-    float eta, h, el, hl, er, hr;
+    float eta, h;
     float S1, S2, N1, N2, E1, E2;
     float o1l, o5r, o2l, o3, o4r, o6r, o7, o8l;
 };
@@ -131,21 +134,30 @@ template <bool EDGE>
 __device__ __forceinline__ void exchange(const Node& d, Row& R)
 {
     R.eta = d.eta; R.h = d.h;
-    R.el = from_left(d.eta);  R.hl = from_left(d.h);
-    R.er = from_right(d.eta); R.hr = from_right(d.h);
-    const float o1l = from_left(d.o[1]), o5r = from_right(d.o[5]);
-    const float o2l = from_left(d.o[2]), o4r = from_right(d.o[4]);
-    const float o6r = from_right(d.o[6]), o8l = from_left(d.o[8]);
     if (EDGE) {
-        R.o1l = o1l; R.o5r = o5r; R.o2l = o2l; R.o3 = d.o[3]; R.o4r = o4r;
-        R.o6r = o6r; R.o7 = d.o[7]; R.o8l = o8l;
+        R.o1l = from_left(d.o[1]); R.o5r = from_right(d.o[5]);
+        R.o2l = from_left(d.o[2]); R.o3 = d.o[3]; R.o4r = from_right(d.o[4]);
+        R.o6r = from_right(d.o[6]); R.o7 = d.o[7]; R.o8l = from_left(d.o[8]);
         R.S1 = R.S2 = R.N1 = R.N2 = R.E1 = R.E2 = 0.0f;
     } else {
-        R.S1 = (o2l + d.o[3]) + o4r; R.S2 = o2l - o4r;
-        R.N1 = (o6r + d.o[7]) + o8l; R.N2 = o8l - o6r;
-        R.E1 = o1l + o5r;            R.E2 = o1l - o5r;
+        R.S1 = (from_left(d.o[2]) + d.o[3]) + from_right(d.o[4]);
+        R.S2 = from_left(d.o[2]) - from_right(d.o[4]);
+        R.N1 = (from_right(d.o[6]) + d.o[7]) + from_left(d.o[8]);
+        R.N2 = from_left(d.o[8]) - from_right(d.o[6]);
+        R.E1 = from_left(d.o[1]) + from_right(d.o[5]);
+        R.E2 = from_left(d.o[1]) - from_right(d.o[5]);
         R.o1l = R.o5r = R.o2l = R.o3 = R.o4r = R.o6r = R.o7 = R.o8l = 0.0f;
     }
+}
+
+// Link of node x with the lane neighbour of row R on its right / left.
+__device__ __forceinline__ float link_right(float hx, float ex, const Row& R)
+{
+    return (hx + from_right(R.h)) * (from_right(R.eta) - ex);
+}
+__device__ __forceinline__ float link_left(float hx, float ex, const Row& R)
+{
+    return (hx + from_left(R.h)) * (from_left(R.eta) - ex);
 }
 
 // Links a row passes to the row above: its N link at x and its NE / NW links
@@ -177,8 +189,7 @@ __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, co
                                             const Row& N, const Carry& cy, float lE, float lN, float lNE,
                                             float lNW, float& en, float& qxn, float& qyn)
 {
-    const float lEl = from_left(lE);
-    const float Ha = lE - lEl, Hs = lEl + lE;          // Ha, -Hx
+    const float Ha = lE - from_left(lE), Hs = from_left(lE) + lE;   // Ha, -Hx
     const float Ud = lNE + lNW, Ux = lNW - lNE;
     const float pa = (Ha - cy.cN) + lN;
     const float pd = Ud - cy.cBd;                      // Bd = -cBd
@@ -351,8 +362,8 @@ __device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, do
 template <bool EDGE>
 __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& cy)
 {
-    carry_from<EDGE>(link(dS.h, dS.eta, C.h, C.eta), link(dS.h, dS.eta, C.hr, C.er),
-                     link(dS.h, dS.eta, C.hl, C.el), cy);
+    carry_from<EDGE>(link(dS.h, dS.eta, C.h, C.eta), link_right(dS.h, dS.eta, C),
+                     link_left(dS.h, dS.eta, C), cy);
 }
 
 // One output row r of a stage V from window rows S (r-1), C (r), N (r+1).
@@ -367,8 +378,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
         derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
         exchange<EDGE>(DN, N);                                                                    \
         LOADNEXT;                                                                                 \
-        const float lE = link(DC.h, DC.eta, C.hr, C.er), lN = link(DC.h, DC.eta, N.h, N.eta);     \
-        const float lNE = link(DC.h, DC.eta, N.hr, N.er), lNW = link(DC.h, DC.eta, N.hl, N.el);   \
+        const float lE = link_right(DC.h, DC.eta, C), lN = link(DC.h, DC.eta, N.h, N.eta);        \
+        const float lNE = link_right(DC.h, DC.eta, N), lNW = link_left(DC.h, DC.eta, N);          \
         float en, qxn, qyn;                                                                       \
         if (EDGE) {                                                                               \
             float P[9], oy[9];                                                                    \
