@@ -645,9 +645,13 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
             stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
         }                                                                                         \
     } while (0)
-    // B row rb consumes A's row rb+1; then A computes row rb+3.  Rows of A
-    // past the tile read the clamped last row and are never used for stores.
-    const int nk = (T.rows + 2) / 3;
+    // B row rb consumes A's row rb+1; then A computes row rb+3.  Interior
+    // tiles pad their rows to 3 nk + 2: nk rounds of three (B, A) pairs, then
+    // B's last two rows alone, which need no further A row (A ends at r1 when
+    // the tile's rows are 2 mod 3).  Edge tiles, whose boundary state leaves
+    // no registers for that tail, pad to 3 nk and let A run two rows past the
+    // tile.  Pad rows and A's surplus rows are computed but never stored.
+    const int nk = EDGE ? (T.rows + 2) / 3 : T.rows / 3;   // T.rows >= 4, so nk >= 1
     for (int k = 0; k < nk; ++k) {
         MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
         ++rb;
@@ -661,6 +665,11 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         ++rb;
         MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_NOTHING);
         ++ra;
+    }
+    if (!EDGE) {
+        MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
+        ++rb;
+        MLB_ROW(SB, rb, q0, B1, B2, B0, b2, b0, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
     }
 #undef MLB_STORE2
 #undef MLB_STORE20
