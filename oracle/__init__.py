@@ -27,6 +27,7 @@ _lib = None
 
 WALL, PERIODIC, DEPTH, DISCHARGE = 0, 1, 2, 3
 W, E, S, N = 0, 1, 2, 3
+FLUID, WALL_NODE, SOLID = 0, 1, 2   # node kinds of an optional geometry mask
 
 
 def build(force: bool = False) -> str:
@@ -48,7 +49,8 @@ class Problem(C.Structure):
                 ("edge", C.c_int32 * 4), ("extrap_order", C.c_int32), ("pad_", C.c_int32),
                 ("bc_h_mean", C.c_double * 4), ("bc_amp", C.c_double * 4),
                 ("bc_period", C.c_double * 4), ("bc_phase", C.c_double * 4),
-                ("bc_qx", C.c_double * 4), ("bc_qy", C.c_double * 4)]
+                ("bc_qx", C.c_double * 4), ("bc_qy", C.c_double * 4),
+                ("kind", C.c_void_p)]
 
 
 def lib():
@@ -69,7 +71,7 @@ def lib():
             L.mref_node.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_double, C.c_int, C.c_int, dp]
             L.mref_run.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_int64, C.c_int64, dp, C.c_int]
             L.mref_diag.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp,
-                                    C.c_void_p, C.c_void_p, dp]
+                                    C.c_void_p, C.c_void_p, C.c_void_p, dp]
             L.mref_lattice.argtypes = [C.c_void_p] * 5
             L.mref_max_threads.restype = C.c_int
             _lib = L
@@ -118,6 +120,8 @@ class Basin:
 
     ``zb`` is the bed, ``h, qx, qy`` the depth and discharge (hu, hv).
     Edge kinds are (W, E, S, N) with WALL/PERIODIC/DEPTH/DISCHARGE.
+    ``kind`` is an optional uint8 [ny][nx] node-kind mask (FLUID, WALL_NODE,
+    SOLID).
     """
     nx: int
     ny: int
@@ -138,6 +142,7 @@ class Basin:
     qy: np.ndarray = None
     step_index: int = 0
     threads: int = 0
+    kind: np.ndarray = None
 
     def __post_init__(self):
         self.zb = np.ascontiguousarray(self.zb, np.float64).reshape(self.ny, self.nx)
@@ -146,6 +151,8 @@ class Basin:
             a = getattr(self, name)
             a = np.zeros((self.ny, self.nx)) if a is None else np.array(a, np.float64, copy=True)
             setattr(self, name, np.ascontiguousarray(a.reshape(self.ny, self.nx)))
+        if self.kind is not None:
+            self.kind = np.ascontiguousarray(np.asarray(self.kind, np.uint8).reshape(self.ny, self.nx))
         self._work = np.zeros(3 * self.nx * self.ny)
 
     def problem(self) -> Problem:
@@ -160,6 +167,7 @@ class Basin:
             p.bc_h_mean[k], p.bc_amp[k], p.bc_period[k], p.bc_phase[k] = hm, amp, per, ph
         for k, (a, b) in self.discharge_bc.items():
             p.bc_qx[k], p.bc_qy[k] = a, b
+        p.kind = None if self.kind is None else self.kind.ctypes.data
         return p
 
     @property
@@ -208,7 +216,8 @@ class Basin:
         b = None if qy0 is None else np.ascontiguousarray(qy0, np.float64)
         lib().mref_diag(self.nx, self.ny, self.dx, self.h, self.qx, self.qy,
                         None if a is None else a.ctypes.data,
-                        None if b is None else b.ctypes.data, out)
+                        None if b is None else b.ctypes.data,
+                        None if self.kind is None else self.kind.ctypes.data, out)
         return {"mass": out[0], "residual": out[1], "max_speed": out[2], "bad": int(out[3])}
 
     def run_steady(self, tol: float, max_steps: int, check_every: int = 100):

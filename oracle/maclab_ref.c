@@ -24,6 +24,13 @@
  *   - after the update: WALL nodes get q = 0; DEPTH nodes get h = h_bc(t+dt)
  *     and q extrapolated inward; DISCHARGE nodes get q = q_bc and the free
  *     surface extrapolated inward (precedence WALL > DISCHARGE > DEPTH).
+ *   - irregular geometry (staircase bounce-back, as the circular basin of
+ *     Section 4 needs) comes from an optional per-node kind: a SOLID node lies
+ *     outside the water and keeps its values; a link whose upstream node is
+ *     SOLID is bounced like a link that leaves the grid; a WALL node is updated
+ *     and then gets q = 0.  The kind overrides the edge logic at that node
+ *     (SOLID, then WALL), and nodes that an open edge extrapolates from must
+ *     be FLUID.
  * No reordering, blocking or fusion beyond that: every node recomputes the
  * equilibria of its upstream neighbours from h, u.
  */
@@ -49,6 +56,7 @@ static const double LAM[9] = {0.0, 1.0, 0.25, 1.0, 0.25, 1.0, 0.25, 1.0, 0.25};
 static const int    OPP[9] = {0, 5, 6, 7, 8, 1, 2, 3, 4};
 
 enum { REF_WALL = 0, REF_PERIODIC = 1, REF_DEPTH = 2, REF_DISCHARGE = 3 };
+enum { NODE_FLUID = 0, NODE_WALL = 1, NODE_SOLID = 2 };
 enum { REF_W = 0, REF_E = 1, REF_S = 2, REF_N = 3 };
 
 typedef struct {
@@ -62,7 +70,13 @@ typedef struct {
     int32_t pad_;
     double  bc_h_mean[4], bc_amp[4], bc_period[4], bc_phase[4];
     double  bc_qx[4], bc_qy[4];
+    const uint8_t* kind;  /* optional node kinds [ny][nx] (NODE_*), or NULL   */
 } mref_problem;
+
+static int kind_at(const mref_problem* p, int i, int j)
+{
+    return p->kind ? p->kind[(size_t)j * p->nx + i] : NODE_FLUID;
+}
 
 /* ---------------------------------------------------------------- lattice */
 
@@ -121,7 +135,8 @@ static void node_force(const mref_problem* p, double h, double qx, double qy, do
 }
 
 /* Upstream neighbour of (i, j) in direction a, i.e. x - e_a dt.  Returns 0 when
- * it lies outside a non-periodic edge (the link is then bounced). */
+ * it lies outside a non-periodic edge or is a SOLID node (the link is then
+ * bounced). */
 static int upstream(const mref_problem* p, int i, int j, int a, int* yi, int* yj)
 {
     int ii = i - EX[a], jj = j - EY[a];
@@ -133,6 +148,7 @@ static int upstream(const mref_problem* p, int i, int j, int a, int* yi, int* yj
         if (p->edge[REF_S] != REF_PERIODIC) return 0;
         jj = (jj + p->ny) % p->ny;
     }
+    if (kind_at(p, ii, jj) == NODE_SOLID) return 0;
     *yi = ii; *yj = jj;
     return 1;
 }
@@ -191,8 +207,12 @@ static void final_update(const mref_problem* p, const double* zb, const double* 
                          const double* qx, const double* qy, double t_new, int i, int j,
                          double out[3])
 {
+    const int nk = kind_at(p, i, j);
+    size_t x = (size_t)j * p->nx + i;
+    if (nk == NODE_SOLID) { out[0] = h[x]; out[1] = qx[x]; out[2] = qy[x]; return; }
     int ed = 0, kind = node_kind(p, i, j, &ed);
     pre_update(p, zb, h, qx, qy, i, j, out);
+    if (nk == NODE_WALL) { out[1] = 0.0; out[2] = 0.0; return; }
     if (kind < 0) return;
     if (kind == REF_WALL) { out[1] = 0.0; out[2] = 0.0; return; }
     int i1 = i + NRM_X[ed], j1 = j + NRM_Y[ed];
@@ -221,13 +241,32 @@ static void final_update(const mref_problem* p, const double* zb, const double* 
 
 /* ------------------------------------------------------------------- API */
 
-/* One step n -> n+1 with t_old = n dt.  Outputs must not alias inputs. */
-int mref_step(const mref_problem* p, const double* zb, const double* h, const double* qx,
-              const double* qy, double t_old, double* h1, double* qx1, double* qy1, int nthreads)
+/* Problem checks: paired periodic edges; node kinds in range; FLUID on every
+ * open edge and on the inner lines it extrapolates from. */
+static int check_problem(const mref_problem* p)
 {
     if (!p || p->nx < 3 || p->ny < 3) return -1;
     if ((p->edge[REF_W] == REF_PERIODIC) != (p->edge[REF_E] == REF_PERIODIC)) return -1;
     if ((p->edge[REF_S] == REF_PERIODIC) != (p->edge[REF_N] == REF_PERIODIC)) return -1;
+    if (!p->kind) return 0;
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            int k = kind_at(p, i, j);
+            if (k > NODE_SOLID) return -1;
+            if (k == NODE_FLUID) continue;
+            int dist[4] = {i, p->nx - 1 - i, j, p->ny - 1 - j};
+            for (int ed = 0; ed < 4; ++ed)
+                if ((p->edge[ed] == REF_DEPTH || p->edge[ed] == REF_DISCHARGE) && dist[ed] <= p->extrap_order)
+                    return -1;
+        }
+    return 0;
+}
+
+/* One step n -> n+1 with t_old = n dt.  Outputs must not alias inputs. */
+int mref_step(const mref_problem* p, const double* zb, const double* h, const double* qx,
+              const double* qy, double t_old, double* h1, double* qx1, double* qy1, int nthreads)
+{
+    if (check_problem(p)) return -1;
     const int nx = p->nx, ny = p->ny;
     const double t_new = t_old + p->dt;
 #ifdef _OPENMP
@@ -249,7 +288,7 @@ int mref_step(const mref_problem* p, const double* zb, const double* h, const do
 int mref_node(const mref_problem* p, const double* zb, const double* h, const double* qx,
               const double* qy, double t_old, int i, int j, double out[3])
 {
-    if (!p || i < 0 || j < 0 || i >= p->nx || j >= p->ny) return -1;
+    if (check_problem(p) || i < 0 || j < 0 || i >= p->nx || j >= p->ny) return -1;
     final_update(p, zb, h, qx, qy, t_old + p->dt, i, j, out);
     return 0;
 }
@@ -273,13 +312,16 @@ int mref_run(const mref_problem* p, const double* zb, double* h, double* qx, dou
 
 /* Diagnostics in a fixed serial order: out = {mass, residual, max speed,
  * non-finite-or-dry count}.  mass = sum h dx^2; residual = |q1 - q0| / |q1|
- * over both components (0 when the numerator is 0). */
+ * over both components (0 when the numerator is 0).  SOLID nodes (kind may be
+ * NULL) are not part of the water and are skipped. */
 void mref_diag(int32_t nx, int32_t ny, double dx, const double* h1, const double* qx1,
-               const double* qy1, const double* qx0, const double* qy0, double out[4])
+               const double* qy1, const double* qx0, const double* qy0, const uint8_t* kind,
+               double out[4])
 {
     double mass = 0.0, num = 0.0, den = 0.0, vmax = 0.0, bad = 0.0;
     size_t n = (size_t)nx * ny;
     for (size_t x = 0; x < n; ++x) {
+        if (kind && kind[x] == NODE_SOLID) continue;
         double hh = h1[x], a = qx1[x], b = qy1[x];
         if (!isfinite(hh) || !isfinite(a) || !isfinite(b) || hh <= 0.0) { bad += 1.0; continue; }
         mass += hh * dx * dx;

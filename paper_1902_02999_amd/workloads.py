@@ -7,7 +7,9 @@ equilibria, no force evaluation, no parameter derivation), so the GPU library
 and the FP64 oracle can both be fed from them.
 
 Edge kinds use the numbering WALL=0, PERIODIC=1, DEPTH=2, DISCHARGE=3 and the
-edge order (W, E, S, N).
+edge order (W, E, S, N).  An optional node-kind mask describes irregular
+geometry: FLUID=0, WALL_NODE=1 (no-slip boundary node), SOLID=2 (outside the
+water).
 """
 from __future__ import annotations
 
@@ -18,6 +20,7 @@ import numpy as np
 
 WALL, PERIODIC, DEPTH, DISCHARGE = 0, 1, 2, 3
 W, E, S, N = 0, 1, 2, 3
+FLUID, WALL_NODE, SOLID = 0, 1, 2
 
 
 @dataclass
@@ -40,9 +43,12 @@ class Spec:
     h0: Optional[np.ndarray] = None      # initial depth; default still water
     qx0: Optional[np.ndarray] = None
     qy0: Optional[np.ndarray] = None
+    kind: Optional[np.ndarray] = None    # node kinds [ny][nx] (uint8), None: all FLUID
 
     def __post_init__(self):
         self.zb = np.ascontiguousarray(self.zb, np.float64).reshape(self.ny, self.nx)
+        if self.kind is not None:
+            self.kind = np.ascontiguousarray(np.asarray(self.kind, np.uint8).reshape(self.ny, self.nx))
 
     @property
     def H(self) -> np.ndarray:
@@ -131,6 +137,80 @@ def bump_channel(nx: int = 4096, ny: Optional[int] = None, dx: float = 1.0, dept
                 edges=(DISCHARGE, DEPTH, WALL, WALL),
                 depth_bc={E: (depth, 0.0, 0.0, 0.0)}, discharge_bc={W: (q_in, 0.0)},
                 qx0=qx0)
+
+
+# ----------------------------------------------------------------------------- irregular geometry
+def staircase_kinds(inside: np.ndarray) -> np.ndarray:
+    """Node kinds of a staircase boundary: nodes outside the water are SOLID;
+    water nodes with an outside node (or the grid's edge) among their eight
+    neighbours are WALL_NODE; the rest FLUID."""
+    inside = np.asarray(inside, bool)
+    pad = np.pad(inside, 1, constant_values=False)
+    ny, nx = inside.shape
+    all_in = np.ones_like(inside)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            all_in &= pad[1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    kind = np.full(inside.shape, SOLID, np.uint8)
+    kind[inside] = WALL_NODE
+    kind[inside & all_in] = FLUID
+    return kind
+
+
+def circular_dish(n: int = 200, dx: float = 2.0, nu: float = 5.33, wind: float = 5.0,
+                  chezy: float = 0.0) -> Spec:
+    """Wind-driven circulation in a circular basin (Section 4): still-water
+    depth H = (1/1.3) (1/2 + sqrt(1/2 - r/386.4)) for r <= 193.2 m, bed
+    z_b = H(0,0) - H, wind u_w m/s from south-west to north-east.  Nodes sit at
+    cell centres of an n x n square of side n dx centred on the basin; nodes
+    with r > 193.2 m are SOLID (their H is the rim depth), the water's outer
+    ring is WALL_NODE (staircase bounce-back).  The paper gives no bed
+    friction for this case: none by default."""
+    c = (np.arange(n) - (n - 1) / 2.0) * dx
+    X, Y = np.meshgrid(c, c)
+    r = np.hypot(X, Y)
+    R = 193.2
+    inside = r <= R
+    H = (1.0 / 1.3) * (0.5 + np.sqrt(np.maximum(0.5 - np.minimum(r, R) / 386.4, 0.0)))
+    H0 = (1.0 / 1.3) * (0.5 + np.sqrt(0.5))
+    w = wind / np.sqrt(2.0)
+    return Spec("circular_dish_%d" % n, n, n, dx, nu, H0 - H, H0, wind_speed=(w, w), chezy=chezy,
+                kind=staircase_kinds(inside))
+
+
+def hump_channel(n: int = 200, length: float = 1000.0, q: float = 10.0, depth: float = 10.0,
+                 e: float = 25.0) -> Spec:
+    """Steady flow over a 2D hump (Section 4): z_b = sin^2(pi (x-300)/200)
+    sin^2(pi (y-400)/200) on [300,500] x [400,600], 0 elsewhere, in a square
+    channel of side `length` on n x n cell-centred nodes; discharge q m^2/s
+    in at the west edge, depth `depth` at the east (outflow) edge, walls
+    north and south.  Initial state: still level `depth`, uniform q.  The
+    paper gives no viscosity for this case: e (hence nu = e dx / 6) is chosen
+    with g H <= e^2 and a small lattice Reynolds number."""
+    dx = length / n
+    c = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(c, c)
+    om = (X >= 300.0) & (X <= 500.0) & (Y >= 400.0) & (Y <= 600.0)
+    zb = np.where(om, np.sin(np.pi * (X - 300.0) / 200.0) ** 2 * np.sin(np.pi * (Y - 400.0) / 200.0) ** 2, 0.0)
+    return Spec("hump_channel_%d" % n, n, n, dx, nu_for_speed(e, dx), zb, depth,
+                edges=(DISCHARGE, DEPTH, WALL, WALL),
+                depth_bc={E: (depth, 0.0, 0.0, 0.0)}, discharge_bc={W: (q, 0.0)},
+                qx0=np.full((n, n), q))
+
+
+def random_geometry(rng: np.random.Generator, nx: int, ny: int, holes: int = 3) -> np.ndarray:
+    """Node kinds of a random closed basin: an ellipse-and-rectangle union
+    with islands (SOLID discs) punched out, staircase boundary."""
+    Y, X = np.mgrid[0:ny, 0:nx].astype(float)
+    cx, cy = rng.uniform(0.35, 0.65) * nx, rng.uniform(0.35, 0.65) * ny
+    ax, ay = rng.uniform(0.3, 0.48) * nx, rng.uniform(0.3, 0.48) * ny
+    inside = ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 <= 1.0
+    x0, y0 = int(rng.integers(1, nx // 3)), int(rng.integers(1, ny // 3))
+    inside |= (X >= x0) & (X < x0 + nx // 3) & (Y >= y0) & (Y < y0 + ny // 2)
+    for _ in range(holes):
+        hx, hy, hr = rng.uniform(0.2, 0.8) * nx, rng.uniform(0.2, 0.8) * ny, rng.uniform(1.0, 3.5)
+        inside &= (X - hx) ** 2 + (Y - hy) ** 2 > hr * hr
+    return staircase_kinds(inside)
 
 
 # ----------------------------------------------------------------------------- ensemble basins
