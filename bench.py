@@ -90,10 +90,14 @@ def main():
                     help="steps per kernel pass when not autotuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default it picks tile rows and the CU cap before timing)")
-    ap.add_argument("--workload", default="bump", choices=["bump", "ensemble", "lake_steady", "warm_start"],
+    ap.add_argument("--workload", default="bump",
+                    choices=["bump", "ensemble", "lake_steady", "warm_start", "dish", "dish4096", "hump"],
                     help="bump: 4096^2 channel (default line); ensemble: 512 basins 64^2..512^2 in "
                          "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6; "
-                         "warm_start: learned warm start vs cold start on held-out 256^2 basins")
+                         "warm_start: learned warm start vs cold start on held-out 256^2 basins; "
+                         "dish: the paper's circular wind-driven basin (200^2, node mask) with its "
+                         "time to steady state; dish4096: the same basin on 4096^2 nodes; "
+                         "hump: the paper's 2D hump channel (200^2) with its time to steady state")
     ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
     ap.add_argument("--ws-train", type=int, default=512, help="warm_start: training basins")
     ap.add_argument("--ws-epochs", type=int, default=40, help="warm_start: training epochs")
@@ -120,6 +124,8 @@ def main():
         return bench_lake_steady(args, ctx)
     if args.workload == "warm_start":
         return bench_warm_start(args, ctx)
+    if args.workload in ("dish", "dish4096", "hump"):
+        return bench_geometry(args, ctx, copy_gbps)
     spec = wl.bump_channel(args.n)
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
@@ -232,6 +238,78 @@ def bench_ensemble(args, ctx, copy_gbps):
                    "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1)},
         "roofline": roofline,
         "cpu_baseline": None}), flush=True)
+
+
+def bench_geometry(args, ctx, copy_gbps):
+    """The paper's own geometries (Section 4).  Throughput of `steps` steps
+    counted over the water nodes (SOLID nodes of the circular basin's mask
+    are not updated), the dominant kernel's HBM roofline at 28 B per water
+    node plus 1 B per node kind read, and for the 200^2 cases the wall time
+    from rest to a per-step residual of 1e-6."""
+    import numpy as np
+    import torch
+    from paper_1902_02999_amd import mlb, workloads as wl
+    if args.workload == "hump":
+        spec = wl.hump_channel()
+    else:
+        n = 4096 if args.workload == "dish4096" else 200
+        spec = wl.circular_dish(n, 400.0 / n)
+    water = spec.nodes if spec.kind is None else int((spec.kind != wl.SOLID).sum())
+    kind_bytes = 0 if spec.kind is None else 1
+    g = mlb.grid_from_spec(ctx, spec)
+    g.set_exec_opts(tile_rows=args.tile_rows, graph_chunk=100, blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
+    tuned = None if args.no_autotune else g.autotune(steps=40)
+    g.step(args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()
+    d = g.diag()
+    opts = g.exec_opts().as_dict()
+    g.close()
+    tb = 1 if spec.kind is not None else opts["tblock"]
+    launch_s = tb * ev_ms / 1e3 / args.steps
+    bpl = (BYTES_PER_LUP + kind_bytes) * water
+    gbs = bpl / launch_s / 1e9
+    if tb == 1:
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        tfl = FLOP_PER_LUP[spec.chezy > 0] * 2 * water / launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    steady = None
+    if spec.nodes <= 200 * 200:
+        g = mlb.grid_from_spec(ctx, spec)
+        if tuned is not None:
+            g.set_exec_opts(**{k: opts[k] for k in ("tile_rows", "tblock", "blocks_per_cu", "persistent")})
+        g.set_exec_opts(graph_chunk=100)
+        ctx.sync()
+        t1 = time.perf_counter()
+        ok, ds = g.run_steady(1e-6, 5_000_000, 2000)
+        steady = {"converged": ok, "wall_s": round(time.perf_counter() - t1, 3), "steps": ds["step"],
+                  "t_model_s": round(ds["t"], 1), "residual": ds["residual"], "max_speed": ds["max_speed"]}
+        g.close()
+    ctx.close()
+    out = {"metric": "MLUPS", "value": round(water * args.steps / wall / 1e6, 1), "unit": "MLUPS",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": spec.name, "nodes": spec.nodes, "water_nodes": water, "dx_m": spec.dx,
+                      "nu": spec.nu, "exec": opts, "autotuned": tuned is not None, "nonfinite": d["nonfinite"],
+                      "launch_us": round(launch_s * 1e6, 3), "copy_probe_GBps": round(copy_gbps, 1),
+                      "steady_1e-6": steady},
+           "roofline": roofline}
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(spec, args.cpu_seconds)
+    if out["cpu_baseline"] is not None and water != spec.nodes:
+        cb = out["cpu_baseline"]
+        cb["value"] = round(cb["value"] * water / spec.nodes, 3)
+        cb["sample"] += " (water nodes only)"
+    print(json.dumps(out), flush=True)
 
 
 def bench_lake_steady(args, ctx):

@@ -78,7 +78,7 @@ typedef struct {
 typedef struct {
     int64_t step;          /* steps taken                                                  */
     double  t;             /* step * dt [s]                                                */
-    double  mass;          /* sum of h dx^2 over all nodes [m^3]                           */
+    double  mass;          /* sum of h dx^2 over all nodes but SOLID ones [m^3]            */
     double  residual;      /* |q(n) - q(n-1)|_2 / |q(n)|_2, both components; 0 if no change */
     double  max_speed;     /* max |q| / h [m/s]                                            */
     int64_t nonfinite;     /* nodes with a non-finite value or h <= 0                      */
@@ -128,6 +128,27 @@ mlb_status mlb_grid_destroy(mlb_grid* g);
  * MLB_E_UNSTABLE if g * max(H) > e^2 (linear stability of the step);
  * MLB_E_INVAL if some H <= 0 (no wetting/drying). */
 mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld);
+
+/* Node kinds of the optional geometry mask: irregular basins by staircase
+ * bounce-back (the bounce-back of Section 3 applied at every link that starts
+ * at a SOLID node; the circular basin of Section 4 is built this way). */
+enum { MLB_NODE_FLUID = 0, MLB_NODE_WALL = 1, MLB_NODE_SOLID = 2 };
+/* Node kinds [ny][ld] (host, copied into a device byte plane that the library
+ * allocates); kind == NULL removes the mask.
+ *   FLUID  an ordinary node (the edge kinds apply as without a mask);
+ *   WALL   updated, then q = 0 (no-slip boundary node);
+ *   SOLID  outside the water: never written, left out of the diagnostics
+ *          (mass, residual, max speed, non-finite count); a link whose
+ *          upstream node is SOLID is bounced (f_a^eq := f_abar^eq of the node
+ *          itself, no bed or force term), as at a wall edge.
+ * A node's kind overrides its edge kind (SOLID, then WALL).  SOLID nodes
+ * still need a positive H (its value is never used).  MLB_E_INVAL for a kind
+ * above SOLID, for a non-FLUID node within extrap_order nodes of an open
+ * (DEPTH / DISCHARGE) edge, or when every node is SOLID.  The current state
+ * is copied into the second buffer set, so the next residual is 0.  Masked
+ * grids run one step per pass (tblock 2 is accepted and runs as 1).
+ * MLB_E_STATE if the grid belongs to a live batch. */
+mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 
 /* Uniform wind speed (u_wx, u_wy) [m/s]: tau_w / rho = rho_air c_w u_w |u_w| / rho_w
  * (Eq. wind_u-stress). */
@@ -304,7 +325,8 @@ mlb_status mlb_net_targets(mlb_net* net, mlb_grid* g, float* t_dev);
  * grid-scale content the step damps only slowly), its mean surface
  * perturbation is removed so the basin holds its still-water volume (closed
  * basins conserve it, so the steady state has that volume), and discharge
- * is zero on wall nodes. */
+ * is zero on wall nodes.  MLB_E_STATE for a grid with a node mask (the net
+ * knows rectangular basins only; the same holds for mlb_warm_start_run). */
 mlb_status mlb_net_infer(mlb_net* net, mlb_grid* g);
 mlb_status mlb_net_save(const mlb_net* net, const char* path);
 mlb_status mlb_net_load(mlb_net* net, const char* path);

@@ -43,6 +43,7 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     BasinDev b{};
     for (int k = 0; k < 2; ++k) { b.eta[k] = g->eta[k]; b.qx[k] = g->qx[k]; b.qy[k] = g->qy[k]; }
     b.H = g->H;
+    b.mask = g->dmask;
     b.stepc = g->stepc;
     b.nx = g->p.nx; b.ny = g->p.ny; b.ld = g->ld;
     b.swap = swap;
@@ -77,12 +78,38 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     return b;
 }
 
+// Mask classification of a one-step tile: TILE_MASKED when its window
+// (columns x0-1 .. x0+62, rows y0-1 .. y0+rows, wrapped or clamped as the
+// kernel loads them) holds a WALL or SOLID node; false when every node it
+// owns is SOLID (the tile has nothing to write and is left out).
+bool classify_tile(const mlb_grid* g, TileDev& t)
+{
+    const int nx = g->p.nx, ny = g->p.ny, ld = g->ld;
+    const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
+    auto wrap = [](int v, int n, bool per) { return per ? ((v % n) + n) % n : std::min(std::max(v, 0), n - 1); };
+    const uint8_t* m = g->hmask.data();
+    bool any = false, owned_water = false;
+    for (int r = t.y0 - 1; r <= t.y0 + t.rows; ++r) {
+        const int rr = wrap(r, ny, py);
+        for (int x = t.x0 - 1; x <= t.x0 + kStripOut; ++x) {
+            const uint8_t k = m[(size_t)rr * ld + wrap(x, nx, px)];
+            any |= k != NODE_FLUID;
+            const bool own = x >= t.x0 && x < t.x0 + kStripOut && x >= t.xo && x < nx && r >= t.yo &&
+                             r < t.y0 + t.rows;
+            owned_water |= own && k != NODE_SOLID;
+        }
+    }
+    if (any) t.flags |= TILE_MASKED;
+    return owned_water;
+}
+
 // Wave tiles of one basin: strips of `strip` output columns (62 for one step
 // per pass, 60 for two), tiles of `rows` rows.  The last strip / tile is
 // shifted inward so that edge extrapolation always finds its inner nodes in
 // the same tile; it then stores only what it owns.  Two-step tiles never
 // start at row 1: their first stage would then compute row 0 of an open S
 // edge, which waits for rows 1 and 2 (such a tile starts at row 0 instead).
+// With a mask (one-step tiles only) tiles are classified by classify_tile.
 void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out, int strip)
 {
     // List order = dispatch order: row band by row band, so one workgroup's
@@ -103,6 +130,7 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
             t.yo = yo;
             t.y0 = y0;
             t.rows = yend - y0;
+            if (!g->hmask.empty() && strip == kStripOut && !classify_tile(g, t)) continue;
             out.push_back(t);
         }
     }
@@ -158,11 +186,13 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.ht.clear();
         g->plan.ht2.clear();
         make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
-        if (g->opts.tblock == 2) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
+        // masked grids run one step per pass
+        if (g->opts.tblock == 2 && !g->dmask) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
         g->plan.hb[0].first_tile2 = 0;
         g->plan.hb[0].ntiles2 = (int)g->plan.ht2.size();
+        g->plan.masked = g->dmask != nullptr;
         CHK(plan_alloc(c, g->plan));
         g->stale_plan = false;
         g->dirty = false;
@@ -203,7 +233,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     int64_t nl = 0;
     auto eager = [&](int k, bool diag) -> mlb_status {
         HIPCHK(launch_step(P.db, k == 2 ? P.dt2 : P.dt, k == 2 ? nt2 : nt1, P.parity, P.dpart, diag ? 1 : 0, k,
-                           dyn, c->stream));
+                           P.masked ? 1 : 0, dyn, c->stream));
         P.parity ^= 1;
         ++nl;
         return MLB_OK;
@@ -221,13 +251,13 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     if (o.persistent && multi > 0 && !P.coop_failed) {
         const int nt = kind == 2 ? nt2 : nt1;
         const int nblk = (nt + kBlock / kWave - 1) / (kBlock / kWave);
-        if (persistent_capacity(kind, c->ncu) < nblk) {
+        if (persistent_capacity(kind, P.masked ? 1 : 0, c->ncu) < nblk) {
             P.coop_failed = true;
         } else {
             while (multi > 0) {
                 const int np = (int)std::min<int64_t>(multi, 1 << 12);
                 const hipError_t e = launch_persistent(P.db, kind == 2 ? P.dt2 : P.dt, nt, P.parity, np, kind,
-                                                       P.dsync, P.sync_base, c->spin_limit, c->stream);
+                                                       P.masked ? 1 : 0, P.dsync, P.sync_base, c->spin_limit, c->stream);
                 if (e != hipSuccess) {
                     (void)hipGetLastError();
                     P.coop_failed = true;   // ordinary launches for the rest
@@ -250,8 +280,8 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             int par = P.parity;
             hipError_t le = hipSuccess;
             for (int i = 0; i < glaunch && le == hipSuccess; ++i) {
-                le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind, dyn,
-                                 c->stream);
+                le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind,
+                                 P.masked ? 1 : 0, dyn, c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -334,6 +364,19 @@ mlb_status upload_host_state(mlb_grid* g, const double* h, const double* hu, con
     }
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     return MLB_OK;
+}
+
+// Sum of the still-water depth over the water (every node but SOLID ones):
+// the mass diagnostic adds the reduced sum of eta to it.
+double water_depth_sum(const mlb_grid* g)
+{
+    double sum = 0;
+    for (int j = 0; j < g->p.ny; ++j)
+        for (int i = 0; i < g->p.nx; ++i) {
+            const size_t o = (size_t)j * g->ld + i;
+            if (g->hmask.empty() || g->hmask[o] != NODE_SOLID) sum += g->Hd[o];
+        }
+    return sum;
 }
 
 mlb_status set_step(mlb_grid* g, int64_t s)
@@ -530,6 +573,7 @@ mlb_status mlb_grid_destroy(mlb_grid* g)
     (void)hipStreamSynchronize(g->ctx->stream);
     g->plan.release();
     if (g->own) (void)hipFree(g->base);
+    if (g->dmask) (void)hipFree(g->dmask);
     g->ctx->live--;
     delete g;
     return MLB_OK;
@@ -543,7 +587,7 @@ mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld)
     const int nx = g->p.nx, ny = g->p.ny;
     g->Hf.assign((size_t)g->ld * ny, 1.0f);
     g->Hd.assign((size_t)g->ld * ny, 1.0);
-    double sum = 0, hmax = 0;
+    double hmax = 0;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             const double Hd = g->p.zeta_ref - zb[(size_t)j * ld + i];
@@ -551,12 +595,11 @@ mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld)
             const float Hs = (float)Hd;
             g->Hf[(size_t)j * g->ld + i] = Hs;
             g->Hd[(size_t)j * g->ld + i] = Hd;
-            sum += Hd;
             hmax = std::max(hmax, Hd);
         }
     if (g->p.g * hmax > g->e * g->e)
         return fail(MLB_E_UNSTABLE, "g * H_max > e^2: choose a larger nu (e = 6 nu / dx)");
-    g->sumH = sum;
+    g->sumH = water_depth_sum(g);
     g->Hmax = hmax;
     HIPCHK(hipMemcpyAsync(g->H, g->Hf.data(), g->Hf.size() * sizeof(float), hipMemcpyHostToDevice,
                           g->ctx->stream));
@@ -607,6 +650,49 @@ mlb_status mlb_set_edge_discharge(mlb_grid* g, int edge, double qx, double qy)
     if (g->p.edge[edge] != MLB_EDGE_DISCHARGE) return fail(MLB_E_INVAL, "edge is not a DISCHARGE edge");
     g->bc_qx[edge] = qx; g->bc_qy[edge] = qy;
     g->dirty = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
+{
+    GRID_OK(g);
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    const int nx = g->p.nx, ny = g->p.ny;
+    if (!kind) {
+        if (g->dmask) (void)hipFree(g->dmask);
+        g->dmask = nullptr;
+        g->hmask.clear();
+    } else {
+        if (ld < nx) return fail(MLB_E_INVAL, "ld < nx");
+        std::vector<uint8_t> m((size_t)g->ld * ny, (uint8_t)NODE_FLUID);
+        int64_t solid = 0;
+        const int reach = g->p.extrap_order;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const uint8_t k = kind[(size_t)j * ld + i];
+                if (k > NODE_SOLID) return fail(MLB_E_INVAL, "node kind must be FLUID, WALL or SOLID");
+                m[(size_t)j * g->ld + i] = k;
+                if (k == NODE_FLUID) continue;
+                solid += k == NODE_SOLID;
+                const int dist[4] = {i, nx - 1 - i, j, ny - 1 - j};
+                for (int ed = 0; ed < 4; ++ed)
+                    if (is_open(g->p.edge[ed]) && dist[ed] <= reach)
+                        return fail(MLB_E_INVAL, "nodes an open edge extrapolates from must be FLUID");
+            }
+        if (solid == (int64_t)nx * ny) return fail(MLB_E_INVAL, "every node is SOLID");
+        if (!g->dmask) HIPCHK(hipMalloc((void**)&g->dmask, m.size()));
+        HIPCHK(hipMemcpyAsync(g->dmask, m.data(), m.size(), hipMemcpyHostToDevice, g->ctx->stream));
+        // SOLID nodes are never written: both buffers must hold their values
+        const size_t bytes = g->plane * sizeof(float);
+        const int o = g->cur ^ 1;
+        HIPCHK(hipMemcpyAsync(g->eta[o], g->eta[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qx[o], g->qx[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qy[o], g->qy[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipStreamSynchronize(g->ctx->stream));
+        g->hmask.swap(m);
+    }
+    g->sumH = water_depth_sum(g);
+    g->stale_plan = true;
     return MLB_OK;
 }
 
@@ -812,6 +898,8 @@ static mlb_status batch_plan(mlb_batch* b)
     b->plan.ht.clear();
     b->plan.ht2.clear();
     b->plan.parity = 0;
+    bool masked = false;
+    for (auto* g : b->grids) masked |= g->dmask != nullptr;
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
         mlb_grid* g = b->grids[i];
@@ -820,10 +908,11 @@ static mlb_status batch_plan(mlb_batch* b)
         make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
         d.first_tile2 = (int)b->plan.ht2.size();
-        if (b->opts.tblock == 2) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
+        if (b->opts.tblock == 2 && !masked) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
     }
+    b->plan.masked = masked;
     CHK(plan_alloc(b->ctx, b->plan));
     b->stale_plan = false;
     return MLB_OK;
@@ -1007,13 +1096,15 @@ bool fits_persistent(mlb_ctx* c, const std::vector<mlb_grid*>& gs, int rows, int
 {
     int64_t tiles = 0;
     const int strip = tb == 2 ? kStripOut2 : kStripOut;
+    bool masked = false;
+    for (auto* g : gs) masked |= g->dmask != nullptr;
     for (auto* g : gs) {
         std::vector<TileDev> t;
         make_tiles(g, 0, rows, t, strip);
         tiles += (int64_t)t.size();
     }
     const int64_t nblk = (tiles + kBlock / kWave - 1) / (kBlock / kWave);
-    return nblk <= persistent_capacity(tb, c->ncu);
+    return nblk <= persistent_capacity(tb, masked ? 1 : 0, c->ncu);
 }
 
 // Times `steps` steps of each candidate; `prepare` rebuilds the plan for the
@@ -1026,6 +1117,8 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
+    bool masked = false;   // masked grids run one step per pass
+    for (auto* g : gs) masked |= g->dmask != nullptr;
     for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))
@@ -1033,6 +1126,7 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
         for (int cap : kTuneCaps) {
             // persistent launches need every tile resident: no workgroup cap
             if (ps && (cap != 0 || !fits_persistent(c, gs, tr, tb))) continue;
+            if (masked && tb == 2) continue;
             mlb_exec_opts o = base;
             o.persistent = ps;
             o.tblock = tb;
@@ -1076,7 +1170,8 @@ mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_
     if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
     if (steps < 2) return fail(MLB_E_INVAL, "steps must be >= 2");
     mlb_ctx* c = g->ctx;
-    const std::string key = c->arch + "_g" + std::to_string(g->p.nx) + "x" + std::to_string(g->p.ny);
+    const std::string key = c->arch + "_g" + std::to_string(g->p.nx) + "x" + std::to_string(g->p.ny) +
+                            (g->dmask ? "m" : "");
     mlb_exec_opts o = g->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_set_exec_opts(g, &o));
@@ -1114,8 +1209,10 @@ mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_pat
     mlb_ctx* c = b->ctx;
     CHK(check_stream(c));
     int64_t nodes = 0;
-    for (auto* g : b->grids) nodes += (int64_t)g->p.nx * g->p.ny;
-    const std::string key = c->arch + "_b" + std::to_string(b->grids.size()) + "n" + std::to_string(nodes);
+    bool masked = false;
+    for (auto* g : b->grids) { nodes += (int64_t)g->p.nx * g->p.ny; masked |= g->dmask != nullptr; }
+    const std::string key = c->arch + "_b" + std::to_string(b->grids.size()) + "n" + std::to_string(nodes) +
+                            (masked ? "m" : "");
     mlb_exec_opts o = b->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_batch_set_exec_opts(b, &o));

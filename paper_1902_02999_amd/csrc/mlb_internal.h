@@ -16,6 +16,10 @@ constexpr int kBlock = 256;            // 4 independent waves per workgroup
 constexpr int kPartials = 6;           // per-tile FP64 partial sums
 
 enum { EDGE_WALL = 0, EDGE_PERIODIC = 1, EDGE_DEPTH = 2, EDGE_DISCHARGE = 3 };
+// Node kinds of the optional geometry mask.
+enum { NODE_FLUID = 0, NODE_WALL = 1, NODE_SOLID = 2 };
+// TileDev::flags
+enum { TILE_MASKED = 1 };   // the tile's window holds a WALL or SOLID node
 
 // Per-basin descriptor read by the step kernel (device memory).
 struct BasinDev {
@@ -23,6 +27,7 @@ struct BasinDev {
     float* qx[2];
     float* qy[2];
     const float* H;
+    const uint8_t* mask;   // node kinds (pitch ld bytes) or nullptr
     int64_t* stepc;        // [2]: step counter, read from [rd], written to [1-rd]
     int32_t nx, ny, ld;
     int32_t swap;          // buffer read by a launch of parity p is p ^ swap
@@ -58,21 +63,24 @@ struct TileDev {
     int32_t basin;
     int32_t x0, y0, rows;  // first output column / row and number of rows computed
     int32_t xo, yo;        // first owned column / row (overlapped edge tiles store only these)
-    int32_t pad[2];
+    int32_t flags;         // TILE_*
+    int32_t pad;
 };
 
 // Host-side launchers (mlb_kernels.hip).
 // tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
-// of kStripOut2 columns, no diag.
+// of kStripOut2 columns, no diag.  masked: the tile list may hold
+// TILE_MASKED tiles (one-step only).
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s);
+                       double* d_partials, int diag, int tblock, int masked, unsigned dyn_lds, hipStream_t s);
 // npasses passes of `kind` steps in one cooperative launch (all tiles
 // resident); base = sync->count at launch.  Fails (no launch) when the grid
 // cannot be co-resident.
 hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity0,
-                             int npasses, int kind, SyncState* sync, uint64_t base, int spin_limit, hipStream_t s);
+                             int npasses, int kind, int masked, SyncState* sync, uint64_t base, int spin_limit,
+                             hipStream_t s);
 // Workgroups of the persistent kernel that fit on the device at once.
-int persistent_capacity(int kind, int ncu);
+int persistent_capacity(int kind, int masked, int ncu);
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);

@@ -11,9 +11,11 @@
 //     - the rest-particle equilibrium cancels the hydrostatic parts at x;
 //     - the force is folded into the linear part of A_a as q~ = q + (dt/2) F
 //       (C_a / e = lambda_a / (3e)), which carries the link-midpoint average;
-//     - a bounced link (upstream outside a wall) takes A_abar(x) and no bed
-//       or force term, i.e. the values of a virtual neighbour with eta_y = eta_x
-//       and A_a(y) = A_abar(x).
+//     - a bounced link (upstream outside a wall edge, or a SOLID node of the
+//       optional geometry mask) takes A_abar(x) and no bed or force term,
+//       i.e. the values of a virtual neighbour with eta_y = eta_x and
+//       A_a(y) = A_abar(x); WALL nodes of the mask get q = 0 after the
+//       update, SOLID nodes are never written.
 //   With Out_a(n) = A_a built from q~(n), kk = 2K/(3e^2), K = q.u:
 //     eta' = eta + sum_a Out_a(y_a) - kk + g/(2e^2) sum_a C_a P_a
 //     q'   = (dt/2) F(x) + e sum_a e^_a Out_a(y_a) + g/(2e) sum_a C_a e^_a P_a
@@ -33,6 +35,9 @@
 //   second stage three rows behind it that computes level n+2; only lanes
 //   2..61 (60 columns) are valid after two steps.  HBM traffic per step is
 //   halved; level n+1 never leaves the registers.
+//   Tiles whose window holds WALL or SOLID nodes of a mask take the edge path
+//   with one extra byte per node (the kind) and a per-link bounce test; the
+//   rest of a masked grid runs the ordinary paths.
 #include "mlb_internal.h"
 
 // Build-time knob (results are bitwise independent of it):
@@ -54,6 +59,14 @@ __device__ __forceinline__ float from_right(float v)  // lane i receives lane i+
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
         __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
+}
+__device__ __forceinline__ int from_left_i(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int from_right_i(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -128,6 +141,7 @@ struct Row {
     float eta, h;
     float S1, S2, N1, N2, E1, E2;
     float o1l, o5r, o2l, o3, o4r, o6r, o7, o8l;
+    int mk, ms;            // masked tiles: node kind; SOLID at x-1, x, x+1 (bits 0, 1, 2)
 };
 
 template <bool EDGE>
@@ -148,6 +162,15 @@ __device__ __forceinline__ void exchange(const Node& d, Row& R)
         R.E2 = from_left(d.o[1]) - from_right(d.o[5]);
         R.o1l = R.o5r = R.o2l = R.o3 = R.o4r = R.o6r = R.o7 = R.o8l = 0.0f;
     }
+}
+
+// Node kinds of a row in a masked tile: its own kind and which of the nodes
+// x-1, x, x+1 are SOLID (their links into x are bounced).
+__device__ __forceinline__ void mask_row(int m, Row& R)
+{
+    const int s = m == NODE_SOLID ? 1 : 0;
+    R.mk = m;
+    R.ms = from_left_i(s) | (s << 1) | (from_right_i(s) << 2);
 }
 
 // Link of node x with the lane neighbour of row R on its right / left.
@@ -227,7 +250,7 @@ __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, co
     qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
 }
 
-struct Raw { float eta, qx, qy, H; };
+struct Raw { float eta, qx, qy, H; int m; };   // m: node kind (masked tiles)
 
 // Index of a column / row to load: wrapped on periodic axes (lanes of a strip
 // can reach past the grid on narrow grids), clamped otherwise (values there
@@ -266,13 +289,17 @@ __device__ __forceinline__ void stf(gfloat* base, uint32_t byte_off, float v)
 #endif
 }
 
+typedef __attribute__((address_space(1))) const uint8_t gcu8;
+
+template <bool MASK>
 __device__ __forceinline__ Raw load_raw(const gfloat* __restrict__ E0, const gfloat* __restrict__ QX0,
                                         const gfloat* __restrict__ QY0, const gfloat* __restrict__ HH,
-                                        uint32_t o)
+                                        gcu8* __restrict__ MK, uint32_t o)
 {
     const uint32_t b = o * 4u;
     Raw w;
     w.eta = ldf(E0, b); w.qx = ldf(QX0, b); w.qy = ldf(QY0, b); w.H = ldf(HH, b);
+    w.m = MASK ? (int)MK[o] : 0;
     return w;
 }
 
@@ -377,6 +404,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
     do {                                                                                          \
         derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
         exchange<EDGE>(DN, N);                                                                    \
+        if (MASK) mask_row(RAWN.m, N);                                                            \
         LOADNEXT;                                                                                 \
         const float lE = link_right(DC.h, DC.eta, C), lN = link(DC.h, DC.eta, N.h, N.eta);        \
         const float lNE = link_right(DC.h, DC.eta, N), lNW = link_left(DC.h, DC.eta, N);          \
@@ -387,18 +415,24 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             P[5] = lE;             P[6] = lNE;        P[7] = lN;       P[8] = lNW;                \
             oy[1] = C.o1l; oy[2] = S.o2l; oy[3] = S.o3;  oy[4] = S.o4r;  /* W SW S SE */          \
             oy[5] = C.o5r; oy[6] = N.o6r; oy[7] = N.o7;  oy[8] = N.o8l;  /* E NE N NW */          \
-            /* bounced link a: no bed term, A_a(y) = A_abar(x) */                                 \
+            /* bounced link a (upstream outside the grid or SOLID): no bed term,                  \
+               A_a(y) = A_abar(x) */                                                              \
             const bool sout = !per_y && (r) == 0, nout = !per_y && (r) == ny - 1;                 \
-            const bool bb2_ = L.wout || sout, bb4_ = L.eout || sout, bb6_ = L.eout || nout,             \
-                       bb8_ = L.wout || nout;                                                       \
-            P[1] = L.wout ? 0.0f : P[1]; oy[1] = L.wout ? DC.o[5] : oy[1];                        \
-            P[2] = bb2_ ? 0.0f : P[2];     oy[2] = bb2_ ? DC.o[6] : oy[2];                            \
-            P[3] = sout ? 0.0f : P[3];   oy[3] = sout ? DC.o[7] : oy[3];                          \
-            P[4] = bb4_ ? 0.0f : P[4];     oy[4] = bb4_ ? DC.o[8] : oy[4];                            \
-            P[5] = L.eout ? 0.0f : P[5]; oy[5] = L.eout ? DC.o[1] : oy[5];                        \
-            P[6] = bb6_ ? 0.0f : P[6];     oy[6] = bb6_ ? DC.o[2] : oy[6];                            \
-            P[7] = nout ? 0.0f : P[7];   oy[7] = nout ? DC.o[3] : oy[7];                          \
-            P[8] = bb8_ ? 0.0f : P[8];     oy[8] = bb8_ ? DC.o[4] : oy[8];                            \
+            bool bb1_ = L.wout, bb2_ = L.wout || sout, bb3_ = sout, bb4_ = L.eout || sout;        \
+            bool bb5_ = L.eout, bb6_ = L.eout || nout, bb7_ = nout, bb8_ = L.wout || nout;        \
+            if (MASK) {                                                                           \
+                bb1_ = bb1_ || (C.ms & 1); bb5_ = bb5_ || (C.ms & 4);                             \
+                bb2_ = bb2_ || (S.ms & 1); bb3_ = bb3_ || (S.ms & 2); bb4_ = bb4_ || (S.ms & 4);  \
+                bb8_ = bb8_ || (N.ms & 1); bb7_ = bb7_ || (N.ms & 2); bb6_ = bb6_ || (N.ms & 4);  \
+            }                                                                                     \
+            P[1] = bb1_ ? 0.0f : P[1];     oy[1] = bb1_ ? DC.o[5] : oy[1];                        \
+            P[2] = bb2_ ? 0.0f : P[2];     oy[2] = bb2_ ? DC.o[6] : oy[2];                        \
+            P[3] = bb3_ ? 0.0f : P[3];     oy[3] = bb3_ ? DC.o[7] : oy[3];                        \
+            P[4] = bb4_ ? 0.0f : P[4];     oy[4] = bb4_ ? DC.o[8] : oy[4];                        \
+            P[5] = bb5_ ? 0.0f : P[5];     oy[5] = bb5_ ? DC.o[1] : oy[5];                        \
+            P[6] = bb6_ ? 0.0f : P[6];     oy[6] = bb6_ ? DC.o[2] : oy[6];                        \
+            P[7] = bb7_ ? 0.0f : P[7];     oy[7] = bb7_ ? DC.o[3] : oy[7];                        \
+            P[8] = bb8_ ? 0.0f : P[8];     oy[8] = bb8_ ? DC.o[4] : oy[8];                        \
             update_edge(B, DC, P, oy, en, qxn, qyn);                                              \
         } else {                                                                                  \
             update_fast(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, qxn, qyn);                    \
@@ -418,7 +452,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                 le2 = from_left(le1); lx2 = from_left(lx1); ly2 = from_left(ly1);                 \
             }                                                                                     \
             const bool onS = !per_y && (r) == 0, onN = !per_y && (r) == ny - 1;                   \
-            const bool wall = L.wall_x || (onS && L.kS == EDGE_WALL) || (onN && L.kN == EDGE_WALL); \
+            const bool wall = L.wall_x || (onS && L.kS == EDGE_WALL) || (onN && L.kN == EDGE_WALL) || \
+                              (MASK && C.mk == NODE_WALL);                                        \
             float fe = en, fx = qxn, fy = qyn;                                                    \
             if (wall) {                                                                           \
                 fx = 0.0f; fy = 0.0f;                                                             \
@@ -464,6 +499,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                          \
             V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                            \
             en = fe; qxn = fx; qyn = fy;                                                          \
+            /* SOLID nodes keep their values: both buffers hold them already */                   \
+            if (MASK && C.mk == NODE_SOLID) emit = false;                                         \
         }                                                                                         \
         if (emit) { EMIT(en, qxn, qyn, DC); }                                                         \
     } while (0)
@@ -471,10 +508,12 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 #define MLB_NOTHING(...) do { } while (0)
 
 // ------------------------------------------------------------------ one step per pass
-template <bool EDGE, bool DIAG, bool FRIC>
+// MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only).
+template <bool EDGE, bool DIAG, bool FRIC, bool MASK>
 __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd, int64_t step,
                                          double* __restrict__ part)
 {
+    static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
     const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
@@ -488,12 +527,13 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     gfloat* __restrict__ E1 = (gfloat*)B.eta[wr];
     gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
+    gcu8* __restrict__ MK = (gcu8*)B.mask;
     Stage V;
     stage_setup<EDGE>(B, L, (double)(step + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
-#define MLB_LD(row) load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<MASK>(E0, QX0, QY0, HH, MK, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
     // Software pipeline: a row's raw values are loaded three rows before they
     // are derived.  Raw slots, window rows and derived nodes rotate with
     // period 3, so the loop is unrolled by 3 and the rotation is a renaming
@@ -505,11 +545,13 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
         const Raw w = MLB_LD(r0 - 1);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d0);
         exchange<EDGE>(d0, R0);
+        if (MASK) mask_row(w.m, R0);
     }
     {
         const Raw w = MLB_LD(r0);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d1);
         exchange<EDGE>(d1, R1);
+        if (MASK) mask_row(w.m, R1);
     }
     carry_init<EDGE>(d0, R1, V.cy);
     int r = r0;
@@ -572,6 +614,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
+    constexpr bool MASK = false;   // masked grids run one step per pass
     const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
     const int wr = rd ^ 1;
@@ -589,7 +632,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
-#define MLB_LD(row) load_raw(E0, QX0, QY0, HH, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<false>(E0, QX0, QY0, HH, nullptr, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
     // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
     Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
     Node a0, a1, a2;
@@ -685,7 +728,9 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 // One wave's share of a pass: tile t advances its basin by one step (KIND 1,
 // with the fused reduction when DIAG) or two (KIND 2).  `step` reads the
 // basin's step counter at buffer rd; the basin's first tile advances it.
-template <int KIND, bool DIAG, class StepRead>
+// MASKED: the tile list may hold TILE_MASKED tiles (a separate kernel, so
+// that grids without a mask keep the smaller register budget).
+template <int KIND, bool DIAG, bool MASKED, class StepRead>
 __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles,
                                           int t, int parity, double* __restrict__ partials, StepRead step_at)
 {
@@ -703,12 +748,15 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         const bool edge = (!B.per_x && (T.x0 == 0 || T.x0 + kStripOut >= B.nx)) ||
                           (!B.per_y && (T.y0 == 0 || T.y0 + T.rows >= B.ny));
         double* part = partials + (size_t)t * kPartials;
+        const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         if (B.cfr != 0.0f) {
-            if (edge) run_tile<true, DIAG, true>(B, T, rd, step, part);
-            else run_tile<false, DIAG, true>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, true, MASKED>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, true, false>(B, T, rd, step, part);
+            else run_tile<false, DIAG, true, false>(B, T, rd, step, part);
         } else {
-            if (edge) run_tile<true, DIAG, false>(B, T, rd, step, part);
-            else run_tile<false, DIAG, false>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, false, MASKED>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, false, false>(B, T, rd, step, part);
+            else run_tile<false, DIAG, false, false>(B, T, rd, step, part);
         }
     } else {
         // a two-step tile needs the boundary logic when stage A's rows
@@ -741,14 +789,14 @@ struct CoherentStep {
 // One pass of one step.  One wave per tile, tiles in list order (largest
 // basins first): the hardware dispatcher hands out workgroups in index
 // order, so the list is consumed as a queue without a software loop.
-template <bool DIAG>
+template <bool DIAG, bool MASKED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                  int parity, double* __restrict__ partials)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<1, DIAG>(basins, tiles, t, parity, partials, PlainStep{});
+    pass_tile<1, DIAG, MASKED>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
 // One pass of two steps, over tiles of 60-column strips.
@@ -758,7 +806,7 @@ void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -767,7 +815,7 @@ void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict
 // included).  Waiting is bounded: after spin_limit polls, or once another
 // workgroup has given up, the error flag is set and every workgroup leaves
 // the loop at that barrier, so the grid always drains.
-template <int KIND>
+template <int KIND, bool MASKED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                        int parity0, int npasses, SyncState* __restrict__ sync, uint64_t base, int spin_limit)
@@ -780,7 +828,7 @@ void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __res
     __syncthreads();
     if (abort_flag) return;
     for (int p = 0; p < npasses; ++p) {
-        if (t < ntiles) pass_tile<KIND, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
+        if (t < ntiles) pass_tile<KIND, false, MASKED>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
         __threadfence();   // release: this wave's stores, device-wide
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -821,6 +869,7 @@ __global__ __launch_bounds__(kBlock) void reduce_state_kernel(const BasinDev* __
     if (own_col) {
         for (int r = T.yo; r < T.y0 + T.rows; ++r) {
             const size_t o = (size_t)r * B.ld + x;
+            if (B.mask && B.mask[o] == NODE_SOLID) continue;   // not part of the water
             const float en = B.eta[cur][o], a = B.qx[cur][o], b = B.qy[cur][o];
             const double h = (double)B.H[o] + (double)en;
             if (__builtin_isfinite(en) && __builtin_isfinite(a) && __builtin_isfinite(b) && h > 0.0) {
@@ -901,49 +950,61 @@ int step_occupancy(int diag)
 {
     int n = 0;
     if (diag)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true, false>, kBlock, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false, false>, kBlock, 0);
     return n > 0 ? n : 1;
 }
 
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, unsigned dyn_lds, hipStream_t s)
+                       double* d_partials, int diag, int tblock, int masked, unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1 && (tblock != 2 || diag)) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag || masked)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (tblock == 2)
         hipLaunchKernelGGL(step2_kernel, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
+    else if (diag && masked)
+        hipLaunchKernelGGL((step_kernel<true, true>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+                           ntiles, parity, d_partials);
     else if (diag)
-        hipLaunchKernelGGL(step_kernel<true>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+        hipLaunchKernelGGL((step_kernel<true, false>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+                           ntiles, parity, d_partials);
+    else if (masked)
+        hipLaunchKernelGGL((step_kernel<false, true>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
                            ntiles, parity, d_partials);
     else
-        hipLaunchKernelGGL(step_kernel<false>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+        hipLaunchKernelGGL((step_kernel<false, false>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
                            ntiles, parity, d_partials);
     return hipGetLastError();
 }
 
 hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity0,
-                             int npasses, int kind, SyncState* sync, uint64_t base, int spin_limit, hipStream_t s)
+                             int npasses, int kind, int masked, SyncState* sync, uint64_t base, int spin_limit,
+                             hipStream_t s)
 {
+    if (kind == 2 && masked) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     void* args[] = {(void*)&d_basins, (void*)&d_tiles, (void*)&ntiles, (void*)&parity0, (void*)&npasses,
                     (void*)&sync, (void*)&base, (void*)&spin_limit};
     if (kind == 2)
-        return hipLaunchCooperativeKernel((const void*)persistent_kernel<2>, grid, dim3(kBlock), args, 0, s);
-    return hipLaunchCooperativeKernel((const void*)persistent_kernel<1>, grid, dim3(kBlock), args, 0, s);
+        return hipLaunchCooperativeKernel((const void*)persistent_kernel<2, false>, grid, dim3(kBlock), args, 0, s);
+    if (masked)
+        return hipLaunchCooperativeKernel((const void*)persistent_kernel<1, true>, grid, dim3(kBlock), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)persistent_kernel<1, false>, grid, dim3(kBlock), args, 0, s);
 }
 
-int persistent_capacity(int kind, int ncu)
+int persistent_capacity(int kind, int masked, int ncu)
 {
     int n = 0;
     if (kind == 2)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<2>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<2, false>, kBlock, 0);
+    else if (masked)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<1, true>, kBlock, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<1>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<1, false>, kBlock, 0);
     return n * ncu;
 }
 

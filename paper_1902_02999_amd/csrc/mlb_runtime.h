@@ -61,6 +61,7 @@ struct Plan {
     uint64_t sync_base = 0;      // dsync->count when the next persistent launch starts
     bool coop_failed = false;    // a persistent launch was refused: use ordinary ones
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
+    bool masked = false;       // some basin has a node mask: one-step passes, masked kernel
     bool built = false;
 
     void release()
@@ -110,6 +111,8 @@ struct mlb_grid {
     std::vector<float> Hf;     // stored (FP32) still-water depth, host copy
     std::vector<double> Hd;    // still-water depth zeta_ref - z_b as given (FP64):
                                // host conversions h <-> eta and the mass use it
+    uint8_t* dmask = nullptr;  // node kinds on the device (pitch ld bytes), or none
+    std::vector<uint8_t> hmask;  // host copy (pitch ld), empty without a mask
     int cur = 0;
     int64_t step = 0;
     double e = 0, dt = 0, sumH = 0, Hmax = 0;

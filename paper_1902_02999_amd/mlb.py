@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmlb.so")
 
 WALL, PERIODIC, DEPTH, DISCHARGE = 0, 1, 2, 3
+NODE_FLUID, NODE_WALL, NODE_SOLID = 0, 1, 2   # MLB_NODE_*
 W, E, S, N = 0, 1, 2, 3
 
 STATUS = {0: "MLB_OK", -1: "MLB_E_INVAL", -2: "MLB_E_NOMEM", -3: "MLB_E_DEVICE",
@@ -108,6 +109,7 @@ SIGNATURES = {
     "mlb_grid_create": (C.c_int, [_VP, C.POINTER(Params), _VP, C.c_size_t, C.POINTER(_VP)]),
     "mlb_grid_destroy": (C.c_int, [_VP]),
     "mlb_set_bathymetry": (C.c_int, [_VP, _DP, C.c_int64]),
+    "mlb_set_mask": (C.c_int, [_VP, C.POINTER(C.c_uint8), C.c_int64]),
     "mlb_set_wind": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_wind_stress": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_chezy": (C.c_int, [_VP, C.c_double]),
@@ -269,6 +271,14 @@ class Grid:
         a = _f64(zb, (self.ny, self.nx))
         _check(lib().mlb_set_bathymetry(self.h, _dptr(a), self.nx), "mlb_set_bathymetry")
 
+    def set_mask(self, kind):
+        """Node kinds [ny][nx] (NODE_FLUID / NODE_WALL / NODE_SOLID); None removes the mask."""
+        if kind is None:
+            _check(lib().mlb_set_mask(self.h, None, self.nx), "mlb_set_mask")
+            return
+        a = np.ascontiguousarray(np.asarray(kind).reshape(self.ny, self.nx), np.uint8)
+        _check(lib().mlb_set_mask(self.h, a.ctypes.data_as(C.POINTER(C.c_uint8)), self.nx), "mlb_set_mask")
+
     def set_wind(self, uwx, uwy):
         _check(lib().mlb_set_wind(self.h, uwx, uwy), "mlb_set_wind")
 
@@ -403,6 +413,8 @@ def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
                     omega=spec.omega)
     g = Grid(ctx, p, workspace)
     g.set_bathymetry(spec.zb)
+    if getattr(spec, "kind", None) is not None:
+        g.set_mask(spec.kind)
     if spec.wind_speed is not None:
         g.set_wind(*spec.wind_speed)
     if spec.wind_stress is not None:
