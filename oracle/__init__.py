@@ -50,7 +50,7 @@ class Problem(C.Structure):
                 ("bc_h_mean", C.c_double * 4), ("bc_amp", C.c_double * 4),
                 ("bc_period", C.c_double * 4), ("bc_phase", C.c_double * 4),
                 ("bc_qx", C.c_double * 4), ("bc_qy", C.c_double * 4),
-                ("kind", C.c_void_p)]
+                ("kind", C.c_void_p), ("hbar_implicit", C.c_int32), ("pad2_", C.c_int32)]
 
 
 def lib():
@@ -69,6 +69,7 @@ def lib():
             L.mref_depth_bc.argtypes = [C.POINTER(Problem), C.c_int, C.c_double]
             L.mref_step.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_double, dp, dp, dp, C.c_int]
             L.mref_node.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_double, C.c_int, C.c_int, dp]
+            L.mref_node_trial.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_int, C.c_int, C.c_double, dp]
             L.mref_run.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, C.c_int64, C.c_int64, dp, C.c_int]
             L.mref_diag.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp,
                                     C.c_void_p, C.c_void_p, C.c_void_p, dp]
@@ -121,7 +122,8 @@ class Basin:
     ``zb`` is the bed, ``h, qx, qy`` the depth and discharge (hu, hv).
     Edge kinds are (W, E, S, N) with WALL/PERIODIC/DEPTH/DISCHARGE.
     ``kind`` is an optional uint8 [ny][nx] node-kind mask (FLUID, WALL_NODE,
-    SOLID).
+    SOLID).  ``hbar_implicit`` selects the link depth with the node's new-time
+    depth (the definition given with Eq. feq-full) instead of Eq. h-bar.
     """
     nx: int
     ny: int
@@ -143,6 +145,7 @@ class Basin:
     step_index: int = 0
     threads: int = 0
     kind: np.ndarray = None
+    hbar_implicit: bool = False
 
     def __post_init__(self):
         self.zb = np.ascontiguousarray(self.zb, np.float64).reshape(self.ny, self.nx)
@@ -168,6 +171,7 @@ class Basin:
         for k, (a, b) in self.discharge_bc.items():
             p.bc_qx[k], p.bc_qy[k] = a, b
         p.kind = None if self.kind is None else self.kind.ctypes.data
+        p.hbar_implicit = int(bool(self.hbar_implicit))
         return p
 
     @property
@@ -205,6 +209,18 @@ class Basin:
         rc = lib().mref_node(C.byref(p), self.zb, np.ascontiguousarray(h, np.float64),
                              np.ascontiguousarray(qx, np.float64),
                              np.ascontiguousarray(qy, np.float64), n * self.dt, int(i), int(j), out)
+        if rc:
+            raise ValueError("bad node")
+        return out
+
+    def node_trial(self, h, qx, qy, i: int, j: int, trial: float):
+        """Node (i, j)'s update (before boundary overrides) with its new-time
+        depth in h-bar taken as `trial` (the map the implicit h-bar solves)."""
+        p = self.problem()
+        out = np.zeros(3)
+        rc = lib().mref_node_trial(C.byref(p), self.zb, np.ascontiguousarray(h, np.float64),
+                                   np.ascontiguousarray(qx, np.float64), np.ascontiguousarray(qy, np.float64),
+                                   int(i), int(j), float(trial), out)
         if rc:
             raise ValueError("bad node")
         return out

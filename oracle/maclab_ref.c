@@ -18,7 +18,11 @@
  *   - e = 6 nu / dx, dt = dx / e                     Eq. (mlb-viscosity)
  *   - bounce-back f_a^eq = f_abar^eq at walls         Section 3, text after the stability note
  * with these readings of the points the paper leaves open:
- *   - h-bar on a link is the old-time average of the two end nodes (Eq. h-bar)
+ *   - h-bar on a link is the old-time average of the two end nodes (Eq. h-bar),
+ *     or, with hbar_implicit, the definition given with Eq. (feq-full): the
+ *     receiving node's new-time depth and the upstream node's old one.  The
+ *     new depth then enters its own update linearly (through the bed term
+ *     only), so the implicit equation is solved exactly per node.
  *   - F at the link midpoint is the old-time average of the two end nodes
  *   - bounced links carry f_abar^eq of the node itself, no bed or force term
  *   - after the update: WALL nodes get q = 0; DEPTH nodes get h = h_bc(t+dt)
@@ -71,6 +75,8 @@ typedef struct {
     double  bc_h_mean[4], bc_amp[4], bc_period[4], bc_phase[4];
     double  bc_qx[4], bc_qy[4];
     const uint8_t* kind;  /* optional node kinds [ny][nx] (NODE_*), or NULL   */
+    int32_t hbar_implicit; /* 0: Eq. (h-bar); 1: new-time depth at the node   */
+    int32_t pad2_;
 } mref_problem;
 
 static int kind_at(const mref_problem* p, int i, int j)
@@ -154,9 +160,12 @@ static int upstream(const mref_problem* p, int i, int j, int a, int* yi, int* yj
 }
 
 /* Eqs. (Mac.lb.3), (Mac.lb.6), (Mac.lb.7): the new h, hu, hv at node (i, j)
- * before any boundary override. */
-static void pre_update(const mref_problem* p, const double* zb, const double* h,
-                       const double* qx, const double* qy, int i, int j, double out[3])
+ * before any boundary override, with the link depth
+ *   h-bar = (h(x) + h(y)) / 2           (Eq. h-bar; trial == NULL), or
+ *   h-bar = (*trial + h(y)) / 2         (*trial: a new-time depth at x). */
+static void update_with(const mref_problem* p, const double* zb, const double* h,
+                        const double* qx, const double* qy, int i, int j, const double* trial,
+                        double out[3])
 {
     const int nx = p->nx;
     const double g = p->g, e = p->e, e2 = e * e, dt = p->dt;
@@ -172,7 +181,8 @@ static void pre_update(const mref_problem* p, const double* zb, const double* h,
             size_t y = (size_t)yj * nx + yi;
             double hy = h[y], uy = qx[y] / hy, vy = qy[y] / hy, fyx, fyy;
             node_force(p, hy, qx[y], qy[y], &fyx, &fyy);
-            double hbar = 0.5 * (hx + hy);                   /* Eq. (h-bar), old time   */
+            double hxb = trial ? *trial : hx;
+            double hbar = 0.5 * (hxb + hy);                  /* Eq. (h-bar) / implicit  */
             double fbx = 0.5 * (fxx + fyx), fby = 0.5 * (fxy + fyy); /* Eq. (force-CS) */
             s = mref_feq(a, g, e, hy, uy, vy)
                 - g / e2 * CA[a] * hbar * (zb[x] - zb[y])
@@ -185,6 +195,34 @@ static void pre_update(const mref_problem* p, const double* zb, const double* h,
         qyn += e * EY[a] * s;
     }
     out[0] = hn; out[1] = qxn; out[2] = qyn;
+}
+
+/* The new state at (i, j) before any boundary override.  With the implicit
+ * h-bar the node's new depth h' appears in its own update only through the
+ * bed terms of its non-bounced links, each -(g/e^2) C_a (h'/2)(zb(x) - zb(y)):
+ * h' = G0 - kap h' with G0 the update at h' = 0 and
+ * kap = (g / (2 e^2)) sum_a C_a (zb(x) - zb(y)), so h' = G0 / (1 + kap); the
+ * discharge is then the update evaluated at that h'. */
+static void pre_update(const mref_problem* p, const double* zb, const double* h,
+                       const double* qx, const double* qy, int i, int j, double out[3])
+{
+    if (!p->hbar_implicit) {
+        update_with(p, zb, h, qx, qy, i, j, NULL, out);
+        return;
+    }
+    const double zero = 0.0;
+    double g0[3];
+    update_with(p, zb, h, qx, qy, i, j, &zero, g0);
+    const size_t x = (size_t)j * p->nx + i;
+    double kap = 0.0;
+    for (int a = 1; a <= 8; ++a) {
+        int yi, yj;
+        if (upstream(p, i, j, a, &yi, &yj))
+            kap += p->g / (2.0 * p->e * p->e) * CA[a] * (zb[x] - zb[(size_t)yj * p->nx + yi]);
+    }
+    const double hnew = g0[0] / (1.0 + kap);
+    update_with(p, zb, h, qx, qy, i, j, &hnew, out);
+    out[0] = hnew;
 }
 
 /* Which override applies at (i, j): returns the kind and the edge whose
@@ -290,6 +328,17 @@ int mref_node(const mref_problem* p, const double* zb, const double* h, const do
 {
     if (check_problem(p) || i < 0 || j < 0 || i >= p->nx || j >= p->ny) return -1;
     final_update(p, zb, h, qx, qy, t_old + p->dt, i, j, out);
+    return 0;
+}
+
+/* The map whose fixed point the implicit h-bar defines: node (i, j)'s update
+ * (before boundary overrides) when its new-time depth in h-bar is taken to be
+ * `trial`.  For checking the exact solve only. */
+int mref_node_trial(const mref_problem* p, const double* zb, const double* h, const double* qx,
+                    const double* qy, int i, int j, double trial, double out[3])
+{
+    if (check_problem(p) || i < 0 || j < 0 || i >= p->nx || j >= p->ny) return -1;
+    update_with(p, zb, h, qx, qy, i, j, &trial, out);
     return 0;
 }
 
