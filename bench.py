@@ -98,6 +98,9 @@ def main():
                          "dish: the paper's circular wind-driven basin (200^2, node mask) with its "
                          "time to steady state; dish4096: the same basin on 4096^2 nodes; "
                          "hump: the paper's 2D hump channel (200^2) with its time to steady state")
+    ap.add_argument("--implicit", action="store_true",
+                    help="bump: the implicit link depth (new-time depth at the node; one step per pass, "
+                         "12 more bytes per node)")
     ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
     ap.add_argument("--ws-train", type=int, default=512, help="warm_start: training basins")
     ap.add_argument("--ws-epochs", type=int, default=40, help="warm_start: training epochs")
@@ -127,6 +130,7 @@ def main():
     if args.workload in ("dish", "dish4096", "hump"):
         return bench_geometry(args, ctx, copy_gbps)
     spec = wl.bump_channel(args.n)
+    spec.hbar_implicit = args.implicit
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
                        blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
@@ -151,9 +155,12 @@ def main():
     tb = grid.exec_opts().tblock
     # Dominant kernel: one launch per step (tblock 1) or per two steps (tblock
     # 2; the one or two closing single steps of the call are < 0.3 % of it).
+    if args.implicit:
+        tb = 1   # one step per pass whatever was requested
     launch_s = tb * ev_ms / 1e3 / args.steps
-    gbs = BYTES_PER_LUP * nodes / launch_s / 1e9
-    traffic = measured_traffic(nodes, tb)
+    bpl = BYTES_PER_LUP + (12 if args.implicit else 0)   # + 1/(1+kappa), kappa_x, kappa_y
+    gbs = bpl * nodes / launch_s / 1e9
+    traffic = None if args.implicit else measured_traffic(nodes, tb)
     if tb == 1:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -177,10 +184,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nodes": nodes, "dx_m": spec.dx, "dt_s": spec.dx / (6 * spec.nu / spec.dx),
                    "tile_rows": grid.exec_opts().tile_rows, "blocks_per_cu": grid.exec_opts().blocks_per_cu,
-                   "tblock": grid.exec_opts().tblock,
+                   "tblock": grid.exec_opts().tblock, "hbar": "implicit" if args.implicit else "eq_h-bar",
                    "autotuned": tuned is not None, "graph": not args.no_graph,
                    # per-step bytes of the one-step formulation x update rate
-                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1),
+                   "effective_GBps": round(mlups * 1e6 * bpl / 1e9, 1),
                    "launch_GBps": round(gbs, 1),
                    "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": roofline,

@@ -150,6 +150,27 @@ enum { MLB_NODE_FLUID = 0, MLB_NODE_WALL = 1, MLB_NODE_SOLID = 2 };
  * MLB_E_STATE if the grid belongs to a live batch. */
 mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 
+/* Link depth h-bar of the bed term (Section 3).
+ *   SEMI_IMPLICIT  h-bar = (h(x,t) + h(x - e_a dt,t)) / 2, Eq. (h-bar): the
+ *                  form the paper prefers; exact volume conservation and the
+ *                  two-step kernel.  Default.
+ *   IMPLICIT       h-bar = (h(x,t+dt) + h(x - e_a dt,t)) / 2, the definition
+ *                  given with Eq. (feq-full): the receiving node's new depth.
+ *                  It enters the node's update only through its bed terms, so
+ *                  the equation is affine in it and is solved exactly per node
+ *                  (static per-node sums over the non-bounced links,
+ *                  recomputed by mlb_set_bathymetry and mlb_set_mask; 12 more
+ *                  bytes per node read per step).  The volume is then
+ *                  conserved only to O(dt) of the bed-term asymmetry.  Grids
+ *                  in this form run one step per pass with ordinary launches
+ *                  (tblock 2 and persistent are accepted and run as one-step
+ *                  graph / stream launches).
+ * MLB_E_UNSTABLE if 1 + kappa <= 0 at some node (a bed far too rough for the
+ * lattice); MLB_E_STATE if the grid belongs to a live batch.  The grids of a
+ * batch must share the form (mlb_batch_create: MLB_E_INVAL otherwise). */
+enum { MLB_HBAR_SEMI_IMPLICIT = 0, MLB_HBAR_IMPLICIT = 1 };
+mlb_status mlb_set_hbar(mlb_grid* g, int32_t mode);
+
 /* Uniform wind speed (u_wx, u_wy) [m/s]: tau_w / rho = rho_air c_w u_w |u_w| / rho_w
  * (Eq. wind_u-stress). */
 mlb_status mlb_set_wind(mlb_grid* g, double uwx, double uwy);

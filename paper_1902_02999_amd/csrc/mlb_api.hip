@@ -44,6 +44,10 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     for (int k = 0; k < 2; ++k) { b.eta[k] = g->eta[k]; b.qx[k] = g->qx[k]; b.qy[k] = g->qy[k]; }
     b.H = g->H;
     b.mask = g->dmask;
+    const bool imp = g->hbar == MLB_HBAR_IMPLICIT && g->dcoef;
+    b.cw = imp ? g->dcoef : nullptr;
+    b.ckx = imp ? g->dcoef + g->plane : nullptr;
+    b.cky = imp ? g->dcoef + 2 * g->plane : nullptr;
     b.stepc = g->stepc;
     b.nx = g->p.nx; b.ny = g->p.ny; b.ld = g->ld;
     b.swap = swap;
@@ -186,13 +190,15 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.ht.clear();
         g->plan.ht2.clear();
         make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
-        // masked grids run one step per pass
-        if (g->opts.tblock == 2 && !g->dmask) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
+        // masked grids and the implicit link depth run one step per pass
+        const bool one = g->dmask || g->hbar == MLB_HBAR_IMPLICIT;
+        if (g->opts.tblock == 2 && !one) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
         g->plan.hb[0].first_tile2 = 0;
         g->plan.hb[0].ntiles2 = (int)g->plan.ht2.size();
         g->plan.masked = g->dmask != nullptr;
+        g->plan.implicit = g->hbar == MLB_HBAR_IMPLICIT;
         CHK(plan_alloc(c, g->plan));
         g->stale_plan = false;
         g->dirty = false;
@@ -233,7 +239,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     int64_t nl = 0;
     auto eager = [&](int k, bool diag) -> mlb_status {
         HIPCHK(launch_step(P.db, k == 2 ? P.dt2 : P.dt, k == 2 ? nt2 : nt1, P.parity, P.dpart, diag ? 1 : 0, k,
-                           P.masked ? 1 : 0, dyn, c->stream));
+                           P.masked ? 1 : 0, P.implicit ? 1 : 0, dyn, c->stream));
         P.parity ^= 1;
         ++nl;
         return MLB_OK;
@@ -248,7 +254,8 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
         singles = n - multi;
     }
     // persistent: all `multi` passes in cooperative launches with grid barriers
-    if (o.persistent && multi > 0 && !P.coop_failed) {
+    // (not for the implicit link depth: those basins use ordinary launches)
+    if (o.persistent && multi > 0 && !P.coop_failed && !P.implicit) {
         const int nt = kind == 2 ? nt2 : nt1;
         const int nblk = (nt + kBlock / kWave - 1) / (kBlock / kWave);
         if (persistent_capacity(kind, P.masked ? 1 : 0, c->ncu) < nblk) {
@@ -281,7 +288,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             hipError_t le = hipSuccess;
             for (int i = 0; i < glaunch && le == hipSuccess; ++i) {
                 le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind,
-                                 P.masked ? 1 : 0, dyn, c->stream);
+                                 P.masked ? 1 : 0, P.implicit ? 1 : 0, dyn, c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -377,6 +384,52 @@ double water_depth_sum(const mlb_grid* g)
             if (g->hmask.empty() || g->hmask[o] != NODE_SOLID) sum += g->Hd[o];
         }
     return sum;
+}
+
+// Static sums of the implicit link depth per node x, over its links a whose
+// upstream node y = x - e_a is in the water (not past a non-periodic edge, not
+// SOLID):  kappa = g/(2e^2) sum_a C_a (z_x - z_y),
+//          kappa_v = g/(2e) sum_a C_a e^_a (z_x - z_y),  z_x - z_y = H_y - H_x,
+// in FP64 from the depths as given; stored 1/(1+kappa), kappa_x, kappa_y (FP32).
+mlb_status implicit_coeffs(mlb_grid* g)
+{
+    if (g->hbar != MLB_HBAR_IMPLICIT) return MLB_OK;
+    // D2Q9 (Section 3): axis directions C = 1/3, diagonals C = 1/12, numbered
+    // counter-clockwise from east
+    static const int ex[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+    static const int ey[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+    static const double ca[9] = {0, 1.0 / 3, 1.0 / 12, 1.0 / 3, 1.0 / 12, 1.0 / 3, 1.0 / 12, 1.0 / 3, 1.0 / 12};
+    const int nx = g->p.nx, ny = g->p.ny, ld = g->ld;
+    const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
+    const double e = g->e, cm = g->p.g / (2.0 * e * e), cv = g->p.g / (2.0 * e);
+    std::vector<float> w(3 * g->plane, 0.0f);
+    float* kx = w.data() + g->plane;
+    float* ky = w.data() + 2 * g->plane;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t o = (size_t)j * ld + i;
+            double kap = 0, kvx = 0, kvy = 0;
+            for (int a = 1; a <= 8; ++a) {
+                int yi = i - ex[a], yj = j - ey[a];
+                if (yi < 0 || yi >= nx) { if (!px) continue; yi = (yi + nx) % nx; }
+                if (yj < 0 || yj >= ny) { if (!py) continue; yj = (yj + ny) % ny; }
+                const size_t y = (size_t)yj * ld + yi;
+                if (!g->hmask.empty() && g->hmask[y] == NODE_SOLID) continue;
+                const double dz = g->Hd[y] - g->Hd[o];
+                kap += cm * ca[a] * dz;
+                kvx += cv * ca[a] * ex[a] * dz;
+                kvy += cv * ca[a] * ey[a] * dz;
+            }
+            if (!(1.0 + kap > 0)) return fail(MLB_E_UNSTABLE, "implicit link depth: 1 + kappa <= 0 at a node");
+            w[o] = (float)(1.0 / (1.0 + kap));
+            kx[o] = (float)kvx;
+            ky[o] = (float)kvy;
+        }
+    if (!g->dcoef) HIPCHK(hipMalloc((void**)&g->dcoef, w.size() * sizeof(float)));
+    HIPCHK(hipMemcpyAsync(g->dcoef, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    g->dirty = true;
+    return MLB_OK;
 }
 
 mlb_status set_step(mlb_grid* g, int64_t s)
@@ -574,6 +627,7 @@ mlb_status mlb_grid_destroy(mlb_grid* g)
     g->plan.release();
     if (g->own) (void)hipFree(g->base);
     if (g->dmask) (void)hipFree(g->dmask);
+    if (g->dcoef) (void)hipFree(g->dcoef);
     g->ctx->live--;
     delete g;
     return MLB_OK;
@@ -601,6 +655,7 @@ mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld)
         return fail(MLB_E_UNSTABLE, "g * H_max > e^2: choose a larger nu (e = 6 nu / dx)");
     g->sumH = water_depth_sum(g);
     g->Hmax = hmax;
+    CHK(implicit_coeffs(g));
     HIPCHK(hipMemcpyAsync(g->H, g->Hf.data(), g->Hf.size() * sizeof(float), hipMemcpyHostToDevice,
                           g->ctx->stream));
     CHK(upload_host_state(g, nullptr, nullptr, nullptr, nx));
@@ -692,7 +747,21 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
         g->hmask.swap(m);
     }
     g->sumH = water_depth_sum(g);
+    CHK(implicit_coeffs(g));
     g->stale_plan = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_hbar(mlb_grid* g, int32_t mode)
+{
+    GRID_OK(g);
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    if (mode != MLB_HBAR_SEMI_IMPLICIT && mode != MLB_HBAR_IMPLICIT) return fail(MLB_E_INVAL, "unknown link-depth form");
+    const int old = g->hbar;
+    g->hbar = mode;
+    mlb_status st = implicit_coeffs(g);
+    if (st != MLB_OK) { g->hbar = old; return st; }
+    if (mode != old) g->stale_plan = true;
     return MLB_OK;
 }
 
@@ -900,6 +969,7 @@ static mlb_status batch_plan(mlb_batch* b)
     b->plan.parity = 0;
     bool masked = false;
     for (auto* g : b->grids) masked |= g->dmask != nullptr;
+    const bool implicit = b->grids[0]->hbar == MLB_HBAR_IMPLICIT;   // shared by every grid
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
         mlb_grid* g = b->grids[i];
@@ -908,11 +978,12 @@ static mlb_status batch_plan(mlb_batch* b)
         make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
         d.first_tile2 = (int)b->plan.ht2.size();
-        if (b->opts.tblock == 2 && !masked) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
+        if (b->opts.tblock == 2 && !masked && !implicit) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
     }
     b->plan.masked = masked;
+    b->plan.implicit = implicit;
     CHK(plan_alloc(b->ctx, b->plan));
     b->stale_plan = false;
     return MLB_OK;
@@ -926,6 +997,8 @@ mlb_status mlb_batch_create(mlb_ctx* c, mlb_grid* const* grids, int32_t n, mlb_b
     for (int i = 0; i < n; ++i) {
         if (!grids[i] || grids[i]->ctx != c) return fail(MLB_E_INVAL, "grid missing or from another context");
         if (grids[i]->batch) return fail(MLB_E_STATE, "grid already in a batch");
+        if (grids[i]->hbar != grids[0]->hbar)
+            return fail(MLB_E_INVAL, "the grids of a batch must share the link-depth form");
         for (int k = 0; k < i; ++k)
             if (grids[k] == grids[i]) return fail(MLB_E_INVAL, "grid listed twice");
     }
@@ -1117,8 +1190,8 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
-    bool masked = false;   // masked grids run one step per pass
-    for (auto* g : gs) masked |= g->dmask != nullptr;
+    bool masked = false;   // masked grids and the implicit link depth run one step per pass
+    for (auto* g : gs) masked |= g->dmask != nullptr || g->hbar == MLB_HBAR_IMPLICIT;
     for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))
@@ -1171,7 +1244,7 @@ mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_
     if (steps < 2) return fail(MLB_E_INVAL, "steps must be >= 2");
     mlb_ctx* c = g->ctx;
     const std::string key = c->arch + "_g" + std::to_string(g->p.nx) + "x" + std::to_string(g->p.ny) +
-                            (g->dmask ? "m" : "");
+                            (g->dmask ? "m" : "") + (g->hbar == MLB_HBAR_IMPLICIT ? "i" : "");
     mlb_exec_opts o = g->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_set_exec_opts(g, &o));
@@ -1212,7 +1285,7 @@ mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_pat
     bool masked = false;
     for (auto* g : b->grids) { nodes += (int64_t)g->p.nx * g->p.ny; masked |= g->dmask != nullptr; }
     const std::string key = c->arch + "_b" + std::to_string(b->grids.size()) + "n" + std::to_string(nodes) +
-                            (masked ? "m" : "");
+                            (masked ? "m" : "") + (b->grids[0]->hbar == MLB_HBAR_IMPLICIT ? "i" : "");
     mlb_exec_opts o = b->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_batch_set_exec_opts(b, &o));

@@ -28,6 +28,11 @@ struct BasinDev {
     float* qy[2];
     const float* H;
     const uint8_t* mask;   // node kinds (pitch ld bytes) or nullptr
+    // implicit link depth: per-node 1/(1+kappa), kappa_x, kappa_y planes
+    // (pitch ld floats), nullptr for the old-time link depth
+    const float* cw;
+    const float* ckx;
+    const float* cky;
     int64_t* stepc;        // [2]: step counter, read from [rd], written to [1-rd]
     int32_t nx, ny, ld;
     int32_t swap;          // buffer read by a launch of parity p is p ^ swap
@@ -70,9 +75,11 @@ struct TileDev {
 // Host-side launchers (mlb_kernels.hip).
 // tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
 // of kStripOut2 columns, no diag.  masked: the tile list may hold
-// TILE_MASKED tiles (one-step only).
+// TILE_MASKED tiles; implicit: every basin has the implicit link-depth
+// planes (both one-step only).
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, int masked, unsigned dyn_lds, hipStream_t s);
+                       double* d_partials, int diag, int tblock, int masked, int implicit, unsigned dyn_lds,
+                       hipStream_t s);
 // npasses passes of `kind` steps in one cooperative launch (all tiles
 // resident); base = sync->count at launch.  Fails (no launch) when the grid
 // cannot be co-resident.

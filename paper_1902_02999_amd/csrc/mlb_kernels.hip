@@ -78,6 +78,7 @@ struct Node {
     float eta, h, kk, fpx, fpy;
     float o[9];            // o[a] = Out_a(node), a = 1..8
     float H, q0x, q0y;     // the node's stored H and old discharge
+    float iw, ikx, iky;    // implicit link depth: 1/(1+kappa), kappa_x, kappa_y
 };
 
 // Node quantities from the old state (Eqs. SWE-force, bed-stress, feq-full).
@@ -208,6 +209,25 @@ __device__ __forceinline__ void carry_from(float lN, float lNE, float lNW, Carry
 //   x: g/(6e) Hx + g/(24e) (Bx + Ux),  y: g/(6e) (P3 - P7) + g/(24e) (Bd - Ud);
 // update_edge forms exactly these from the eight values, update_fast from
 // the shared partial sums (equal bits: only exact negations differ).
+//
+// IMPL (implicit link depth, h-bar with the node's new depth): the new depth
+// enters only through the bed terms, -(g/(2e^2)) C_a (h' - h) (z_x - z_y) more
+// per link than with the old depth, so with the static per-node sums
+// kappa = g/(2e^2) sum_a C_a (z_x - z_y) and kappa_v = g/(2e) sum_a C_a e^_a (z_x - z_y)
+// over the non-bounced links the increment of the old-depth update is scaled
+// by 1/(1+kappa) and the discharge loses increment * kappa_v.
+template <bool IMPL>
+__device__ __forceinline__ void finish(const Node& x, float inc, float& en, float& qxn, float& qyn)
+{
+    if (IMPL) {
+        inc = inc * x.iw;
+        qxn = __builtin_fmaf(-inc, x.ikx, qxn);
+        qyn = __builtin_fmaf(-inc, x.iky, qyn);
+    }
+    en = x.eta + inc;
+}
+
+template <bool IMPL>
 __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, const Row& S, const Row& C,
                                             const Row& N, const Carry& cy, float lE, float lN, float lNE,
                                             float lNW, float& en, float& qxn, float& qyn)
@@ -222,12 +242,13 @@ __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, co
     const float so = (C.E1 + S.S1) + N.N1;
     const float mxo = (C.E2 + S.S2) + N.N2;
     const float myo = S.S1 - N.N1;
-    en = x.eta + ((so - x.kk) + mp);
     qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
     qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
+    finish<IMPL>(x, (so - x.kk) + mp, en, qxn, qyn);
 }
 
 // The same from the link products P[a] and gathered equilibria oy[a] = Out_a(y_a).
+template <bool IMPL>
 __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, const float* P, const float* oy,
                                             float& en, float& qxn, float& qyn)
 {
@@ -245,12 +266,12 @@ __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, co
     const float so = (E1 + S1) + N1;
     const float mxo = (E2 + S2) + N2;
     const float myo = S1 - N1;
-    en = x.eta + ((so - x.kk) + mp);
     qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
     qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
+    finish<IMPL>(x, (so - x.kk) + mp, en, qxn, qyn);
 }
 
-struct Raw { float eta, qx, qy, H; int m; };   // m: node kind (masked tiles)
+struct Raw { float eta, qx, qy, H; int m; float iw, ikx, iky; };   // m: node kind (masked tiles)
 
 // Index of a column / row to load: wrapped on periodic axes (lanes of a strip
 // can reach past the grid on narrow grids), clamped otherwise (values there
@@ -291,16 +312,27 @@ __device__ __forceinline__ void stf(gfloat* base, uint32_t byte_off, float v)
 
 typedef __attribute__((address_space(1))) const uint8_t gcu8;
 
-template <bool MASK>
+// Static per-node planes of the implicit link depth.
+struct Coef { const gfloat* w; const gfloat* kx; const gfloat* ky; };
+
+template <bool MASK, bool IMPL>
 __device__ __forceinline__ Raw load_raw(const gfloat* __restrict__ E0, const gfloat* __restrict__ QX0,
                                         const gfloat* __restrict__ QY0, const gfloat* __restrict__ HH,
-                                        gcu8* __restrict__ MK, uint32_t o)
+                                        gcu8* __restrict__ MK, const Coef& K, uint32_t o)
 {
     const uint32_t b = o * 4u;
     Raw w;
     w.eta = ldf(E0, b); w.qx = ldf(QX0, b); w.qy = ldf(QY0, b); w.H = ldf(HH, b);
     w.m = MASK ? (int)MK[o] : 0;
+    if (IMPL) { w.iw = ldf(K.w, b); w.ikx = ldf(K.kx, b); w.iky = ldf(K.ky, b); }
+    else { w.iw = 1.0f; w.ikx = 0.0f; w.iky = 0.0f; }
     return w;
+}
+
+template <bool IMPL>
+__device__ __forceinline__ void take_coef(const Raw& w, Node& d)
+{
+    if (IMPL) { d.iw = w.iw; d.ikx = w.ikx; d.iky = w.iky; }
 }
 
 struct Sums { double eta, dq, q, bad, vmax; };
@@ -403,6 +435,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 #define MLB_ROW(V, r, RAWN, S, C, N, DC, DN, LOADNEXT, EMIT, EMIT0)                                 \
     do {                                                                                          \
         derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
+        take_coef<IMPL>(RAWN, DN);                                                                \
         exchange<EDGE>(DN, N);                                                                    \
         if (MASK) mask_row(RAWN.m, N);                                                            \
         LOADNEXT;                                                                                 \
@@ -433,9 +466,9 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             P[6] = bb6_ ? 0.0f : P[6];     oy[6] = bb6_ ? DC.o[2] : oy[6];                        \
             P[7] = bb7_ ? 0.0f : P[7];     oy[7] = bb7_ ? DC.o[3] : oy[7];                        \
             P[8] = bb8_ ? 0.0f : P[8];     oy[8] = bb8_ ? DC.o[4] : oy[8];                        \
-            update_edge(B, DC, P, oy, en, qxn, qyn);                                              \
+            update_edge<IMPL>(B, DC, P, oy, en, qxn, qyn);                                        \
         } else {                                                                                  \
-            update_fast(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, qxn, qyn);                    \
+            update_fast<IMPL>(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, qxn, qyn);              \
         }                                                                                         \
         carry_from<EDGE>(lN, lNE, lNW, V.cy); /* for row r+1 */                                   \
         /* keep the row's arithmetic ahead of the ownership branch of EMIT */                     \
@@ -509,7 +542,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 
 // ------------------------------------------------------------------ one step per pass
 // MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only).
-template <bool EDGE, bool DIAG, bool FRIC, bool MASK>
+// IMPL: the basin uses the implicit link depth (coefficient planes).
+template <bool EDGE, bool DIAG, bool FRIC, bool MASK, bool IMPL>
 __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd, int64_t step,
                                          double* __restrict__ part)
 {
@@ -528,12 +562,13 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     gfloat* __restrict__ QX1 = (gfloat*)B.qx[wr];
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
     gcu8* __restrict__ MK = (gcu8*)B.mask;
+    const Coef K = {(const gfloat*)B.cw, (const gfloat*)B.ckx, (const gfloat*)B.cky};
     Stage V;
     stage_setup<EDGE>(B, L, (double)(step + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
-#define MLB_LD(row) load_raw<MASK>(E0, QX0, QY0, HH, MK, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<MASK, IMPL>(E0, QX0, QY0, HH, MK, K, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
     // Software pipeline: a row's raw values are loaded three rows before they
     // are derived.  Raw slots, window rows and derived nodes rotate with
     // period 3, so the loop is unrolled by 3 and the rotation is a renaming
@@ -544,12 +579,14 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     {
         const Raw w = MLB_LD(r0 - 1);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d0);
+        take_coef<IMPL>(w, d0);
         exchange<EDGE>(d0, R0);
         if (MASK) mask_row(w.m, R0);
     }
     {
         const Raw w = MLB_LD(r0);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d1);
+        take_coef<IMPL>(w, d1);
         exchange<EDGE>(d1, R1);
         if (MASK) mask_row(w.m, R1);
     }
@@ -615,6 +652,8 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
     constexpr bool MASK = false;   // masked grids run one step per pass
+    constexpr bool IMPL = false;   // so do grids with the implicit link depth
+    const Coef K = {nullptr, nullptr, nullptr};
     const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
     const int wr = rd ^ 1;
@@ -632,7 +671,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
-#define MLB_LD(row) load_raw<false>(E0, QX0, QY0, HH, nullptr, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<false, false>(E0, QX0, QY0, HH, nullptr, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
     // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
     Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
     Node a0, a1, a2;
@@ -730,7 +769,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 // basin's step counter at buffer rd; the basin's first tile advances it.
 // MASKED: the tile list may hold TILE_MASKED tiles (a separate kernel, so
 // that grids without a mask keep the smaller register budget).
-template <int KIND, bool DIAG, bool MASKED, class StepRead>
+template <int KIND, bool DIAG, bool MASKED, bool IMPL, class StepRead>
 __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles,
                                           int t, int parity, double* __restrict__ partials, StepRead step_at)
 {
@@ -750,13 +789,13 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         double* part = partials + (size_t)t * kPartials;
         const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         if (B.cfr != 0.0f) {
-            if (masked) run_tile<true, DIAG, true, MASKED>(B, T, rd, step, part);
-            else if (edge) run_tile<true, DIAG, true, false>(B, T, rd, step, part);
-            else run_tile<false, DIAG, true, false>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, true, MASKED, IMPL>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, true, false, IMPL>(B, T, rd, step, part);
+            else run_tile<false, DIAG, true, false, IMPL>(B, T, rd, step, part);
         } else {
-            if (masked) run_tile<true, DIAG, false, MASKED>(B, T, rd, step, part);
-            else if (edge) run_tile<true, DIAG, false, false>(B, T, rd, step, part);
-            else run_tile<false, DIAG, false, false>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, false, MASKED, IMPL>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, false, false, IMPL>(B, T, rd, step, part);
+            else run_tile<false, DIAG, false, false, IMPL>(B, T, rd, step, part);
         }
     } else {
         // a two-step tile needs the boundary logic when stage A's rows
@@ -789,14 +828,15 @@ struct CoherentStep {
 // One pass of one step.  One wave per tile, tiles in list order (largest
 // basins first): the hardware dispatcher hands out workgroups in index
 // order, so the list is consumed as a queue without a software loop.
-template <bool DIAG, bool MASKED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+// (the checked step of the implicit link depth needs more than 128 VGPRs)
+template <bool DIAG, bool MASKED, bool IMPL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((DIAG && IMPL) ? 3 : 4)))
 void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                  int parity, double* __restrict__ partials)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<1, DIAG, MASKED>(basins, tiles, t, parity, partials, PlainStep{});
+    pass_tile<1, DIAG, MASKED, IMPL>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
 // One pass of two steps, over tiles of 60-column strips.
@@ -806,7 +846,7 @@ void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -828,7 +868,7 @@ void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __res
     __syncthreads();
     if (abort_flag) return;
     for (int p = 0; p < npasses; ++p) {
-        if (t < ntiles) pass_tile<KIND, false, MASKED>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
+        if (t < ntiles) pass_tile<KIND, false, MASKED, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
         __threadfence();   // release: this wave's stores, device-wide
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -950,33 +990,39 @@ int step_occupancy(int diag)
 {
     int n = 0;
     if (diag)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true, false>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true, false, false>, kBlock, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false, false>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false, false, false>, kBlock, 0);
     return n > 0 ? n : 1;
 }
 
+template <bool DIAG, bool MASKED, bool IMPL>
+static void launch_one(dim3 grid, unsigned dyn_lds, hipStream_t s, const BasinDev* d_basins, const TileDev* d_tiles,
+                       int ntiles, int parity, double* d_partials)
+{
+    hipLaunchKernelGGL((step_kernel<DIAG, MASKED, IMPL>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+                       ntiles, parity, d_partials);
+}
+
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, int masked, unsigned dyn_lds, hipStream_t s)
+                       double* d_partials, int diag, int tblock, int masked, int implicit, unsigned dyn_lds,
+                       hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1 && (tblock != 2 || diag || masked)) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag || masked || implicit)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
-    if (tblock == 2)
+    if (tblock == 2) {
         hipLaunchKernelGGL(step2_kernel, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
-    else if (diag && masked)
-        hipLaunchKernelGGL((step_kernel<true, true>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
-                           ntiles, parity, d_partials);
-    else if (diag)
-        hipLaunchKernelGGL((step_kernel<true, false>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
-                           ntiles, parity, d_partials);
-    else if (masked)
-        hipLaunchKernelGGL((step_kernel<false, true>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
-                           ntiles, parity, d_partials);
-    else
-        hipLaunchKernelGGL((step_kernel<false, false>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
-                           ntiles, parity, d_partials);
+        return hipGetLastError();
+    }
+    using L = void (*)(dim3, unsigned, hipStream_t, const BasinDev*, const TileDev*, int, int, double*);
+    static const L table[8] = {launch_one<false, false, false>, launch_one<false, false, true>,
+                               launch_one<false, true, false>,  launch_one<false, true, true>,
+                               launch_one<true, false, false>,  launch_one<true, false, true>,
+                               launch_one<true, true, false>,   launch_one<true, true, true>};
+    table[(diag ? 4 : 0) + (masked ? 2 : 0) + (implicit ? 1 : 0)](grid, dyn_lds, s, d_basins, d_tiles, ntiles,
+                                                                  parity, d_partials);
     return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct Plan {
     bool coop_failed = false;    // a persistent launch was refused: use ordinary ones
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool masked = false;       // some basin has a node mask: one-step passes, masked kernel
+    bool implicit = false;     // the basins use the implicit link depth: one-step passes
     bool built = false;
 
     void release()
@@ -113,6 +114,8 @@ struct mlb_grid {
                                // host conversions h <-> eta and the mass use it
     uint8_t* dmask = nullptr;  // node kinds on the device (pitch ld bytes), or none
     std::vector<uint8_t> hmask;  // host copy (pitch ld), empty without a mask
+    int hbar = MLB_HBAR_SEMI_IMPLICIT;
+    float* dcoef = nullptr;    // implicit link depth: 3 planes (1/(1+kappa), kappa_x, kappa_y)
     int cur = 0;
     int64_t step = 0;
     double e = 0, dt = 0, sumH = 0, Hmax = 0;

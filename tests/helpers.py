@@ -19,7 +19,7 @@ def oracle_from_spec(spec: wl.Spec, h=None, qx=None, qy=None, step0=0) -> "oracl
                      cb=oracle.bed_coeff(spec.chezy) if spec.chezy > 0 else 0.0,
                      omega=spec.omega, edges=spec.edges, extrap_order=spec.extrap_order,
                      depth_bc=dict(spec.depth_bc), discharge_bc=dict(spec.discharge_bc),
-                     h=h, qx=qx, qy=qy, kind=spec.kind)
+                     h=h, qx=qx, qy=qy, kind=spec.kind, hbar_implicit=spec.hbar_implicit)
     b.step_index = step0
     return b
 
