@@ -74,6 +74,10 @@ def lib():
             L.mref_diag.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp,
                                     C.c_void_p, C.c_void_p, C.c_void_p, dp]
             L.mref_lattice.argtypes = [C.c_void_p] * 5
+            L.mref_elab_init.argtypes = [C.POINTER(Problem), dp, dp, dp, dp]
+            L.mref_elab_macro.argtypes = [C.POINTER(Problem), dp, dp, dp, dp]
+            L.mref_elab_step.argtypes = [C.POINTER(Problem), C.c_double, dp, dp, dp, C.c_int]
+            L.mref_elab_run.argtypes = [C.POINTER(Problem), C.c_double, dp, dp, C.c_int64, dp, C.c_int]
             L.mref_max_threads.restype = C.c_int
             _lib = L
     return _lib
@@ -248,3 +252,41 @@ class Basin:
             if d["residual"] <= tol:
                 return d
         return None
+
+
+class ElabBasin:
+    """The eLABSWE baseline (Eq. lb.1; nine stored distributions, relaxation
+    time tau) on the problem of a ``Basin``: same bed, forcing, edges (walls
+    and periodic only) and node kinds.  Starts from f = f^eq of the basin's
+    state."""
+
+    def __init__(self, basin: Basin, tau: float):
+        self.b = basin
+        self.tau = float(tau)
+        n = basin.nx * basin.ny
+        self.f = np.zeros(9 * n)
+        self._work = np.zeros(9 * n)
+        p = basin.problem()
+        if lib().mref_elab_init(C.byref(p), basin.h, basin.qx, basin.qy, self.f):
+            raise ValueError("oracle rejected the problem")
+        self.step_index = basin.step_index
+
+    def run(self, nsteps: int) -> None:
+        p = self.b.problem()
+        rc = lib().mref_elab_run(C.byref(p), self.tau, self.b.zb, self.f, int(nsteps), self._work,
+                                 self.b.threads or default_threads())
+        if rc:
+            raise ValueError("oracle rejected the eLABSWE problem (rc=%d)" % rc)
+        self.step_index += int(nsteps)
+
+    def macro(self):
+        """(h, hu, hv) [ny][nx] of the stored distributions."""
+        b = self.b
+        h = np.zeros((b.ny, b.nx)); qx = np.zeros_like(h); qy = np.zeros_like(h)
+        p = b.problem()
+        lib().mref_elab_macro(C.byref(p), self.f, h, qx, qy)
+        return h, qx, qy
+
+    def dist(self):
+        """The distributions as [9][ny][nx]."""
+        return self.f.reshape(9, self.b.ny, self.b.nx)

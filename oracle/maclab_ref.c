@@ -396,3 +396,135 @@ int mref_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------- eLABSWE (tau != 1)
+ * The lattice Boltzmann equation the method starts from (Eq. lb.1, in the
+ * pull form of Eq. lb.Mac.1): nine stored distributions per node, relaxed
+ * with the single time tau and streamed,
+ *   f_a(x, t+dt) = f*_a(y) - (g/e^2) C_a h-bar (zb(x) - zb(y)) + (dt/e^2) C_a e_a . F-bar,
+ *   f*_a(n) = f_a(n) - (f_a(n) - f_a^eq(n)) / tau,   y = x - e_a dt,
+ * with the same readings as the streaming-only step: h-bar and F-bar are
+ * old-time link averages (Eq. h-bar); a link whose upstream node lies past a
+ * wall edge or is SOLID takes the node's own f*_abar and no bed or force term;
+ * SOLID nodes keep their distributions; WALL nodes (edges of kind WALL or the
+ * mask's WALL nodes) end the step at equilibrium with zero velocity,
+ * f_a := f_a^eq(h', 0), h' = sum_a f_a (their discharge is zero, as in the
+ * streaming-only step).  Open (DEPTH / DISCHARGE) edges are not part of this
+ * baseline.  With tau = 1, f*_a = f_a^eq and the step is the streaming-only
+ * one (Eq. Mac.lb.3); the viscosity is nu = e^2 dt (2 tau - 1) / 6 (Eq. viscosity).
+ * Distributions are stored [9][ny][nx]. */
+
+static void elab_macro(const mref_problem* p, const double* f, size_t x, size_t n, double* h, double* qx,
+                       double* qy)
+{
+    double hh = 0.0, a = 0.0, b = 0.0;
+    for (int k = 0; k < 9; ++k) {
+        double v = f[(size_t)k * n + x];
+        hh += v;
+        a += p->e * EX[k] * v;
+        b += p->e * EY[k] * v;
+    }
+    *h = hh; *qx = a; *qy = b;
+}
+
+/* Post-collision value f*_a at node x. */
+static double elab_post(const mref_problem* p, double tau, const double* f, size_t x, size_t n, int a)
+{
+    double h, qx, qy;
+    elab_macro(p, f, x, n, &h, &qx, &qy);
+    double fa = f[(size_t)a * n + x];
+    return fa - (fa - mref_feq(a, p->g, p->e, h, qx / h, qy / h)) / tau;
+}
+
+static int elab_check(const mref_problem* p, double tau)
+{
+    if (check_problem(p) || !(tau > 0.5)) return -1;
+    for (int k = 0; k < 4; ++k)
+        if (p->edge[k] == REF_DEPTH || p->edge[k] == REF_DISCHARGE) return -1;
+    return 0;
+}
+
+/* f := f^eq(h, q) at every node (the usual start from a macroscopic state). */
+int mref_elab_init(const mref_problem* p, const double* h, const double* qx, const double* qy, double* f)
+{
+    if (check_problem(p)) return -1;
+    size_t n = (size_t)p->nx * p->ny;
+    for (size_t x = 0; x < n; ++x)
+        for (int a = 0; a < 9; ++a) f[(size_t)a * n + x] = mref_feq(a, p->g, p->e, h[x], qx[x] / h[x], qy[x] / h[x]);
+    return 0;
+}
+
+/* h, hu, hv of stored distributions (Eqs. fea-0-h, fea-0-v). */
+int mref_elab_macro(const mref_problem* p, const double* f, double* h, double* qx, double* qy)
+{
+    if (check_problem(p)) return -1;
+    size_t n = (size_t)p->nx * p->ny;
+    for (size_t x = 0; x < n; ++x) elab_macro(p, f, x, n, &h[x], &qx[x], &qy[x]);
+    return 0;
+}
+
+/* One eLABSWE step f -> f1 (no aliasing). */
+int mref_elab_step(const mref_problem* p, double tau, const double* zb, const double* f, double* f1,
+                   int nthreads)
+{
+    if (elab_check(p, tau)) return -1;
+    const int nx = p->nx, ny = p->ny;
+    const size_t n = (size_t)nx * ny;
+    const double g = p->g, e = p->e, e2 = e * e, dt = p->dt;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t x = (size_t)j * nx + i;
+            const int nk = kind_at(p, i, j);
+            if (nk == NODE_SOLID) {
+                for (int a = 0; a < 9; ++a) f1[(size_t)a * n + x] = f[(size_t)a * n + x];
+                continue;
+            }
+            double hx, qxx, qyx, fxx, fxy;
+            elab_macro(p, f, x, n, &hx, &qxx, &qyx);
+            node_force(p, hx, qxx, qyx, &fxx, &fxy);
+            double out[9];
+            out[0] = elab_post(p, tau, f, x, n, 0);
+            for (int a = 1; a <= 8; ++a) {
+                int yi, yj;
+                if (upstream(p, i, j, a, &yi, &yj)) {
+                    const size_t y = (size_t)yj * nx + yi;
+                    double hy, qxy, qyy, fyx, fyy;
+                    elab_macro(p, f, y, n, &hy, &qxy, &qyy);
+                    node_force(p, hy, qxy, qyy, &fyx, &fyy);
+                    double hbar = 0.5 * (hx + hy);                          /* Eq. (h-bar)    */
+                    double fbx = 0.5 * (fxx + fyx), fby = 0.5 * (fxy + fyy); /* Eq. (force-CS) */
+                    out[a] = elab_post(p, tau, f, y, n, a)
+                             - g / e2 * CA[a] * hbar * (zb[x] - zb[y])
+                             + dt / e2 * CA[a] * (e * EX[a] * fbx + e * EY[a] * fby);
+                } else {
+                    out[a] = elab_post(p, tau, f, x, n, OPP[a]);            /* bounce-back    */
+                }
+            }
+            int ed = 0;
+            if (nk == NODE_WALL || node_kind(p, i, j, &ed) == REF_WALL) {
+                double hn = 0.0;
+                for (int a = 0; a < 9; ++a) hn += out[a];
+                for (int a = 0; a < 9; ++a) out[a] = mref_feq(a, g, e, hn, 0.0, 0.0);
+            }
+            for (int a = 0; a < 9; ++a) f1[(size_t)a * n + x] = out[a];
+        }
+    (void)nthreads;
+    return 0;
+}
+
+/* nsteps eLABSWE steps in place; work holds 9 nx ny doubles. */
+int mref_elab_run(const mref_problem* p, double tau, const double* zb, double* f, int64_t nsteps, double* work,
+                  int nthreads)
+{
+    size_t n9 = (size_t)9 * p->nx * p->ny;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int rc = mref_elab_step(p, tau, zb, f, work, nthreads);
+        if (rc) return rc;
+        memcpy(f, work, n9 * sizeof(double));
+    }
+    return 0;
+}
