@@ -91,13 +91,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default it picks tile rows and the CU cap before timing)")
     ap.add_argument("--workload", default="bump",
-                    choices=["bump", "ensemble", "lake_steady", "warm_start", "dish", "dish4096", "hump"],
+                    choices=["bump", "ensemble", "lake_steady", "warm_start", "dish", "dish4096", "hump", "elab"],
                     help="bump: 4096^2 channel (default line); ensemble: 512 basins 64^2..512^2 in "
                          "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6; "
                          "warm_start: learned warm start vs cold start on held-out 256^2 basins; "
                          "dish: the paper's circular wind-driven basin (200^2, node mask) with its "
                          "time to steady state; dish4096: the same basin on 4096^2 nodes; "
-                         "hump: the paper's 2D hump channel (200^2) with its time to steady state")
+                         "hump: the paper's 2D hump channel (200^2) with its time to steady state; "
+                         "elab: the eLABSWE baseline (nine stored distributions) against the streaming-only "
+                         "step on a closed 4096^2 basin")
     ap.add_argument("--implicit", action="store_true",
                     help="bump: the implicit link depth (new-time depth at the node; one step per pass, "
                          "12 more bytes per node)")
@@ -129,6 +131,8 @@ def main():
         return bench_warm_start(args, ctx)
     if args.workload in ("dish", "dish4096", "hump"):
         return bench_geometry(args, ctx, copy_gbps)
+    if args.workload == "elab":
+        return bench_elab(args, ctx, copy_gbps)
     spec = wl.bump_channel(args.n)
     spec.hbar_implicit = args.implicit
     grid = mlb.grid_from_spec(ctx, spec)
@@ -316,6 +320,78 @@ def bench_geometry(args, ctx, copy_gbps):
         cb = out["cpu_baseline"]
         cb["value"] = round(cb["value"] * water / spec.nodes, 3)
         cb["sample"] += " (water nodes only)"
+    print(json.dumps(out), flush=True)
+
+
+ELAB_BYTES_PER_LUP = 76   # read nine distributions and H, write nine (FP32)
+
+
+def bench_elab(args, ctx, copy_gbps):
+    """The storage claim on one GPU: the eLABSWE baseline (Eq. lb.1, nine
+    FP32 distributions per node, tau = 1) and the streaming-only step on the
+    same closed 4096^2 wind-driven basin, same tiles.  `value` is the
+    baseline's rate; the streaming-only rate (autotuned, two steps per pass)
+    and the ratio are in config."""
+    import torch
+    from paper_1902_02999_amd import mlb, workloads as wl
+    spec = wl.wind_lake(args.n)
+    g = mlb.grid_from_spec(ctx, spec)
+    tuned = None if args.no_autotune else g.autotune(steps=40)
+    g.step(args.warmup)
+    ctx.sync()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    ctx.sync()
+    mac_wall = time.perf_counter() - t0
+    # tile rows of the baseline: the fastest of a few (50 steps each)
+    tried = {}
+    for tr in (6, 9, 12, 15):
+        g.set_exec_opts(tile_rows=tr)
+        el = mlb.Elab(g, 1.0)
+        el.step(10)
+        ctx.sync()
+        t1 = time.perf_counter()
+        el.step(50)
+        ctx.sync()
+        tried[tr] = round((time.perf_counter() - t1) / 50 * 1e6, 2)
+        el.close()
+    best_tr = min(tried, key=tried.get)
+    g.set_exec_opts(tile_rows=best_tr)
+    el = mlb.Elab(g, 1.0)
+    el.step(args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    el.step(args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()
+    h, qx, qy = el.get_state()
+    el.close()
+    g.close()
+    ctx.close()
+    import numpy as np
+    if not (np.isfinite(h).all() and np.isfinite(qx).all() and (h > 0).all()):
+        print("bench.py: non-finite eLABSWE state", file=sys.stderr)
+        sys.exit(1)
+    nodes = spec.nodes
+    launch_s = ev_ms / 1e3 / args.steps
+    gbs = ELAB_BYTES_PER_LUP * nodes / launch_s / 1e9
+    mlups = nodes * args.steps / wall / 1e6
+    mac = nodes * args.steps / mac_wall / 1e6
+    out = {"metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "elab_tau1_" + spec.name, "nodes": nodes, "tile_rows": best_tr,
+                      "tile_rows_us_per_step": tried,
+                      "streaming_only_MLUPS": round(mac, 1), "streaming_only_exec": tuned,
+                      "streaming_only_over_elab": round(mac / mlups, 3),
+                      "elab_bytes_per_node": ELAB_BYTES_PER_LUP, "launch_us": round(launch_s * 1e6, 2),
+                      "copy_probe_GBps": round(copy_gbps, 1)},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

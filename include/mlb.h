@@ -406,6 +406,36 @@ typedef struct {
 mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* net, double tol, int64_t max_steps, int32_t check_every,
                               mlb_warm_report* report);
 
+/* ------------------------------------------------------------- eLABSWE baseline
+ * The lattice Boltzmann equation the method is derived from (Eq. lb.1): nine
+ * stored distributions per node, relaxed with a single time tau > 1/2 and
+ * streamed (pull form, Eq. lb.Mac.1), f_a^eq of Eq. feq-full, the link depth
+ * of Eq. h-bar and the link-midpoint force; viscosity
+ * nu = e^2 dt (2 tau - 1) / 6 (Eq. viscosity) with the grid's e and dt (so
+ * tau = 1 is the grid's own nu, and the step is then the streaming-only one).
+ * Bounced links take the node's own post-collision f*_abar; nodes on wall
+ * edges and WALL nodes end each step at f^eq(h', 0); SOLID nodes keep their
+ * distributions.  A baseline for measuring what stored distributions cost
+ * (72 B per node moved per step against 28 B); it has no diagnostics,
+ * graphs or batches.
+ *
+ * mlb_elab_create takes the grid's bed, node mask, edges (WALL / PERIODIC
+ * only: MLB_E_INVAL otherwise), forcing and tile rows as they are at the call,
+ * and starts from f = f^eq of the grid's current state.  The grid must
+ * outlive the baseline (mlb_grid_destroy returns MLB_E_STATE meanwhile) and
+ * must use Eq. h-bar.  Device memory: 21 planes of nx * ny floats (with the
+ * grid's pitch), allocated by the library.
+ * mlb_elab_step enqueues nsteps steps (timed by mlb_last_step_ms).
+ * mlb_elab_get_state: h = H + (sum f - H), hu, hv into host arrays [ny][ld]
+ * (synchronises); mlb_elab_get_dist_device: the distributions as
+ * [9][ny][nx] FP32 into a device array (enqueued on the stream). */
+typedef struct mlb_elab mlb_elab;
+mlb_status mlb_elab_create(mlb_grid* g, double tau, mlb_elab** out);
+mlb_status mlb_elab_step(mlb_elab* s, int64_t nsteps);
+mlb_status mlb_elab_get_state(mlb_elab* s, double* h, double* hu, double* hv, int64_t ld);
+mlb_status mlb_elab_get_dist_device(mlb_elab* s, float* f);
+mlb_status mlb_elab_destroy(mlb_elab* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -482,6 +482,7 @@ mlb_status read_diag(mlb_ctx* c, Plan& P)
 
 namespace mlb {
 mlb_status grid_set_step(mlb_grid* g, int64_t s) { return set_step(g, s); }
+void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out) { make_tiles(g, 0, rows, out, kStripOut); }
 }  // namespace mlb
 
 // ====================================================================== C ABI
@@ -622,6 +623,7 @@ mlb_status mlb_grid_destroy(mlb_grid* g)
 {
     if (!g) return fail(MLB_E_INVAL, "grid is NULL");
     if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    if (g->elab_refs) return fail(MLB_E_STATE, "an eLABSWE baseline still uses the grid");
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
     g->plan.release();

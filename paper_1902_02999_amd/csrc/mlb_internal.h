@@ -72,6 +72,30 @@ struct TileDev {
     int32_t pad;
 };
 
+// eLABSWE baseline (elab_kernels.hip): nine planes per buffer of the
+// distributions minus the node's still-water equilibrium, [9][ny][ld]
+// floats, plane = ld * ny rounded up (floats between planes).
+struct ElabDev {
+    float* f[2];
+    const float* H;
+    const uint8_t* mask;   // node kinds or nullptr
+    int64_t plane;
+    int32_t nx, ny, ld;
+    int32_t per_x, per_y;
+    // FP32 constants (computed in FP64 on the host)
+    float e;               // lattice speed
+    float tx, ty, cb, om;  // tau_w / rho, C_b, Omega
+    float cfp;             // dt / (2e)
+    float g6, c6, c3, c2;  // g/(6e^2), 1/(6e^2), 1/(3e), 1/(2e^2)
+    float gb;              // g/(2e^2)
+    float rtau;            // 1 / tau
+};
+
+hipError_t launch_elab_step(const ElabDev& D, const TileDev* d_tiles, int ntiles, int rd, hipStream_t s);
+hipError_t launch_elab_init(const ElabDev& D, const float* eta, const float* qx, const float* qy, hipStream_t s);
+hipError_t launch_elab_macro(const ElabDev& D, int rd, float* eta, float* qx, float* qy, hipStream_t s);
+hipError_t launch_elab_dist(const ElabDev& D, int rd, float* out, hipStream_t s);
+
 // Host-side launchers (mlb_kernels.hip).
 // tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
 // of kStripOut2 columns, no diag.  masked: the tile list may hold

@@ -20,6 +20,9 @@ constexpr double kStallBand = 10.0;
 // Sets a grid's step counter (host and device copies); syncs the stream.
 mlb_status grid_set_step(mlb_grid* g, int64_t s);
 
+// One-step wave tiles of a grid (mask classification included).
+void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out);
+
 }  // namespace mlb
 
 #define HIPCHK(call)                                                                        \
@@ -125,6 +128,7 @@ struct mlb_grid {
     mlb_batch* batch = nullptr;
     mlb_exec_opts opts{15, 1, 1, 64, 3, 0};
     mlb::Plan plan;
+    int elab_refs = 0;         // live eLABSWE baselines built on this grid
     bool dirty = true;         // descriptor must be re-uploaded
     bool stale_plan = true;    // tiles / allocation must be rebuilt
 };

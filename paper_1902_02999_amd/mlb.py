@@ -153,6 +153,11 @@ SIGNATURES = {
     "mlb_net_train": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(TrainCfg), _DP]),
     "mlb_warm_start_run": (C.c_int, [_VP, _VP, C.c_double, C.c_int64, C.c_int32, C.POINTER(WarmReport)]),
     "mlb_set_stall_checks": (C.c_int, [_VP, C.c_int32]),
+    "mlb_elab_create": (C.c_int, [_VP, C.c_double, C.POINTER(_VP)]),
+    "mlb_elab_step": (C.c_int, [_VP, C.c_int64]),
+    "mlb_elab_get_state": (C.c_int, [_VP, _DP, _DP, _DP, C.c_int64]),
+    "mlb_elab_get_dist_device": (C.c_int, [_VP, _VP]),
+    "mlb_elab_destroy": (C.c_int, [_VP]),
 }
 
 _lib = None
@@ -435,6 +440,36 @@ def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
     h, qx, qy = spec.initial()
     g.set_state(h, qx, qy)
     return g
+
+
+class Elab:
+    """The eLABSWE baseline (nine stored distributions, relaxation time tau)
+    on a grid's geometry and forcing; starts from f = f^eq of its state."""
+
+    def __init__(self, grid: "Grid", tau: float):
+        self.grid = grid
+        h = _VP()
+        _check(lib().mlb_elab_create(grid.h, float(tau), C.byref(h)), "mlb_elab_create")
+        self.h = h
+
+    def step(self, n: int):
+        _check(lib().mlb_elab_step(self.h, int(n)), "mlb_elab_step")
+
+    def get_state(self):
+        g = self.grid
+        h = np.empty((g.ny, g.nx)); qx = np.empty_like(h); qy = np.empty_like(h)
+        _check(lib().mlb_elab_get_state(self.h, _dptr(h), _dptr(qx), _dptr(qy), g.nx), "mlb_elab_get_state")
+        return h, qx, qy
+
+    def get_dist(self, out):
+        """Distributions [9][ny][nx] into a torch CUDA float32 tensor (or a device pointer)."""
+        ptr = out if isinstance(out, int) else out.data_ptr()
+        _check(lib().mlb_elab_get_dist_device(self.h, ptr), "mlb_elab_get_dist_device")
+
+    def close(self):
+        if self.h:
+            _check(lib().mlb_elab_destroy(self.h), "mlb_elab_destroy")
+            self.h = None
 
 
 class Net:
