@@ -343,6 +343,14 @@ def bench_elab(args, ctx, copy_gbps):
     g.step(args.steps)
     ctx.sync()
     mac_wall = time.perf_counter() - t0
+    # the streaming-only step with one step per pass (same tiles as the baseline's walk)
+    g.set_exec_opts(tblock=1, tile_rows=15)
+    g.step(args.warmup)
+    ctx.sync()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    ctx.sync()
+    mac1_wall = time.perf_counter() - t0
     # tile rows of the baseline: the fastest of a few (50 steps each)
     tried = {}
     for tr in (6, 9, 12, 15):
@@ -387,6 +395,7 @@ def bench_elab(args, ctx, copy_gbps):
                       "tile_rows_us_per_step": tried,
                       "streaming_only_MLUPS": round(mac, 1), "streaming_only_exec": tuned,
                       "streaming_only_over_elab": round(mac / mlups, 3),
+                      "streaming_only_one_step_MLUPS": round(nodes * args.steps / mac1_wall / 1e6, 1),
                       "elab_bytes_per_node": ELAB_BYTES_PER_LUP, "launch_us": round(launch_s * 1e6, 2),
                       "copy_probe_GBps": round(copy_gbps, 1)},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
