@@ -30,24 +30,25 @@ FP32_PEAK_TFLOPS = 78.6
 FLOP_PER_LUP = {True: 104, False: 97}
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
-                 2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json")}
+                 2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
+                 "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
+                 "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
+                 "elab": os.path.join(ROOT, "profiles", "elab_step_kernel_lake4096_traffic.json")}
 
 
-def kernel_hash() -> str:
-    from paper_1902_02999_amd.profiling import kernel_sha
-    return kernel_sha()
-
-
-def measured_traffic(nodes: int, tblock: int):
-    """HBM bytes per launch of the dominant step kernel from the committed
+def measured_traffic(nodes: int, key):
+    """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, or None when it was taken on a different
-    kernel source."""
+    kernel source or problem size."""
+    from paper_1902_02999_amd.profiling import kernel_sha
     try:
-        with open(TRAFFIC_FILES[tblock]) as f:
+        with open(TRAFFIC_FILES[key]) as f:
             t = json.load(f)
-    except (OSError, ValueError):
+        src = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", t.get("kernel_source", "mlb_kernels.hip"))
+        sha = kernel_sha(src)
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_sha") != kernel_hash() or t.get("nodes") != nodes:
+    if t.get("kernel_sha") != sha or t.get("nodes") != nodes:
         return None
     return t.get("bytes_per_launch")
 
@@ -103,6 +104,8 @@ def main():
     ap.add_argument("--implicit", action="store_true",
                     help="bump: the implicit link depth (new-time depth at the node; one step per pass, "
                          "12 more bytes per node)")
+    ap.add_argument("--elab-tile-rows", type=int, default=0,
+                    help="elab: tile rows of the eLABSWE baseline (0: the fastest of 6, 9, 12, 15)")
     ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
     ap.add_argument("--ws-train", type=int, default=512, help="warm_start: training basins")
     ap.add_argument("--ws-epochs", type=int, default=40, help="warm_start: training epochs")
@@ -164,7 +167,7 @@ def main():
     launch_s = tb * ev_ms / 1e3 / args.steps
     bpl = BYTES_PER_LUP + (12 if args.implicit else 0)   # + 1/(1+kappa), kappa_x, kappa_y
     gbs = bpl * nodes / launch_s / 1e9
-    traffic = None if args.implicit else measured_traffic(nodes, tb)
+    traffic = measured_traffic(nodes, "implicit" if args.implicit else tb)
     if tb == 1:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -288,7 +291,8 @@ def bench_geometry(args, ctx, copy_gbps):
     gbs = bpl / launch_s / 1e9
     if tb == 1:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(water, args.workload) if args.workload == "dish4096" else None}
     else:
         tfl = FLOP_PER_LUP[spec.chezy > 0] * 2 * water / launch_s / 1e12
         roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -353,7 +357,7 @@ def bench_elab(args, ctx, copy_gbps):
     mac1_wall = time.perf_counter() - t0
     # tile rows of the baseline: the fastest of a few (50 steps each)
     tried = {}
-    for tr in (6, 9, 12, 15):
+    for tr in ((args.elab_tile_rows,) if args.elab_tile_rows else (6, 9, 12, 15)):
         g.set_exec_opts(tile_rows=tr)
         el = mlb.Elab(g, 1.0)
         el.step(10)
@@ -365,6 +369,7 @@ def bench_elab(args, ctx, copy_gbps):
         el.close()
     best_tr = min(tried, key=tried.get)
     g.set_exec_opts(tile_rows=best_tr)
+    tried = tried if len(tried) > 1 else None
     el = mlb.Elab(g, 1.0)
     el.step(args.warmup)
     ctx.sync()
@@ -399,7 +404,7 @@ def bench_elab(args, ctx, copy_gbps):
                       "elab_bytes_per_node": ELAB_BYTES_PER_LUP, "launch_us": round(launch_s * 1e6, 2),
                       "copy_probe_GBps": round(copy_gbps, 1)},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(nodes, "elab")},
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

@@ -20,8 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "mlb_kernels.hip")
 
 
-def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_sha(src: str = KERNEL_SRC) -> str:
+    """Short hash of a kernel source file (default: the step kernels)."""
+    with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -93,7 +94,8 @@ def cmd_traffic(a):
     fetch_b = f_k * sf * 1024.0
     write_b = w_k * sw * 1024.0
     alg = a.bytes_per_unit * a.nodes
-    res = {"kernel": a.kernel, "kernel_sha": kernel_sha(), "nodes": a.nodes,
+    src = os.path.join(HERE, "csrc", a.source)
+    res = {"kernel": a.kernel, "kernel_source": a.source, "kernel_sha": kernel_sha(src), "nodes": a.nodes,
            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
            "bytes_per_launch": fetch_b + write_b, "algorithmic_bytes_per_launch": alg,
            "fetch_scale": sf, "write_scale": sw,
@@ -112,7 +114,7 @@ def cmd_traffic(a):
               (fetch_b + write_b) / 1e6, fetch_b / 1e6, write_b / 1e6),
           "| algorithmic bytes per launch | %.1f MB (%d B x %d nodes) |" % (alg / 1e6, a.bytes_per_unit, a.nodes),
           "| measured / algorithmic | %.3f |" % ((fetch_b + write_b) / alg),
-          "", "Kernel source sha256[:16]: `%s`" % res["kernel_sha"]]
+          "", "Kernel source (`%s`) sha256[:16]: `%s`" % (a.source, res["kernel_sha"])]
     open(a.out_md, "w").write("\n".join(md) + "\n")
     print("\n".join(md))
 
@@ -133,6 +135,7 @@ def main():
     t.add_argument("--kernel", default="step_kernel")
     t.add_argument("--nodes", type=int, required=True)
     t.add_argument("--bytes-per-unit", type=int, default=28)
+    t.add_argument("--source", default="mlb_kernels.hip", help="kernel source file under csrc/ (for its hash)")
     t.add_argument("--title", default="")
     t.add_argument("--commands", required=True)
     t.add_argument("--out-json", required=True)
