@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--implicit", action="store_true",
                     help="bump: the implicit link depth (new-time depth at the node; one step per pass, "
                          "12 more bytes per node)")
+    ap.add_argument("--compensated", action="store_true",
+                    help="bump: surface stored as a compensated FP32 pair (one step per pass, 8 more bytes per node)")
     ap.add_argument("--elab-tile-rows", type=int, default=0,
                     help="elab: tile rows of the eLABSWE baseline (0: the fastest of 6, 9, 12, 15)")
     ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
@@ -138,6 +140,7 @@ def main():
         return bench_elab(args, ctx, copy_gbps)
     spec = wl.bump_channel(args.n)
     spec.hbar_implicit = args.implicit
+    spec.compensated = args.compensated
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
                        blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
@@ -162,12 +165,13 @@ def main():
     tb = grid.exec_opts().tblock
     # Dominant kernel: one launch per step (tblock 1) or per two steps (tblock
     # 2; the one or two closing single steps of the call are < 0.3 % of it).
-    if args.implicit:
+    if args.implicit or args.compensated:
         tb = 1   # one step per pass whatever was requested
     launch_s = tb * ev_ms / 1e3 / args.steps
-    bpl = BYTES_PER_LUP + (12 if args.implicit else 0)   # + 1/(1+kappa), kappa_x, kappa_y
+    # + 1/(1+kappa), kappa_x, kappa_y; + the low part of eta read and written
+    bpl = BYTES_PER_LUP + (12 if args.implicit else 0) + (8 if args.compensated else 0)
     gbs = bpl * nodes / launch_s / 1e9
-    traffic = measured_traffic(nodes, "implicit" if args.implicit else tb)
+    traffic = None if args.compensated else measured_traffic(nodes, "implicit" if args.implicit else tb)
     if tb == 1:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -192,6 +196,7 @@ def main():
         "config": {"workload": spec.name, "nodes": nodes, "dx_m": spec.dx, "dt_s": spec.dx / (6 * spec.nu / spec.dx),
                    "tile_rows": grid.exec_opts().tile_rows, "blocks_per_cu": grid.exec_opts().blocks_per_cu,
                    "tblock": grid.exec_opts().tblock, "hbar": "implicit" if args.implicit else "eq_h-bar",
+                   "surface": "compensated" if args.compensated else "fp32",
                    "autotuned": tuned is not None, "graph": not args.no_graph,
                    # per-step bytes of the one-step formulation x update rate
                    "effective_GBps": round(mlups * 1e6 * bpl / 1e9, 1),

@@ -171,6 +171,30 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 enum { MLB_HBAR_SEMI_IMPLICIT = 0, MLB_HBAR_IMPLICIT = 1 };
 mlb_status mlb_set_hbar(mlb_grid* g, int32_t mode);
 
+/* Storage precision of the surface perturbation eta = h - H.
+ *   FP32         one FP32 plane per buffer (default; every kernel).
+ *   COMPENSATED  eta is the unevaluated sum of two FP32 values (a second
+ *                plane per buffer holds the low part): each update adds its
+ *                increment to the low part and renormalises exactly, and link
+ *                surface differences include the low parts.  For slow flows
+ *                under a large surface range (a tide of several metres driven
+ *                by surface slopes of 1e-7) FP32 rounding of eta, not the
+ *                arithmetic, limits the accuracy; this removes that limit.
+ *                8 more bytes per node per step (36 B); one step per pass
+ *                with ordinary launches (tblock 2 and persistent are accepted
+ *                and run as one-step graph / stream launches).  The
+ *                free surface extrapolated onto a DISCHARGE edge is rounded
+ *                to FP32 (its low part is 0).  Switching it on sets the low
+ *                parts to 0; mlb_set_state splits h - H exactly into the
+ *                pair, mlb_get_state returns H + high + low,
+ *                mlb_set_state_device sets the low parts to 0 and
+ *                mlb_get_state_device returns the high part.
+ * MLB_E_STATE if the grid belongs to a live batch.  The grids of a batch must
+ * share the mode (mlb_batch_create: MLB_E_INVAL otherwise); the warm start
+ * (mlb_net_infer, mlb_warm_start_run) takes FP32 grids only. */
+enum { MLB_SURFACE_FP32 = 0, MLB_SURFACE_COMPENSATED = 1 };
+mlb_status mlb_set_surface(mlb_grid* g, int32_t mode);
+
 /* Uniform wind speed (u_wx, u_wy) [m/s]: tau_w / rho = rho_air c_w u_w |u_w| / rho_w
  * (Eq. wind_u-stress). */
 mlb_status mlb_set_wind(mlb_grid* g, double uwx, double uwy);

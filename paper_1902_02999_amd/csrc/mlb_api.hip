@@ -48,6 +48,7 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     b.cw = imp ? g->dcoef : nullptr;
     b.ckx = imp ? g->dcoef + g->plane : nullptr;
     b.cky = imp ? g->dcoef + 2 * g->plane : nullptr;
+    for (int k = 0; k < 2; ++k) b.etal[k] = g->etal ? g->etal + k * g->plane : nullptr;
     b.stepc = g->stepc;
     b.nx = g->p.nx; b.ny = g->p.ny; b.ld = g->ld;
     b.swap = swap;
@@ -191,7 +192,7 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.ht2.clear();
         make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
         // masked grids and the implicit link depth run one step per pass
-        const bool one = g->dmask || g->hbar == MLB_HBAR_IMPLICIT;
+        const bool one = g->dmask || g->hbar == MLB_HBAR_IMPLICIT || g->etal;
         if (g->opts.tblock == 2 && !one) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
@@ -199,6 +200,7 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.hb[0].ntiles2 = (int)g->plan.ht2.size();
         g->plan.masked = g->dmask != nullptr;
         g->plan.implicit = g->hbar == MLB_HBAR_IMPLICIT;
+        g->plan.comp = g->etal != nullptr;
         CHK(plan_alloc(c, g->plan));
         g->stale_plan = false;
         g->dirty = false;
@@ -239,7 +241,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     int64_t nl = 0;
     auto eager = [&](int k, bool diag) -> mlb_status {
         HIPCHK(launch_step(P.db, k == 2 ? P.dt2 : P.dt, k == 2 ? nt2 : nt1, P.parity, P.dpart, diag ? 1 : 0, k,
-                           P.masked ? 1 : 0, P.implicit ? 1 : 0, dyn, c->stream));
+                           P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, dyn, c->stream));
         P.parity ^= 1;
         ++nl;
         return MLB_OK;
@@ -255,7 +257,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     }
     // persistent: all `multi` passes in cooperative launches with grid barriers
     // (not for the implicit link depth: those basins use ordinary launches)
-    if (o.persistent && multi > 0 && !P.coop_failed && !P.implicit) {
+    if (o.persistent && multi > 0 && !P.coop_failed && !P.implicit && !P.comp) {
         const int nt = kind == 2 ? nt2 : nt1;
         const int nblk = (nt + kBlock / kWave - 1) / (kBlock / kWave);
         if (persistent_capacity(kind, P.masked ? 1 : 0, c->ncu) < nblk) {
@@ -288,7 +290,7 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             hipError_t le = hipSuccess;
             for (int i = 0; i < glaunch && le == hipSuccess; ++i) {
                 le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind,
-                                 P.masked ? 1 : 0, P.implicit ? 1 : 0, dyn, c->stream);
+                                 P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, dyn, c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -356,10 +358,13 @@ mlb_status upload_host_state(mlb_grid* g, const double* h, const double* hu, con
 {
     const int nx = g->p.nx, ny = g->p.ny;
     std::vector<float> e((size_t)g->ld * ny, 0.f), a((size_t)g->ld * ny, 0.f), b((size_t)g->ld * ny, 0.f);
+    std::vector<float> el(g->etal ? e.size() : 0, 0.f);
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             const size_t s = (size_t)j * ld + i, d = (size_t)j * g->ld + i;
-            e[d] = h ? (float)(h[s] - g->Hd[d]) : 0.f;
+            const double ed = h ? h[s] - g->Hd[d] : 0.0;
+            e[d] = (float)ed;
+            if (g->etal) el[d] = (float)(ed - (double)e[d]);   // compensated surface: the remainder
             a[d] = hu ? (float)hu[s] : 0.f;
             b[d] = hv ? (float)hv[s] : 0.f;
         }
@@ -368,6 +373,8 @@ mlb_status upload_host_state(mlb_grid* g, const double* h, const double* hu, con
         HIPCHK(hipMemcpyAsync(g->eta[k], e.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
         HIPCHK(hipMemcpyAsync(g->qx[k], a.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
         HIPCHK(hipMemcpyAsync(g->qy[k], b.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        if (g->etal)
+            HIPCHK(hipMemcpyAsync(g->etal + k * g->plane, el.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
     }
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     return MLB_OK;
@@ -630,6 +637,7 @@ mlb_status mlb_grid_destroy(mlb_grid* g)
     if (g->own) (void)hipFree(g->base);
     if (g->dmask) (void)hipFree(g->dmask);
     if (g->dcoef) (void)hipFree(g->dcoef);
+    if (g->etal) (void)hipFree(g->etal);
     g->ctx->live--;
     delete g;
     return MLB_OK;
@@ -745,12 +753,35 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
         HIPCHK(hipMemcpyAsync(g->eta[o], g->eta[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
         HIPCHK(hipMemcpyAsync(g->qx[o], g->qx[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
         HIPCHK(hipMemcpyAsync(g->qy[o], g->qy[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        if (g->etal)
+            HIPCHK(hipMemcpyAsync(g->etal + o * g->plane, g->etal + g->cur * g->plane, bytes, hipMemcpyDeviceToDevice,
+                                  g->ctx->stream));
         HIPCHK(hipStreamSynchronize(g->ctx->stream));
         g->hmask.swap(m);
     }
     g->sumH = water_depth_sum(g);
     CHK(implicit_coeffs(g));
     g->stale_plan = true;
+    return MLB_OK;
+}
+
+mlb_status mlb_set_surface(mlb_grid* g, int32_t mode)
+{
+    GRID_OK(g);
+    if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
+    if (mode != MLB_SURFACE_FP32 && mode != MLB_SURFACE_COMPENSATED) return fail(MLB_E_INVAL, "unknown surface mode");
+    const bool on = mode == MLB_SURFACE_COMPENSATED;
+    if (on && !g->etal) {
+        HIPCHK(hipMalloc((void**)&g->etal, 2 * g->plane * sizeof(float)));
+        HIPCHK(hipMemsetAsync(g->etal, 0, 2 * g->plane * sizeof(float), g->ctx->stream));
+        HIPCHK(hipStreamSynchronize(g->ctx->stream));
+        g->stale_plan = true;
+    } else if (!on && g->etal) {
+        HIPCHK(hipStreamSynchronize(g->ctx->stream));
+        (void)hipFree(g->etal);
+        g->etal = nullptr;
+        g->stale_plan = true;
+    }
     return MLB_OK;
 }
 
@@ -788,6 +819,7 @@ mlb_status mlb_set_state_device(mlb_grid* g, const float* eta, const float* qx, 
         HIPCHK(hipMemcpy2DAsync(g->qx[k], pitch, qx, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
         HIPCHK(hipMemcpy2DAsync(g->qy[k], pitch, qy, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
     }
+    if (g->etal) HIPCHK(hipMemsetAsync(g->etal, 0, 2 * g->plane * sizeof(float), g->ctx->stream));
     return MLB_OK;
 }
 
@@ -801,11 +833,14 @@ mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t
     HIPCHK(hipMemcpyAsync(e.data(), g->eta[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     HIPCHK(hipMemcpyAsync(a.data(), g->qx[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     HIPCHK(hipMemcpyAsync(b.data(), g->qy[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    std::vector<float> el(g->etal ? e.size() : 0, 0.f);
+    if (g->etal)
+        HIPCHK(hipMemcpyAsync(el.data(), g->etal + g->cur * g->plane, bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             const size_t s = (size_t)j * g->ld + i, d = (size_t)j * ld + i;
-            if (h) h[d] = g->Hd[s] + (double)e[s];
+            if (h) h[d] = g->Hd[s] + (double)e[s] + (g->etal ? (double)el[s] : 0.0);
             if (hu) hu[d] = a[s];
             if (hv) hv[d] = b[s];
         }
@@ -972,6 +1007,7 @@ static mlb_status batch_plan(mlb_batch* b)
     bool masked = false;
     for (auto* g : b->grids) masked |= g->dmask != nullptr;
     const bool implicit = b->grids[0]->hbar == MLB_HBAR_IMPLICIT;   // shared by every grid
+    const bool comp = b->grids[0]->etal != nullptr;                  // likewise
     for (int k = 0; k < n; ++k) {
         const int i = order[k];
         mlb_grid* g = b->grids[i];
@@ -980,12 +1016,14 @@ static mlb_status batch_plan(mlb_batch* b)
         make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
         d.first_tile2 = (int)b->plan.ht2.size();
-        if (b->opts.tblock == 2 && !masked && !implicit) make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
+        if (b->opts.tblock == 2 && !masked && !implicit && !comp)
+            make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
     }
     b->plan.masked = masked;
     b->plan.implicit = implicit;
+    b->plan.comp = comp;
     CHK(plan_alloc(b->ctx, b->plan));
     b->stale_plan = false;
     return MLB_OK;
@@ -1001,6 +1039,8 @@ mlb_status mlb_batch_create(mlb_ctx* c, mlb_grid* const* grids, int32_t n, mlb_b
         if (grids[i]->batch) return fail(MLB_E_STATE, "grid already in a batch");
         if (grids[i]->hbar != grids[0]->hbar)
             return fail(MLB_E_INVAL, "the grids of a batch must share the link-depth form");
+        if ((grids[i]->etal != nullptr) != (grids[0]->etal != nullptr))
+            return fail(MLB_E_INVAL, "the grids of a batch must share the surface precision");
         for (int k = 0; k < i; ++k)
             if (grids[k] == grids[i]) return fail(MLB_E_INVAL, "grid listed twice");
     }
@@ -1116,9 +1156,12 @@ mlb_status save_states(mlb_ctx* c, const std::vector<mlb_grid*>& gs, Saved& sv)
 {
     for (mlb_grid* g : gs) {
         float* p = nullptr;
-        HIPCHK(hipMalloc(&p, 3 * g->plane * sizeof(float)));
+        HIPCHK(hipMalloc(&p, 4 * g->plane * sizeof(float)));
         sv.buf.push_back(p);
         sv.step.push_back(g->step);
+        if (g->etal)
+            HIPCHK(hipMemcpyAsync(p + 3 * g->plane, g->etal + g->cur * g->plane, g->plane * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(p, g->eta[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(p + g->plane, g->qx[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(p + 2 * g->plane, g->qy[g->cur], g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
@@ -1135,6 +1178,9 @@ mlb_status restore_states(mlb_ctx* c, const std::vector<mlb_grid*>& gs, Saved& s
             HIPCHK(hipMemcpyAsync(g->eta[k], p, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(hipMemcpyAsync(g->qx[k], p + g->plane, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
             HIPCHK(hipMemcpyAsync(g->qy[k], p + 2 * g->plane, g->plane * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            if (g->etal)
+                HIPCHK(hipMemcpyAsync(g->etal + k * g->plane, p + 3 * g->plane, g->plane * sizeof(float),
+                                      hipMemcpyDeviceToDevice, c->stream));
         }
         CHK(set_step(g, sv.step[i]));
     }
@@ -1193,7 +1239,7 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
     bool masked = false;   // masked grids and the implicit link depth run one step per pass
-    for (auto* g : gs) masked |= g->dmask != nullptr || g->hbar == MLB_HBAR_IMPLICIT;
+    for (auto* g : gs) masked |= g->dmask != nullptr || g->hbar == MLB_HBAR_IMPLICIT || g->etal != nullptr;
     for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))
@@ -1246,7 +1292,8 @@ mlb_status mlb_autotune(mlb_grid* g, int32_t steps, const char* cache_path, mlb_
     if (steps < 2) return fail(MLB_E_INVAL, "steps must be >= 2");
     mlb_ctx* c = g->ctx;
     const std::string key = c->arch + "_g" + std::to_string(g->p.nx) + "x" + std::to_string(g->p.ny) +
-                            (g->dmask ? "m" : "") + (g->hbar == MLB_HBAR_IMPLICIT ? "i" : "");
+                            (g->dmask ? "m" : "") + (g->hbar == MLB_HBAR_IMPLICIT ? "i" : "") +
+                            (g->etal ? "c" : "");
     mlb_exec_opts o = g->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_set_exec_opts(g, &o));
@@ -1287,7 +1334,8 @@ mlb_status mlb_batch_autotune(mlb_batch* b, int32_t steps, const char* cache_pat
     bool masked = false;
     for (auto* g : b->grids) { nodes += (int64_t)g->p.nx * g->p.ny; masked |= g->dmask != nullptr; }
     const std::string key = c->arch + "_b" + std::to_string(b->grids.size()) + "n" + std::to_string(nodes) +
-                            (masked ? "m" : "") + (b->grids[0]->hbar == MLB_HBAR_IMPLICIT ? "i" : "");
+                            (masked ? "m" : "") + (b->grids[0]->hbar == MLB_HBAR_IMPLICIT ? "i" : "") +
+                            (b->grids[0]->etal ? "c" : "");
     mlb_exec_opts o = b->opts;
     if (cache_lookup(cache_path, key, &o)) {
         CHK(mlb_batch_set_exec_opts(b, &o));

@@ -33,6 +33,8 @@ struct BasinDev {
     const float* cw;
     const float* ckx;
     const float* cky;
+    // compensated surface: low part of eta per buffer (nullptr: plain FP32)
+    float* etal[2];
     int64_t* stepc;        // [2]: step counter, read from [rd], written to [1-rd]
     int32_t nx, ny, ld;
     int32_t swap;          // buffer read by a launch of parity p is p ^ swap
@@ -100,10 +102,10 @@ hipError_t launch_elab_dist(const ElabDev& D, int rd, float* out, hipStream_t s)
 // tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
 // of kStripOut2 columns, no diag.  masked: the tile list may hold
 // TILE_MASKED tiles; implicit: every basin has the implicit link-depth
-// planes (both one-step only).
+// planes; comp: every basin has a compensated surface (all one-step only).
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, int masked, int implicit, unsigned dyn_lds,
-                       hipStream_t s);
+                       double* d_partials, int diag, int tblock, int masked, int implicit, int comp,
+                       unsigned dyn_lds, hipStream_t s);
 // npasses passes of `kind` steps in one cooperative launch (all tiles
 // resident); base = sync->count at launch.  Fails (no launch) when the grid
 // cannot be co-resident.

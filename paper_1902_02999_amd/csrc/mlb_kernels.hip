@@ -79,6 +79,7 @@ struct Node {
     float o[9];            // o[a] = Out_a(node), a = 1..8
     float H, q0x, q0y;     // the node's stored H and old discharge
     float iw, ikx, iky;    // implicit link depth: 1/(1+kappa), kappa_x, kappa_y
+    float el;              // compensated surface: low part of eta
 };
 
 // Node quantities from the old state (Eqs. SWE-force, bed-stress, feq-full).
@@ -143,6 +144,7 @@ struct Row {
     float S1, S2, N1, N2, E1, E2;
     float o1l, o5r, o2l, o3, o4r, o6r, o7, o8l;
     int mk, ms;            // masked tiles: node kind; SOLID at x-1, x, x+1 (bits 0, 1, 2)
+    float el;              // compensated surface: low part of eta
 };
 
 template <bool EDGE>
@@ -184,6 +186,22 @@ __device__ __forceinline__ float link_left(float hx, float ex, const Row& R)
     return (hx + from_left(R.h)) * (from_left(R.eta) - ex);
 }
 
+// Compensated surface (eta = eta_hi + eta_lo, both FP32): the surface
+// difference of a link is (ey - ex) + (ly - lx), the low parts restoring what
+// rounding eta to FP32 loses.
+__device__ __forceinline__ float link_c(float hx, float ex, float lx, float hy, float ey, float ly)
+{
+    return (hx + hy) * ((ey - ex) + (ly - lx));
+}
+__device__ __forceinline__ float link_right_c(float hx, float ex, float lx, const Row& R)
+{
+    return (hx + from_right(R.h)) * ((from_right(R.eta) - ex) + (from_right(R.el) - lx));
+}
+__device__ __forceinline__ float link_left_c(float hx, float ex, float lx, const Row& R)
+{
+    return (hx + from_left(R.h)) * ((from_left(R.eta) - ex) + (from_left(R.el) - lx));
+}
+
 // Links a row passes to the row above: its N link at x and its NE / NW links
 // as the node above at x receives them (from x-1 and x+1).  Interior tiles
 // keep their sum and difference, edge tiles the two values.
@@ -216,21 +234,31 @@ __device__ __forceinline__ void carry_from(float lN, float lNE, float lNW, Carry
 // kappa = g/(2e^2) sum_a C_a (z_x - z_y) and kappa_v = g/(2e) sum_a C_a e^_a (z_x - z_y)
 // over the non-bounced links the increment of the old-depth update is scaled
 // by 1/(1+kappa) and the discharge loses increment * kappa_v.
-template <bool IMPL>
-__device__ __forceinline__ void finish(const Node& x, float inc, float& en, float& qxn, float& qyn)
+//
+// COMP (compensated surface): the increment joins the low part first and the
+// new pair is renormalised exactly (Fast2Sum: |eta_hi| >= |inc + eta_lo|, or
+// eta_hi = 0), so eta loses no more than FP32 rounding of the pair's sum.
+template <bool IMPL, bool COMP>
+__device__ __forceinline__ void finish(const Node& x, float inc, float& en, float& enl, float& qxn, float& qyn)
 {
     if (IMPL) {
         inc = inc * x.iw;
         qxn = __builtin_fmaf(-inc, x.ikx, qxn);
         qyn = __builtin_fmaf(-inc, x.iky, qyn);
     }
-    en = x.eta + inc;
+    if (COMP) {
+        const float s = inc + x.el;
+        en = x.eta + s;
+        enl = s - (en - x.eta);
+    } else {
+        en = x.eta + inc;
+    }
 }
 
-template <bool IMPL>
+template <bool IMPL, bool COMP>
 __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, const Row& S, const Row& C,
                                             const Row& N, const Carry& cy, float lE, float lN, float lNE,
-                                            float lNW, float& en, float& qxn, float& qyn)
+                                            float lNW, float& en, float& enl, float& qxn, float& qyn)
 {
     const float Ha = lE - from_left(lE), Hs = from_left(lE) + lE;   // Ha, -Hx
     const float Ud = lNE + lNW, Ux = lNW - lNE;
@@ -244,13 +272,13 @@ __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, co
     const float myo = S.S1 - N.N1;
     qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
     qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
-    finish<IMPL>(x, (so - x.kk) + mp, en, qxn, qyn);
+    finish<IMPL, COMP>(x, (so - x.kk) + mp, en, enl, qxn, qyn);
 }
 
 // The same from the link products P[a] and gathered equilibria oy[a] = Out_a(y_a).
-template <bool IMPL>
+template <bool IMPL, bool COMP>
 __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, const float* P, const float* oy,
-                                            float& en, float& qxn, float& qyn)
+                                            float& en, float& enl, float& qxn, float& qyn)
 {
     const float Ha = P[1] + P[5], Hx = P[1] - P[5];
     const float Bd = P[2] + P[4], Bx = P[2] - P[4];
@@ -268,10 +296,10 @@ __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, co
     const float myo = S1 - N1;
     qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
     qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
-    finish<IMPL>(x, (so - x.kk) + mp, en, qxn, qyn);
+    finish<IMPL, COMP>(x, (so - x.kk) + mp, en, enl, qxn, qyn);
 }
 
-struct Raw { float eta, qx, qy, H; int m; float iw, ikx, iky; };   // m: node kind (masked tiles)
+struct Raw { float eta, qx, qy, H; int m; float iw, ikx, iky; float el; };   // m: node kind (masked tiles)
 
 // Index of a column / row to load: wrapped on periodic axes (lanes of a strip
 // can reach past the grid on narrow grids), clamped otherwise (values there
@@ -315,10 +343,11 @@ typedef __attribute__((address_space(1))) const uint8_t gcu8;
 // Static per-node planes of the implicit link depth.
 struct Coef { const gfloat* w; const gfloat* kx; const gfloat* ky; };
 
-template <bool MASK, bool IMPL>
+template <bool MASK, bool IMPL, bool COMP>
 __device__ __forceinline__ Raw load_raw(const gfloat* __restrict__ E0, const gfloat* __restrict__ QX0,
                                         const gfloat* __restrict__ QY0, const gfloat* __restrict__ HH,
-                                        gcu8* __restrict__ MK, const Coef& K, uint32_t o)
+                                        const gfloat* __restrict__ EL0, gcu8* __restrict__ MK, const Coef& K,
+                                        uint32_t o)
 {
     const uint32_t b = o * 4u;
     Raw w;
@@ -326,19 +355,21 @@ __device__ __forceinline__ Raw load_raw(const gfloat* __restrict__ E0, const gfl
     w.m = MASK ? (int)MK[o] : 0;
     if (IMPL) { w.iw = ldf(K.w, b); w.ikx = ldf(K.kx, b); w.iky = ldf(K.ky, b); }
     else { w.iw = 1.0f; w.ikx = 0.0f; w.iky = 0.0f; }
+    w.el = COMP ? ldf(EL0, b) : 0.0f;
     return w;
 }
 
-template <bool IMPL>
+template <bool IMPL, bool COMP>
 __device__ __forceinline__ void take_coef(const Raw& w, Node& d)
 {
     if (IMPL) { d.iw = w.iw; d.ikx = w.ikx; d.iky = w.iky; }
+    d.el = COMP ? w.el : 0.0f;
 }
 
 struct Sums { double eta, dq, q, bad, vmax; };
 
 __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn, float Hn, float oqx,
-                                        float oqy)
+                                        float oqy, float el)
 {
     const double h = (double)Hn + (double)en;
     const bool ok = __builtin_isfinite(en) && __builtin_isfinite(qxn) && __builtin_isfinite(qyn) &&
@@ -346,6 +377,7 @@ __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn,
     if (ok) {
         const double a = qxn, b = qyn, da = a - (double)oqx, db = b - (double)oqy;
         s.eta += en;
+        s.eta += el;
         s.dq += da * da + db * db;
         const double q2 = a * a + b * b;
         s.q += q2;
@@ -362,7 +394,7 @@ __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn,
 struct Stage {
     Carry cy;
     float h1e, h1x, h1y, h2e, h2x, h2y;
-    float pe, pqx, pqy, pH, poqx, poqy;
+    float pe, pqx, pqy, pH, poqx, poqy, pl;
     double hbS, hbN, hb_x;
 };
 
@@ -406,7 +438,7 @@ template <bool EDGE>
 __device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, double tn, Stage& V)
 {
     V.h1e = V.h1x = V.h1y = V.h2e = V.h2x = V.h2y = 0.0f;
-    V.pe = V.pqx = V.pqy = V.pH = V.poqx = V.poqy = 0.0f;
+    V.pe = V.pqx = V.pqy = V.pH = V.poqx = V.poqy = V.pl = 0.0f;
     V.hbS = V.hbN = V.hb_x = 0.0;
     if (EDGE) {
         const int kW = B.kind[0], kE = B.kind[1];
@@ -418,30 +450,38 @@ __device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, do
 }
 
 // Links of window row S towards row C (the first row of a walk).
-template <bool EDGE>
+template <bool EDGE, bool COMP>
 __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& cy)
 {
-    carry_from<EDGE>(link(dS.h, dS.eta, C.h, C.eta), link_right(dS.h, dS.eta, C),
-                     link_left(dS.h, dS.eta, C), cy);
+    if (COMP)
+        carry_from<EDGE>(link_c(dS.h, dS.eta, dS.el, C.h, C.eta, C.el), link_right_c(dS.h, dS.eta, dS.el, C),
+                         link_left_c(dS.h, dS.eta, dS.el, C), cy);
+    else
+        carry_from<EDGE>(link(dS.h, dS.eta, C.h, C.eta), link_right(dS.h, dS.eta, C),
+                         link_left(dS.h, dS.eta, C), cy);
 }
 
 // One output row r of a stage V from window rows S (r-1), C (r), N (r+1).
 // RAWN holds the raw values of row r+1; LOADNEXT refills it (or nothing).
-// EMIT(en, qxn, qyn, DC) receives the row's new values and its old node
-// (lanes decide ownership);
-// EMIT0(ge, gx, gy) the deferred row 0 of an open S edge, once rows 1 (and 2)
-// exist.  A macro rather than a function or lambda: every operand stays a
+// EMIT(en, qxn, qyn, DC, enl) receives the row's new values and its old node
+// (lanes decide ownership; enl is the new low part of a compensated surface);
+// EMIT0(ge, gx, gy, gl) the deferred row 0 of an open S edge, once rows 1
+// (and 2) exist.  A macro rather than a function or lambda: every operand stays a
 // plain local, so the whole window lives in registers.
 #define MLB_ROW(V, r, RAWN, S, C, N, DC, DN, LOADNEXT, EMIT, EMIT0)                                 \
     do {                                                                                          \
         derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
-        take_coef<IMPL>(RAWN, DN);                                                                \
+        take_coef<IMPL, COMP>(RAWN, DN);                                                          \
         exchange<EDGE>(DN, N);                                                                    \
+        if (COMP) N.el = DN.el;                                                                   \
         if (MASK) mask_row(RAWN.m, N);                                                            \
         LOADNEXT;                                                                                 \
-        const float lE = link_right(DC.h, DC.eta, C), lN = link(DC.h, DC.eta, N.h, N.eta);        \
-        const float lNE = link_right(DC.h, DC.eta, N), lNW = link_left(DC.h, DC.eta, N);          \
-        float en, qxn, qyn;                                                                       \
+        const float lE = COMP ? link_right_c(DC.h, DC.eta, DC.el, C) : link_right(DC.h, DC.eta, C); \
+        const float lN = COMP ? link_c(DC.h, DC.eta, DC.el, N.h, N.eta, N.el)                    \
+                              : link(DC.h, DC.eta, N.h, N.eta);                                   \
+        const float lNE = COMP ? link_right_c(DC.h, DC.eta, DC.el, N) : link_right(DC.h, DC.eta, N); \
+        const float lNW = COMP ? link_left_c(DC.h, DC.eta, DC.el, N) : link_left(DC.h, DC.eta, N); \
+        float en, enl = 0.0f, qxn, qyn;                                                           \
         if (EDGE) {                                                                               \
             float P[9], oy[9];                                                                    \
             P[1] = -from_left(lE); P[2] = -V.cy.cNEl; P[3] = -V.cy.cN; P[4] = -V.cy.cNWr;         \
@@ -466,13 +506,14 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             P[6] = bb6_ ? 0.0f : P[6];     oy[6] = bb6_ ? DC.o[2] : oy[6];                        \
             P[7] = bb7_ ? 0.0f : P[7];     oy[7] = bb7_ ? DC.o[3] : oy[7];                        \
             P[8] = bb8_ ? 0.0f : P[8];     oy[8] = bb8_ ? DC.o[4] : oy[8];                        \
-            update_edge<IMPL>(B, DC, P, oy, en, qxn, qyn);                                        \
+            update_edge<IMPL, COMP>(B, DC, P, oy, en, enl, qxn, qyn);                             \
         } else {                                                                                  \
-            update_fast<IMPL>(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, qxn, qyn);              \
+            update_fast<IMPL, COMP>(B, DC, S, C, N, V.cy, lE, lN, lNE, lNW, en, enl, qxn, qyn);   \
         }                                                                                         \
         carry_from<EDGE>(lN, lNE, lNW, V.cy); /* for row r+1 */                                   \
         /* keep the row's arithmetic ahead of the ownership branch of EMIT */                     \
         asm volatile("" ::"v"(en), "v"(qxn), "v"(qyn));                                           \
+        if (COMP) asm volatile("" ::"v"(enl));                                                    \
         bool emit = true;                                                                         \
         if (EDGE) {                                                                               \
             /* pre-override values of the x-neighbours (inward normals of W / E) */               \
@@ -487,7 +528,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             const bool onS = !per_y && (r) == 0, onN = !per_y && (r) == ny - 1;                   \
             const bool wall = L.wall_x || (onS && L.kS == EDGE_WALL) || (onN && L.kN == EDGE_WALL) || \
                               (MASK && C.mk == NODE_WALL);                                        \
-            float fe = en, fx = qxn, fy = qyn;                                                    \
+            float fe = en, fx = qxn, fy = qyn, fl = enl;                                          \
             if (wall) {                                                                           \
                 fx = 0.0f; fy = 0.0f;                                                             \
             } else {                                                                              \
@@ -505,15 +546,19 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                     const float xy = L.two ? __builtin_fmaf(2.0f, n1y, -n2y) : n1y;               \
                     const bool dep = oN ? L.kN == EDGE_DEPTH : L.dep_x;                           \
                     if (dep) {                                                                    \
-                        fe = (float)((oN ? V.hbN : V.hb_x) - (double)DC.H); fx = xx; fy = xy;     \
+                        const double dv = (oN ? V.hbN : V.hb_x) - (double)DC.H;                   \
+                        fe = (float)dv; fx = xx; fy = xy;                                         \
+                        if (COMP) fl = (float)(dv - (double)fe);                                  \
                     } else {                                                                      \
-                        fe = xe; fx = oN ? L.bqxN : L.bqx_x; fy = oN ? L.bqyN : L.bqy_x;          \
+                        /* the extrapolated surface is taken in FP32 */                           \
+                        fe = xe; fx = oN ? L.bqxN : L.bqx_x; fy = oN ? L.bqyN : L.bqy_x; fl = 0.0f; \
                     }                                                                             \
                 }                                                                                 \
             }                                                                                     \
             if (L.open_s) {                                                                       \
                 if ((r) == 0) { /* row 0 waits for rows 1 (and 2) of this step */                 \
                     V.pe = en; V.pqx = qxn; V.pqy = qyn; V.pH = DC.H; V.poqx = DC.q0x; V.poqy = DC.q0y; \
+                    V.pl = enl;                                                                   \
                     emit = false;                                                                 \
                 } else if ((r) == extrap) {                                                       \
                     const float m1e = L.two ? V.h1e : en, m1x = L.two ? V.h1x : qxn;              \
@@ -522,20 +567,24 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                     const float vx = L.two ? __builtin_fmaf(2.0f, m1x, -qxn) : m1x;               \
                     const float vy = L.two ? __builtin_fmaf(2.0f, m1y, -qyn) : m1y;               \
                     /* row-0 lanes are S-edge nodes or wall corners */                            \
-                    float ge = V.pe, gx = V.pqx, gy = V.pqy;                                      \
+                    float ge = V.pe, gx = V.pqx, gy = V.pqy, gl = V.pl;                           \
                     if (L.wall_x) { gx = 0.0f; gy = 0.0f; }                                       \
-                    else if (L.kS == EDGE_DEPTH) { ge = (float)(V.hbS - (double)V.pH); gx = vx; gy = vy; } \
-                    else { ge = ve; gx = L.bqxS; gy = L.bqyS; }                                   \
-                    EMIT0(ge, gx, gy);                                                            \
+                    else if (L.kS == EDGE_DEPTH) {                                                \
+                        const double dv = V.hbS - (double)V.pH;                                   \
+                        ge = (float)dv; gx = vx; gy = vy;                                         \
+                        if (COMP) gl = (float)(dv - (double)ge);                                  \
+                    }                                                                             \
+                    else { ge = ve; gx = L.bqxS; gy = L.bqyS; gl = 0.0f; }                        \
+                    EMIT0(ge, gx, gy, gl);                                                        \
                 }                                                                                 \
             }                                                                                     \
             V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                          \
             V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                            \
-            en = fe; qxn = fx; qyn = fy;                                                          \
+            en = fe; qxn = fx; qyn = fy; enl = fl;                                                \
             /* SOLID nodes keep their values: both buffers hold them already */                   \
             if (MASK && C.mk == NODE_SOLID) emit = false;                                         \
         }                                                                                         \
-        if (emit) { EMIT(en, qxn, qyn, DC); }                                                         \
+        if (emit) { EMIT(en, qxn, qyn, DC, enl); }                                                \
     } while (0)
 
 #define MLB_NOTHING(...) do { } while (0)
@@ -543,7 +592,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 // ------------------------------------------------------------------ one step per pass
 // MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only).
 // IMPL: the basin uses the implicit link depth (coefficient planes).
-template <bool EDGE, bool DIAG, bool FRIC, bool MASK, bool IMPL>
+// COMP: the surface is a compensated pair (eta plane plus a low-part plane).
+template <bool EDGE, bool DIAG, bool FRIC, bool MASK, bool IMPL, bool COMP>
 __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int rd, int64_t step,
                                          double* __restrict__ part)
 {
@@ -563,12 +613,14 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
     gcu8* __restrict__ MK = (gcu8*)B.mask;
     const Coef K = {(const gfloat*)B.cw, (const gfloat*)B.ckx, (const gfloat*)B.cky};
+    const gfloat* __restrict__ EL0 = (const gfloat*)B.etal[rd];
+    gfloat* __restrict__ EL1 = (gfloat*)B.etal[wr];
     Stage V;
     stage_setup<EDGE>(B, L, (double)(step + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
-#define MLB_LD(row) load_raw<MASK, IMPL>(E0, QX0, QY0, HH, MK, K, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<MASK, IMPL, COMP>(E0, QX0, QY0, HH, EL0, MK, K, (uint32_t)(wrap_or_clamp(min((row), r1), ny, per_y) * ld) + (uint32_t)L.xl)
     // Software pipeline: a row's raw values are loaded three rows before they
     // are derived.  Raw slots, window rows and derived nodes rotate with
     // period 3, so the loop is unrolled by 3 and the rotation is a renaming
@@ -579,33 +631,37 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     {
         const Raw w = MLB_LD(r0 - 1);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d0);
-        take_coef<IMPL>(w, d0);
+        take_coef<IMPL, COMP>(w, d0);
         exchange<EDGE>(d0, R0);
+        if (COMP) R0.el = d0.el;
         if (MASK) mask_row(w.m, R0);
     }
     {
         const Raw w = MLB_LD(r0);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, d1);
-        take_coef<IMPL>(w, d1);
+        take_coef<IMPL, COMP>(w, d1);
         exchange<EDGE>(d1, R1);
+        if (COMP) R1.el = d1.el;
         if (MASK) mask_row(w.m, R1);
     }
-    carry_init<EDGE>(d0, R1, V.cy);
+    carry_init<EDGE, COMP>(d0, R1, V.cy);
     int r = r0;
-#define MLB_STORE1(en_, qx_, qy_, D_)                                                             \
+#define MLB_STORE1(en_, qx_, qy_, D_, el_)                                                        \
     do {                                                                                          \
         if (L.own_col && r >= T.yo && r < r1) {                                                   \
             const uint32_t o = ((uint32_t)(r * ld) + (uint32_t)L.x) * 4u;                         \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
-            if (DIAG) account(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y);                         \
+            if (COMP) stf(EL1, o, el_);                                                           \
+            if (DIAG) account(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y, COMP ? el_ : 0.0f);      \
         }                                                                                         \
     } while (0)
-#define MLB_STORE0(ge_, gx_, gy_)                                                                 \
+#define MLB_STORE0(ge_, gx_, gy_, gl_)                                                            \
     do {                                                                                          \
         if (L.own_col) {                                                                          \
             const uint32_t o = (uint32_t)L.x * 4u;                                                \
             stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
-            if (DIAG) account(sums, ge_, gx_, gy_, V.pH, V.poqx, V.poqy);                         \
+            if (COMP) stf(EL1, o, gl_);                                                           \
+            if (DIAG) account(sums, ge_, gx_, gy_, V.pH, V.poqx, V.poqy, COMP ? gl_ : 0.0f);      \
         }                                                                                         \
     } while (0)
     // single-exit counted loop: the tile's rows are rounded up to a multiple
@@ -653,6 +709,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
     constexpr bool MASK = false;   // masked grids run one step per pass
     constexpr bool IMPL = false;   // so do grids with the implicit link depth
+    constexpr bool COMP = false;   // and grids with a compensated surface
     const Coef K = {nullptr, nullptr, nullptr};
     const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
@@ -671,7 +728,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
-#define MLB_LD(row) load_raw<false, false>(E0, QX0, QY0, HH, nullptr, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<false, false, false>(E0, QX0, QY0, HH, nullptr, nullptr, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
     // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
     Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
     Node a0, a1, a2;
@@ -686,16 +743,16 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a1);
         exchange<EDGE>(a1, A1);
     }
-    carry_init<EDGE>(a0, A1, SA.cy);
+    carry_init<EDGE, false>(a0, A1, SA.cy);
     Raw q0, q1, q2;               // level n+1 rows handed from A to B
     Node b0, b1, b2;
     Row B0, B1, B2;
     int ra = r0 - 1;
-#define MLB_Q0(en_, qx_, qy_, D_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; } while (0)
-#define MLB_Q1(en_, qx_, qy_, D_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; } while (0)
-#define MLB_Q2(en_, qx_, qy_, D_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; } while (0)
+#define MLB_Q0(en_, qx_, qy_, D_, el_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; } while (0)
+#define MLB_Q1(en_, qx_, qy_, D_, el_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; } while (0)
+#define MLB_Q2(en_, qx_, qy_, D_, el_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; } while (0)
     // A's deferred row 0 (open S edge: r0 == 0, so its slot is q1)
-#define MLB_A0(ge_, gx_, gy_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; } while (0)
+#define MLB_A0(ge_, gx_, gy_, gl_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; } while (0)
     MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0-1
     ++ra;
     // B's window row r0-1
@@ -710,17 +767,17 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     // B's window row r0 (final now) and its links towards row r0-1
     derive<FRIC>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
     exchange<EDGE>(b1, B1);
-    carry_init<EDGE>(b0, B1, SB.cy);
+    carry_init<EDGE, false>(b0, B1, SB.cy);
 
     int rb = r0;
-#define MLB_STORE2(en_, qx_, qy_, D_)                                                              \
+#define MLB_STORE2(en_, qx_, qy_, D_, el_)                                                         \
     do {                                                                                          \
         if (L.own_col && rb >= T.yo && rb < r1) {                                                 \
             const uint32_t o = ((uint32_t)(rb * ld) + (uint32_t)L.x) * 4u;                        \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
         }                                                                                         \
     } while (0)
-#define MLB_STORE20(ge_, gx_, gy_)                                                                \
+#define MLB_STORE20(ge_, gx_, gy_, gl_)                                                           \
     do {                                                                                          \
         if (L.own_col) {                                                                          \
             const uint32_t o = (uint32_t)L.x * 4u;                                                \
@@ -769,7 +826,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 // basin's step counter at buffer rd; the basin's first tile advances it.
 // MASKED: the tile list may hold TILE_MASKED tiles (a separate kernel, so
 // that grids without a mask keep the smaller register budget).
-template <int KIND, bool DIAG, bool MASKED, bool IMPL, class StepRead>
+template <int KIND, bool DIAG, bool MASKED, bool IMPL, bool COMP, class StepRead>
 __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles,
                                           int t, int parity, double* __restrict__ partials, StepRead step_at)
 {
@@ -789,13 +846,13 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         double* part = partials + (size_t)t * kPartials;
         const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         if (B.cfr != 0.0f) {
-            if (masked) run_tile<true, DIAG, true, MASKED, IMPL>(B, T, rd, step, part);
-            else if (edge) run_tile<true, DIAG, true, false, IMPL>(B, T, rd, step, part);
-            else run_tile<false, DIAG, true, false, IMPL>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, true, MASKED, IMPL, COMP>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, true, false, IMPL, COMP>(B, T, rd, step, part);
+            else run_tile<false, DIAG, true, false, IMPL, COMP>(B, T, rd, step, part);
         } else {
-            if (masked) run_tile<true, DIAG, false, MASKED, IMPL>(B, T, rd, step, part);
-            else if (edge) run_tile<true, DIAG, false, false, IMPL>(B, T, rd, step, part);
-            else run_tile<false, DIAG, false, false, IMPL>(B, T, rd, step, part);
+            if (masked) run_tile<true, DIAG, false, MASKED, IMPL, COMP>(B, T, rd, step, part);
+            else if (edge) run_tile<true, DIAG, false, false, IMPL, COMP>(B, T, rd, step, part);
+            else run_tile<false, DIAG, false, false, IMPL, COMP>(B, T, rd, step, part);
         }
     } else {
         // a two-step tile needs the boundary logic when stage A's rows
@@ -828,15 +885,16 @@ struct CoherentStep {
 // One pass of one step.  One wave per tile, tiles in list order (largest
 // basins first): the hardware dispatcher hands out workgroups in index
 // order, so the list is consumed as a queue without a software loop.
-// (the checked step of the implicit link depth needs more than 128 VGPRs)
-template <bool DIAG, bool MASKED, bool IMPL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((DIAG && IMPL) ? 3 : 4)))
+// (the checked step of the implicit link depth or of a compensated surface
+// needs more than 128 VGPRs)
+template <bool DIAG, bool MASKED, bool IMPL, bool COMP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((DIAG && (IMPL || COMP)) ? 3 : 4)))
 void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                  int parity, double* __restrict__ partials)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<1, DIAG, MASKED, IMPL>(basins, tiles, t, parity, partials, PlainStep{});
+    pass_tile<1, DIAG, MASKED, IMPL, COMP>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
 // One pass of two steps, over tiles of 60-column strips.
@@ -846,7 +904,7 @@ void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, false, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -868,7 +926,8 @@ void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __res
     __syncthreads();
     if (abort_flag) return;
     for (int p = 0; p < npasses; ++p) {
-        if (t < ntiles) pass_tile<KIND, false, MASKED, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
+        if (t < ntiles)
+            pass_tile<KIND, false, MASKED, false, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
         __threadfence();   // release: this wave's stores, device-wide
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -911,11 +970,13 @@ __global__ __launch_bounds__(kBlock) void reduce_state_kernel(const BasinDev* __
             const size_t o = (size_t)r * B.ld + x;
             if (B.mask && B.mask[o] == NODE_SOLID) continue;   // not part of the water
             const float en = B.eta[cur][o], a = B.qx[cur][o], b = B.qy[cur][o];
+            const float el = B.etal[cur] ? B.etal[cur][o] : 0.0f;   // compensated surface
             const double h = (double)B.H[o] + (double)en;
             if (__builtin_isfinite(en) && __builtin_isfinite(a) && __builtin_isfinite(b) && h > 0.0) {
                 const double da = (double)a - (double)B.qx[prev][o];
                 const double db = (double)b - (double)B.qy[prev][o];
                 s_eta += en;
+                s_eta += el;
                 s_dq += da * da + db * db;
                 const double q2 = (double)a * a + (double)b * b;
                 s_q += q2;
@@ -990,26 +1051,26 @@ int step_occupancy(int diag)
 {
     int n = 0;
     if (diag)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true, false, false>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<true, false, false, false>, kBlock, 0);
     else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false, false, false>, kBlock, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<false, false, false, false>, kBlock, 0);
     return n > 0 ? n : 1;
 }
 
-template <bool DIAG, bool MASKED, bool IMPL>
+template <bool DIAG, bool MASKED, bool IMPL, bool COMP>
 static void launch_one(dim3 grid, unsigned dyn_lds, hipStream_t s, const BasinDev* d_basins, const TileDev* d_tiles,
                        int ntiles, int parity, double* d_partials)
 {
-    hipLaunchKernelGGL((step_kernel<DIAG, MASKED, IMPL>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
+    hipLaunchKernelGGL((step_kernel<DIAG, MASKED, IMPL, COMP>), grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles,
                        ntiles, parity, d_partials);
 }
 
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
-                       double* d_partials, int diag, int tblock, int masked, int implicit, unsigned dyn_lds,
-                       hipStream_t s)
+                       double* d_partials, int diag, int tblock, int masked, int implicit, int comp,
+                       unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1 && (tblock != 2 || diag || masked || implicit)) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag || masked || implicit || comp)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (tblock == 2) {
@@ -1017,12 +1078,18 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
         return hipGetLastError();
     }
     using L = void (*)(dim3, unsigned, hipStream_t, const BasinDev*, const TileDev*, int, int, double*);
-    static const L table[8] = {launch_one<false, false, false>, launch_one<false, false, true>,
-                               launch_one<false, true, false>,  launch_one<false, true, true>,
-                               launch_one<true, false, false>,  launch_one<true, false, true>,
-                               launch_one<true, true, false>,   launch_one<true, true, true>};
-    table[(diag ? 4 : 0) + (masked ? 2 : 0) + (implicit ? 1 : 0)](grid, dyn_lds, s, d_basins, d_tiles, ntiles,
-                                                                  parity, d_partials);
+    static const L table[16] = {
+        launch_one<false, false, false, false>, launch_one<false, false, false, true>,
+        launch_one<false, false, true, false>,  launch_one<false, false, true, true>,
+        launch_one<false, true, false, false>,  launch_one<false, true, false, true>,
+        launch_one<false, true, true, false>,   launch_one<false, true, true, true>,
+        launch_one<true, false, false, false>,  launch_one<true, false, false, true>,
+        launch_one<true, false, true, false>,   launch_one<true, false, true, true>,
+        launch_one<true, true, false, false>,   launch_one<true, true, false, true>,
+        launch_one<true, true, true, false>,    launch_one<true, true, true, true>};
+    table[(diag ? 8 : 0) + (masked ? 4 : 0) + (implicit ? 2 : 0) + (comp ? 1 : 0)](grid, dyn_lds, s, d_basins,
+                                                                                   d_tiles, ntiles, parity,
+                                                                                   d_partials);
     return hipGetLastError();
 }
 

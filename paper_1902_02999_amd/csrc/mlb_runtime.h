@@ -66,6 +66,7 @@ struct Plan {
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool masked = false;       // some basin has a node mask: one-step passes, masked kernel
     bool implicit = false;     // the basins use the implicit link depth: one-step passes
+    bool comp = false;         // the basins have a compensated surface: one-step passes
     bool built = false;
 
     void release()
@@ -119,6 +120,7 @@ struct mlb_grid {
     std::vector<uint8_t> hmask;  // host copy (pitch ld), empty without a mask
     int hbar = MLB_HBAR_SEMI_IMPLICIT;
     float* dcoef = nullptr;    // implicit link depth: 3 planes (1/(1+kappa), kappa_x, kappa_y)
+    float* etal = nullptr;     // compensated surface: low part of eta, 2 planes (one per buffer)
     int cur = 0;
     int64_t step = 0;
     double e = 0, dt = 0, sumH = 0, Hmax = 0;

@@ -516,6 +516,7 @@ mlb_status mlb_net_infer(mlb_net* n, mlb_grid* g)
     if (!n) return fail(MLB_E_INVAL, "net is NULL");
     CHK(check_grid(n, g));
     if (g->dmask) return fail(MLB_E_STATE, "the warm start covers grids without a node mask");
+    if (g->etal) return fail(MLB_E_STATE, "the warm start covers grids with an FP32 surface");
     HIPCHK(hipSetDevice(n->ctx->device));
     hipStream_t s = n->ctx->stream;
     HIPCHK(nn::features(g->H, g->p.nx, g->p.ny, g->ld, n->norm.in_mean, n->norm.in_std, g->tx, g->ty, g->cb,
@@ -677,6 +678,7 @@ mlb_status mlb_warm_start_run(mlb_grid* g, mlb_net* n, double tol, int64_t max_s
     if (check_every < 1 || max_steps < 2 || !(tol >= 0)) return fail(MLB_E_INVAL, "bad tol / max_steps / check_every");
     CHK(check_grid(n, g));
     if (g->dmask) return fail(MLB_E_STATE, "the warm start covers grids without a node mask");
+    if (g->etal) return fail(MLB_E_STATE, "the warm start covers grids with an FP32 surface");
     HIPCHK(hipSetDevice(n->ctx->device));
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = n->ctx->stream;

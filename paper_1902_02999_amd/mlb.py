@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmlb.so")
 WALL, PERIODIC, DEPTH, DISCHARGE = 0, 1, 2, 3
 NODE_FLUID, NODE_WALL, NODE_SOLID = 0, 1, 2   # MLB_NODE_*
 HBAR_SEMI_IMPLICIT, HBAR_IMPLICIT = 0, 1       # MLB_HBAR_*
+SURFACE_FP32, SURFACE_COMPENSATED = 0, 1       # MLB_SURFACE_*
 W, E, S, N = 0, 1, 2, 3
 
 STATUS = {0: "MLB_OK", -1: "MLB_E_INVAL", -2: "MLB_E_NOMEM", -3: "MLB_E_DEVICE",
@@ -112,6 +113,7 @@ SIGNATURES = {
     "mlb_set_bathymetry": (C.c_int, [_VP, _DP, C.c_int64]),
     "mlb_set_mask": (C.c_int, [_VP, C.POINTER(C.c_uint8), C.c_int64]),
     "mlb_set_hbar": (C.c_int, [_VP, C.c_int32]),
+    "mlb_set_surface": (C.c_int, [_VP, C.c_int32]),
     "mlb_set_wind": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_wind_stress": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_chezy": (C.c_int, [_VP, C.c_double]),
@@ -290,6 +292,11 @@ class Grid:
         """Link depth: Eq. h-bar (False, default) or the implicit new-time form (True)."""
         _check(lib().mlb_set_hbar(self.h, HBAR_IMPLICIT if implicit else HBAR_SEMI_IMPLICIT), "mlb_set_hbar")
 
+    def set_surface(self, compensated: bool):
+        """Surface perturbation in FP32 (False, default) or as a compensated FP32 pair (True)."""
+        _check(lib().mlb_set_surface(self.h, SURFACE_COMPENSATED if compensated else SURFACE_FP32),
+               "mlb_set_surface")
+
     def set_wind(self, uwx, uwy):
         _check(lib().mlb_set_wind(self.h, uwx, uwy), "mlb_set_wind")
 
@@ -428,6 +435,8 @@ def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
         g.set_mask(spec.kind)
     if getattr(spec, "hbar_implicit", False):
         g.set_hbar(True)
+    if getattr(spec, "compensated", False):
+        g.set_surface(True)
     if spec.wind_speed is not None:
         g.set_wind(*spec.wind_speed)
     if spec.wind_stress is not None:

@@ -45,6 +45,7 @@ class Spec:
     qy0: Optional[np.ndarray] = None
     kind: Optional[np.ndarray] = None    # node kinds [ny][nx] (uint8), None: all FLUID
     hbar_implicit: bool = False          # link depth with the node's new-time depth
+    compensated: bool = False            # GPU: surface stored as a compensated FP32 pair
 
     def __post_init__(self):
         self.zb = np.ascontiguousarray(self.zb, np.float64).reshape(self.ny, self.nx)
