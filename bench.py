@@ -290,7 +290,7 @@ def bench_geometry(args, ctx, copy_gbps):
     d = g.diag()
     opts = g.exec_opts().as_dict()
     g.close()
-    tb = 1 if spec.kind is not None else opts["tblock"]
+    tb = opts["tblock"]
     launch_s = tb * ev_ms / 1e3 / args.steps
     bpl = (BYTES_PER_LUP + kind_bytes) * water
     gbs = bpl / launch_s / 1e9

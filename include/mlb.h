@@ -145,8 +145,9 @@ enum { MLB_NODE_FLUID = 0, MLB_NODE_WALL = 1, MLB_NODE_SOLID = 2 };
  * still need a positive H (its value is never used).  MLB_E_INVAL for a kind
  * above SOLID, for a non-FLUID node within extrap_order nodes of an open
  * (DEPTH / DISCHARGE) edge, or when every node is SOLID.  The current state
- * is copied into the second buffer set, so the next residual is 0.  Masked
- * grids run one step per pass (tblock 2 is accepted and runs as 1).
+ * is copied into the second buffer set, so the next residual is 0.  Tiles
+ * whose window holds WALL or SOLID nodes run a masked kernel variant (one or
+ * two steps per pass); tiles owning only SOLID nodes are not launched.
  * MLB_E_STATE if the grid belongs to a live batch. */
 mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 

@@ -83,23 +83,25 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     return b;
 }
 
-// Mask classification of a one-step tile: TILE_MASKED when its window
-// (columns x0-1 .. x0+62, rows y0-1 .. y0+rows, wrapped or clamped as the
-// kernel loads them) holds a WALL or SOLID node; false when every node it
-// owns is SOLID (the tile has nothing to write and is left out).
-bool classify_tile(const mlb_grid* g, TileDev& t)
+// Mask classification of a tile: TILE_MASKED when its window holds a WALL or
+// SOLID node; false when every node it owns is SOLID (the tile has nothing
+// to write and is left out).  The window is what the kernel loads, wrapped or
+// clamped: one-step tiles columns x0-1 .. x0+62 and rows y0-1 .. y0+rows,
+// two-step tiles columns x0-2 .. x0+61 and rows y0-2 .. y0+rows+1.
+bool classify_tile(const mlb_grid* g, TileDev& t, int strip)
 {
+    const int halo = strip == kStripOut2 ? 2 : 1;
     const int nx = g->p.nx, ny = g->p.ny, ld = g->ld;
     const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
     auto wrap = [](int v, int n, bool per) { return per ? ((v % n) + n) % n : std::min(std::max(v, 0), n - 1); };
     const uint8_t* m = g->hmask.data();
     bool any = false, owned_water = false;
-    for (int r = t.y0 - 1; r <= t.y0 + t.rows; ++r) {
+    for (int r = t.y0 - halo; r <= t.y0 + t.rows + halo - 1; ++r) {
         const int rr = wrap(r, ny, py);
-        for (int x = t.x0 - 1; x <= t.x0 + kStripOut; ++x) {
+        for (int x = t.x0 - halo; x < t.x0 - halo + kWave; ++x) {
             const uint8_t k = m[(size_t)rr * ld + wrap(x, nx, px)];
             any |= k != NODE_FLUID;
-            const bool own = x >= t.x0 && x < t.x0 + kStripOut && x >= t.xo && x < nx && r >= t.yo &&
+            const bool own = x >= t.x0 && x < t.x0 + strip && x >= t.xo && x < nx && r >= t.yo &&
                              r < t.y0 + t.rows;
             owned_water |= own && k != NODE_SOLID;
         }
@@ -114,7 +116,7 @@ bool classify_tile(const mlb_grid* g, TileDev& t)
 // the same tile; it then stores only what it owns.  Two-step tiles never
 // start at row 1: their first stage would then compute row 0 of an open S
 // edge, which waits for rows 1 and 2 (such a tile starts at row 0 instead).
-// With a mask (one-step tiles only) tiles are classified by classify_tile.
+// With a mask, tiles are classified by classify_tile.
 void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out, int strip)
 {
     // List order = dispatch order: row band by row band, so one workgroup's
@@ -135,7 +137,7 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
             t.yo = yo;
             t.y0 = y0;
             t.rows = yend - y0;
-            if (!g->hmask.empty() && strip == kStripOut && !classify_tile(g, t)) continue;
+            if (!g->hmask.empty() && !classify_tile(g, t, strip)) continue;
             out.push_back(t);
         }
     }
@@ -191,8 +193,8 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.ht.clear();
         g->plan.ht2.clear();
         make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
-        // masked grids and the implicit link depth run one step per pass
-        const bool one = g->dmask || g->hbar == MLB_HBAR_IMPLICIT || g->etal;
+        // the implicit link depth and the compensated surface run one step per pass
+        const bool one = g->hbar == MLB_HBAR_IMPLICIT || g->etal;
         if (g->opts.tblock == 2 && !one) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
@@ -1016,7 +1018,7 @@ static mlb_status batch_plan(mlb_batch* b)
         make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
         d.first_tile2 = (int)b->plan.ht2.size();
-        if (b->opts.tblock == 2 && !masked && !implicit && !comp)
+        if (b->opts.tblock == 2 && !implicit && !comp)
             make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
@@ -1238,8 +1240,8 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
-    bool masked = false;   // masked grids and the implicit link depth run one step per pass
-    for (auto* g : gs) masked |= g->dmask != nullptr || g->hbar == MLB_HBAR_IMPLICIT || g->etal != nullptr;
+    bool one = false;   // the implicit link depth and the compensated surface run one step per pass
+    for (auto* g : gs) one |= g->hbar == MLB_HBAR_IMPLICIT || g->etal != nullptr;
     for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))
@@ -1247,7 +1249,7 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
         for (int cap : kTuneCaps) {
             // persistent launches need every tile resident: no workgroup cap
             if (ps && (cap != 0 || !fits_persistent(c, gs, tr, tb))) continue;
-            if (masked && tb == 2) continue;
+            if (one && tb == 2) continue;
             mlb_exec_opts o = base;
             o.persistent = ps;
             o.tblock = tb;

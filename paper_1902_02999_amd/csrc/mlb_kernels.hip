@@ -80,6 +80,7 @@ struct Node {
     float H, q0x, q0y;     // the node's stored H and old discharge
     float iw, ikx, iky;    // implicit link depth: 1/(1+kappa), kappa_x, kappa_y
     float el;              // compensated surface: low part of eta
+    int mk;                // masked tiles: node kind
 };
 
 // Node quantities from the old state (Eqs. SWE-force, bed-stress, feq-full).
@@ -474,7 +475,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
         take_coef<IMPL, COMP>(RAWN, DN);                                                          \
         exchange<EDGE>(DN, N);                                                                    \
         if (COMP) N.el = DN.el;                                                                   \
-        if (MASK) mask_row(RAWN.m, N);                                                            \
+        if (MASK) { mask_row(RAWN.m, N); DN.mk = RAWN.m; }                                        \
         LOADNEXT;                                                                                 \
         const float lE = COMP ? link_right_c(DC.h, DC.eta, DC.el, C) : link_right(DC.h, DC.eta, C); \
         const float lN = COMP ? link_c(DC.h, DC.eta, DC.el, N.h, N.eta, N.el)                    \
@@ -581,8 +582,6 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                          \
             V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                            \
             en = fe; qxn = fx; qyn = fy; enl = fl;                                                \
-            /* SOLID nodes keep their values: both buffers hold them already */                   \
-            if (MASK && C.mk == NODE_SOLID) emit = false;                                         \
         }                                                                                         \
         if (emit) { EMIT(en, qxn, qyn, DC, enl); }                                                \
     } while (0)
@@ -634,7 +633,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
         take_coef<IMPL, COMP>(w, d0);
         exchange<EDGE>(d0, R0);
         if (COMP) R0.el = d0.el;
-        if (MASK) mask_row(w.m, R0);
+        if (MASK) { mask_row(w.m, R0); d0.mk = w.m; }
     }
     {
         const Raw w = MLB_LD(r0);
@@ -642,13 +641,14 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
         take_coef<IMPL, COMP>(w, d1);
         exchange<EDGE>(d1, R1);
         if (COMP) R1.el = d1.el;
-        if (MASK) mask_row(w.m, R1);
+        if (MASK) { mask_row(w.m, R1); d1.mk = w.m; }
     }
     carry_init<EDGE, COMP>(d0, R1, V.cy);
     int r = r0;
+// SOLID nodes are never stored: both buffers hold their values already
 #define MLB_STORE1(en_, qx_, qy_, D_, el_)                                                        \
     do {                                                                                          \
-        if (L.own_col && r >= T.yo && r < r1) {                                                   \
+        if (L.own_col && r >= T.yo && r < r1 && !(MASK && D_.mk == NODE_SOLID)) {                 \
             const uint32_t o = ((uint32_t)(r * ld) + (uint32_t)L.x) * 4u;                         \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
             if (COMP) stf(EL1, o, el_);                                                           \
@@ -702,14 +702,17 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // level n+2 for rows r0 .. r1-1 from the queue and stores lanes 2..61.
 // Queue slot of A's row ra: (ra - r0 + 1) mod 3.  A's row 0 of an open S edge
 // is final only after A's row `extrap`, so B starts once A has done row r0+2.
-template <bool EDGE, bool FRIC>
+// MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only); the
+// kinds travel with stage A's rows through the queue to stage B.
+template <bool EDGE, bool FRIC, bool MASK>
 __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step)
 {
+    static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
-    constexpr bool MASK = false;   // masked grids run one step per pass
-    constexpr bool IMPL = false;   // so do grids with the implicit link depth
-    constexpr bool COMP = false;   // and grids with a compensated surface
+    constexpr bool IMPL = false;   // grids with the implicit link depth run one step per pass
+    constexpr bool COMP = false;   // so do grids with a compensated surface
+    gcu8* __restrict__ MK = (gcu8*)B.mask;
     const Coef K = {nullptr, nullptr, nullptr};
     const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
@@ -728,7 +731,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
-#define MLB_LD(row) load_raw<false, false, false>(E0, QX0, QY0, HH, nullptr, nullptr, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<MASK, false, false>(E0, QX0, QY0, HH, nullptr, MK, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
     // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
     Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
     Node a0, a1, a2;
@@ -737,27 +740,33 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         const Raw w = MLB_LD(r0 - 2);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a0);
         exchange<EDGE>(a0, A0);
+        if (MASK) { mask_row(w.m, A0); a0.mk = w.m; }
     }
     {
         const Raw w = MLB_LD(r0 - 1);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a1);
         exchange<EDGE>(a1, A1);
+        if (MASK) { mask_row(w.m, A1); a1.mk = w.m; }
     }
     carry_init<EDGE, false>(a0, A1, SA.cy);
     Raw q0, q1, q2;               // level n+1 rows handed from A to B
     Node b0, b1, b2;
     Row B0, B1, B2;
     int ra = r0 - 1;
-#define MLB_Q0(en_, qx_, qy_, D_, el_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; } while (0)
-#define MLB_Q1(en_, qx_, qy_, D_, el_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; } while (0)
-#define MLB_Q2(en_, qx_, qy_, D_, el_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; } while (0)
-    // A's deferred row 0 (open S edge: r0 == 0, so its slot is q1)
-#define MLB_A0(ge_, gx_, gy_, gl_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; } while (0)
+    // every lane's row goes into the queue, SOLID nodes included (their values
+    // only meet bounced links, and stage B does not store them)
+#define MLB_Q0(en_, qx_, qy_, D_, el_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; if (MASK) q0.m = D_.mk; } while (0)
+#define MLB_Q1(en_, qx_, qy_, D_, el_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; if (MASK) q1.m = D_.mk; } while (0)
+#define MLB_Q2(en_, qx_, qy_, D_, el_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; if (MASK) q2.m = D_.mk; } while (0)
+    // A's deferred row 0 (open S edge: r0 == 0, so its slot is q1; nodes next
+    // to an open edge are FLUID)
+#define MLB_A0(ge_, gx_, gy_, gl_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; if (MASK) q1.m = NODE_FLUID; } while (0)
     MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0-1
     ++ra;
     // B's window row r0-1
     derive<FRIC>(B, q0.eta, q0.qx, q0.qy, q0.H, b0);
     exchange<EDGE>(b0, B0);
+    if (MASK) { mask_row(q0.m, B0); b0.mk = q0.m; }
     MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_A0);   // row r0
     ++ra;
     MLB_ROW(SA, ra, wc, A2, A0, A1, a0, a1, wc = MLB_LD(ra + 4), MLB_Q2, MLB_A0);   // row r0+1
@@ -767,12 +776,13 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     // B's window row r0 (final now) and its links towards row r0-1
     derive<FRIC>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
     exchange<EDGE>(b1, B1);
+    if (MASK) { mask_row(q1.m, B1); b1.mk = q1.m; }
     carry_init<EDGE, false>(b0, B1, SB.cy);
 
     int rb = r0;
 #define MLB_STORE2(en_, qx_, qy_, D_, el_)                                                         \
     do {                                                                                          \
-        if (L.own_col && rb >= T.yo && rb < r1) {                                                 \
+        if (L.own_col && rb >= T.yo && rb < r1 && !(MASK && D_.mk == NODE_SOLID)) {               \
             const uint32_t o = ((uint32_t)(rb * ld) + (uint32_t)L.x) * 4u;                        \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
         }                                                                                         \
@@ -859,12 +869,15 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         // r0-1 .. r1 or lanes 1..62 touch an edge
         const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
                           (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
+        const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         if (B.cfr != 0.0f) {
-            if (edge) run_tile2<true, true>(B, T, rd, step);
-            else run_tile2<false, true>(B, T, rd, step);
+            if (masked) run_tile2<true, true, MASKED>(B, T, rd, step);
+            else if (edge) run_tile2<true, true, false>(B, T, rd, step);
+            else run_tile2<false, true, false>(B, T, rd, step);
         } else {
-            if (edge) run_tile2<true, false>(B, T, rd, step);
-            else run_tile2<false, false>(B, T, rd, step);
+            if (masked) run_tile2<true, false, MASKED>(B, T, rd, step);
+            else if (edge) run_tile2<true, false, false>(B, T, rd, step);
+            else run_tile2<false, false, false>(B, T, rd, step);
         }
     }
 }
@@ -897,14 +910,16 @@ void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict_
     pass_tile<1, DIAG, MASKED, IMPL, COMP>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
-// One pass of two steps, over tiles of 60-column strips.
+// One pass of two steps, over tiles of 60-column strips (MASKED: the list
+// may hold TILE_MASKED tiles).
+template <bool MASKED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                   int parity)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false, false, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, MASKED, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -1070,11 +1085,14 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
                        unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1 && (tblock != 2 || diag || masked || implicit || comp)) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag || implicit || comp)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (tblock == 2) {
-        hipLaunchKernelGGL(step2_kernel, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
+        if (masked)
+            hipLaunchKernelGGL(step2_kernel<true>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
+        else
+            hipLaunchKernelGGL(step2_kernel<false>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
         return hipGetLastError();
     }
     using L = void (*)(dim3, unsigned, hipStream_t, const BasinDev*, const TileDev*, int, int, double*);
@@ -1097,13 +1115,14 @@ hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, i
                              int npasses, int kind, int masked, SyncState* sync, uint64_t base, int spin_limit,
                              hipStream_t s)
 {
-    if (kind == 2 && masked) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     void* args[] = {(void*)&d_basins, (void*)&d_tiles, (void*)&ntiles, (void*)&parity0, (void*)&npasses,
                     (void*)&sync, (void*)&base, (void*)&spin_limit};
     if (kind == 2)
-        return hipLaunchCooperativeKernel((const void*)persistent_kernel<2, false>, grid, dim3(kBlock), args, 0, s);
+        return hipLaunchCooperativeKernel(masked ? (const void*)persistent_kernel<2, true>
+                                                 : (const void*)persistent_kernel<2, false>,
+                                          grid, dim3(kBlock), args, 0, s);
     if (masked)
         return hipLaunchCooperativeKernel((const void*)persistent_kernel<1, true>, grid, dim3(kBlock), args, 0, s);
     return hipLaunchCooperativeKernel((const void*)persistent_kernel<1, false>, grid, dim3(kBlock), args, 0, s);
@@ -1112,7 +1131,9 @@ hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, i
 int persistent_capacity(int kind, int masked, int ncu)
 {
     int n = 0;
-    if (kind == 2)
+    if (kind == 2 && masked)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<2, true>, kBlock, 0);
+    else if (kind == 2)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<2, false>, kBlock, 0);
     else if (masked)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, persistent_kernel<1, true>, kBlock, 0);

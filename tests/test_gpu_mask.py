@@ -196,7 +196,7 @@ def test_masked_batch_bitwise(ctx):
     for g, st in zip(gs, states):
         g.set_state(*st)
     b = mlb.Batch(ctx, gs)
-    b.set_exec_opts(tile_rows=12, tblock=2)   # runs one step per pass: the batch holds masks
+    b.set_exec_opts(tile_rows=12, tblock=2)   # two steps per pass, masked tiles included
     b.step(77)
     b.close()
     for g, want in zip(gs, singles):
@@ -262,6 +262,43 @@ def test_mask_argument_errors(ctx):
         net.warm_start_run(g, 1e-6, 100, 10)
     g.close()
     net.close()
+
+
+def islands_channel():
+    spec = wl.bump_channel(180, 60, sigma=10.0)
+    Y, X = np.mgrid[0:60, 0:180].astype(float)
+    inside = ((X - 70) ** 2 + (Y - 25) ** 2 > 36) & ((X - 120) ** 2 + (Y - 40) ** 2 > 20)
+    inside &= ~((X >= 95) & (X < 98) & (Y < 22))
+    spec.kind = wl.staircase_kinds(np.pad(inside[1:-1, 3:-3], ((1, 1), (3, 3)), constant_values=True))
+    spec.kind[0, :] = wl.FLUID
+    spec.kind[-1, :] = wl.FLUID
+    spec.kind[:, :3] = wl.FLUID
+    spec.kind[:, -3:] = wl.FLUID
+    return spec
+
+
+@pytest.mark.parametrize("case", ["basin", "periodic", "islands_channel", "dish", "narrow"])
+def test_masked_two_step_passes_bitwise(ctx, case):
+    """Two steps per pass on masked grids (the kinds travel with the first
+    stage's rows to the second) give the one-step result bit for bit, for
+    odd step counts, several tile heights and with open edges."""
+    if case == "basin":
+        spec, state = masked_spec(150, 80, 7), None
+    elif case == "periodic":
+        spec, state = masked_spec(96, 50, 6, edges=(wl.PERIODIC,) * 4, omega=1e-3), None
+    elif case == "islands_channel":
+        spec, state = islands_channel(), None
+    elif case == "dish":
+        spec, state = wl.circular_dish(), None
+    else:
+        spec, state = masked_spec(20, 133, 3), None
+    state = seeded(spec, 5, solid_h=-2.0) if case in ("basin", "periodic", "narrow") else spec.initial()
+    one = run_gpu(ctx, spec, 211, state, dict(tile_rows=15, tblock=1))
+    for tr in (8, 17, 44):
+        two = run_gpu(ctx, spec, 211, state, dict(tile_rows=tr, tblock=2))
+        say(case, "two-step tile rows", tr)
+        for u, v in zip(one, two):
+            assert np.array_equal(u, v)
 
 
 # ----------------------------------------------------------------------------- the paper's geometries
