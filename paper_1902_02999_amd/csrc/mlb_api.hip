@@ -1141,9 +1141,11 @@ mlb_status mlb_batch_destroy(mlb_batch* b)
 namespace {
 
 // One-step tiles cost least at 3k rows, two-step interior tiles at 3k + 2
-// (their walk ends with two rows of the second stage alone).
-const int kTuneRows[] = {6, 9, 12, 15, 21, 27, 33, 45};
-const int kTuneRows2[] = {8, 11, 14, 17, 20, 23, 26, 32, 44};
+// (their walk ends with two rows of the second stage alone).  The shortest
+// tiles serve small grids, where a wave's serial row walk, not bandwidth,
+// sets the time of a pass.
+const int kTuneRows[] = {4, 6, 9, 12, 15, 21, 27, 33, 45};
+const int kTuneRows2[] = {5, 8, 11, 14, 17, 20, 23, 26, 32, 44};
 const int kTuneCaps[] = {0, 2, 3, 4, 5};
 const int kTuneBlocks[] = {1, 2};
 
