@@ -151,6 +151,18 @@ enum { MLB_NODE_FLUID = 0, MLB_NODE_WALL = 1, MLB_NODE_SOLID = 2 };
  * MLB_E_STATE if the grid belongs to a live batch. */
 mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 
+/* The wave tiles a grid of these parameters (and optional node kinds
+ * [ny][kind_ld]) is stepped with, without a device: six int32 per tile,
+ * (x0, y0, rows, xo, yo, flags).  A tile's wave covers columns x0 - k ..
+ * x0 - k + 63 (k = 1 for one step per pass, 2 for two) and computes rows
+ * y0 .. y0 + rows - 1; it stores the nodes of columns max(x0, xo) ..
+ * x0 + 61 - (k - 1) * 2 (below nx) and rows yo .. y0 + rows - 1.  flags bit 0:
+ * the tile's window holds a WALL or SOLID node (masked kernel path).  Tiles
+ * that would own only SOLID nodes are left out.  Writes at most `capacity`
+ * tiles; *count receives the number of tiles.  No device memory is used. */
+mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
+                          int32_t tblock, int32_t* tiles, int64_t capacity, int64_t* count);
+
 /* Link depth h-bar of the bed term (Section 3).
  *   SEMI_IMPLICIT  h-bar = (h(x,t) + h(x - e_a dt,t)) / 2, Eq. (h-bar): the
  *                  form the paper prefers; exact volume conservation and the

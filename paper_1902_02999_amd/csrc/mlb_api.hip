@@ -720,6 +720,37 @@ mlb_status mlb_set_edge_discharge(mlb_grid* g, int edge, double qx, double qy)
     return MLB_OK;
 }
 
+mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
+                          int32_t tblock, int32_t* tiles, int64_t capacity, int64_t* count)
+{
+    CHK(validate_params(p));
+    if (!count || (capacity > 0 && !tiles)) return fail(MLB_E_INVAL, "count or tiles is NULL");
+    if (tile_rows < 4 || tile_rows > 4096) return fail(MLB_E_INVAL, "tile_rows out of range");
+    if (tblock != 1 && tblock != 2) return fail(MLB_E_INVAL, "tblock must be 1 or 2");
+    if (kind && kind_ld < p->nx) return fail(MLB_E_INVAL, "kind_ld < nx");
+    // a host-only grid: the tile builder reads the shape, edges and kinds
+    mlb_grid g;
+    g.p = *p;
+    (void)field_bytes(p, &g.ld);
+    if (kind) {
+        g.hmask.assign((size_t)g.ld * p->ny, (uint8_t)NODE_FLUID);
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                const uint8_t k = kind[(size_t)j * kind_ld + i];
+                if (k > NODE_SOLID) return fail(MLB_E_INVAL, "node kind must be FLUID, WALL or SOLID");
+                g.hmask[(size_t)j * g.ld + i] = k;
+            }
+    }
+    std::vector<TileDev> t;
+    make_tiles(&g, 0, tile_rows, t, tblock == 2 ? kStripOut2 : kStripOut);
+    *count = (int64_t)t.size();
+    for (int64_t i = 0; i < std::min<int64_t>(capacity, (int64_t)t.size()); ++i) {
+        int32_t* o = tiles + 6 * i;
+        o[0] = t[i].x0; o[1] = t[i].y0; o[2] = t[i].rows; o[3] = t[i].xo; o[4] = t[i].yo; o[5] = t[i].flags;
+    }
+    return MLB_OK;
+}
+
 mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
 {
     GRID_OK(g);

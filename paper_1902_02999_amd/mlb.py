@@ -113,6 +113,8 @@ SIGNATURES = {
     "mlb_set_bathymetry": (C.c_int, [_VP, _DP, C.c_int64]),
     "mlb_set_mask": (C.c_int, [_VP, C.POINTER(C.c_uint8), C.c_int64]),
     "mlb_set_hbar": (C.c_int, [_VP, C.c_int32]),
+    "mlb_plan_tiles": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_uint8), C.c_int64, C.c_int32, C.c_int32,
+                                 C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
     "mlb_set_surface": (C.c_int, [_VP, C.c_int32]),
     "mlb_set_wind": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_wind_stress": (C.c_int, [_VP, C.c_double, C.c_double]),
@@ -423,6 +425,21 @@ class Batch:
         if self.h:
             _check(lib().mlb_batch_destroy(self.h), "mlb_batch_destroy")
             self.h = None
+
+
+def plan_tiles(params: Params, tile_rows: int, tblock: int, kind=None) -> np.ndarray:
+    """The wave tiles of a grid (no device needed): rows of (x0, y0, rows, xo, yo, flags)."""
+    kp, kld = None, 0
+    if kind is not None:
+        ka = np.ascontiguousarray(np.asarray(kind).reshape(params.ny, params.nx), np.uint8)
+        kp, kld = ka.ctypes.data_as(C.POINTER(C.c_uint8)), params.nx
+    n = C.c_int64()
+    _check(lib().mlb_plan_tiles(C.byref(params), kp, kld, int(tile_rows), int(tblock), None, 0, C.byref(n)),
+           "mlb_plan_tiles")
+    out = np.zeros((max(n.value, 1), 6), np.int32)
+    _check(lib().mlb_plan_tiles(C.byref(params), kp, kld, int(tile_rows), int(tblock),
+                                out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)), "mlb_plan_tiles")
+    return out[:n.value]
 
 
 def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:
