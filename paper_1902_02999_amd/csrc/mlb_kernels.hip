@@ -75,7 +75,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 
 // ------------------------------------------------------------------ node arithmetic
 struct Node {
-    float eta, h, kk, fpx, fpy;
+    float eta, h, kq, fpx, fpy;       // kq = q . u
     float o[9];            // o[a] = Out_a(node), a = 1..8
     float H, q0x, q0y;     // the node's stored H and old discharge
     float iw, ikx, iky;    // implicit link depth: 1/(1+kappa), kappa_x, kappa_y
@@ -103,21 +103,22 @@ __device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, f
         fpx = __builtin_fmaf(B.omh, qy, B.tpx);
         fpy = __builtin_fmaf(-B.omh, qx, B.tpy);
     }
+    // Out_a = quadratic part + linear part, each product fused into the sum
+    // that uses it (every kernel variant evaluates this one expression)
     const float tqx = qx + fpx, tqy = qy + fpy;
     const float pxx = qx * u, pyy = qy * v, pxy = qx * v;
     const float kq = pxx + pyy;
     const float lx = B.c3e * tqx, ly = B.c3e * tqy;
-    const float qxx = B.c6 * __builtin_fmaf(2.0f, pxx, -pyy);
-    const float qyy = B.c6 * __builtin_fmaf(2.0f, pyy, -pxx);
-    const float qd = B.c12 * kq, rxy = B.c4 * pxy;
-    const float qd1 = qd + rxy, qd2 = qd - rxy;
-    const float ldp = 0.25f * (lx + ly), ldm = 0.25f * (lx - ly);
+    const float txx = __builtin_fmaf(2.0f, pxx, -pyy), tyy = __builtin_fmaf(2.0f, pyy, -pxx);
+    const float rxy = B.c4 * pxy;
+    const float qd1 = __builtin_fmaf(B.c12, kq, rxy), qd2 = __builtin_fmaf(B.c12, kq, -rxy);
+    const float sp = lx + ly, sm = lx - ly;
     d.o[0] = 0.0f;
-    d.o[1] = qxx + lx;  d.o[5] = qxx - lx;
-    d.o[3] = qyy + ly;  d.o[7] = qyy - ly;
-    d.o[2] = qd1 + ldp; d.o[6] = qd1 - ldp;
-    d.o[4] = qd2 - ldm; d.o[8] = qd2 + ldm;
-    d.eta = eta; d.h = h; d.kk = B.ckk * kq; d.fpx = fpx; d.fpy = fpy;
+    d.o[1] = __builtin_fmaf(B.c6, txx, lx);     d.o[5] = __builtin_fmaf(B.c6, txx, -lx);
+    d.o[3] = __builtin_fmaf(B.c6, tyy, ly);     d.o[7] = __builtin_fmaf(B.c6, tyy, -ly);
+    d.o[2] = __builtin_fmaf(0.25f, sp, qd1);    d.o[6] = __builtin_fmaf(-0.25f, sp, qd1);
+    d.o[4] = __builtin_fmaf(-0.25f, sm, qd2);   d.o[8] = __builtin_fmaf(0.25f, sm, qd2);
+    d.eta = eta; d.h = h; d.kq = kq; d.fpx = fpx; d.fpy = fpy;
     d.H = H; d.q0x = qx; d.q0y = qy;
 }
 
@@ -226,6 +227,9 @@ __device__ __forceinline__ void carry_from(float lN, float lNE, float lNW, Carry
 //   pa = (Ha + P3) + P7, pd = Bd + Ud,
 //   mass: g/(6e^2) pa + g/(24e^2) pd,
 //   x: g/(6e) Hx + g/(24e) (Bx + Ux),  y: g/(6e) (P3 - P7) + g/(24e) (Bd - Ud);
+// each product is fused into the sum that takes it, in one fixed order:
+//   eta increment = g/(6e^2) pa + (g/(24e^2) pd + (so - kk)),
+//   qx = e mxo + (g/(6e) Hx + (g/(24e) (Bx + Ux) + (dt/2) Fx)), likewise qy.
 // update_edge forms exactly these from the eight values, update_fast from
 // the shared partial sums (equal bits: only exact negations differ).
 //
@@ -265,15 +269,13 @@ __device__ __forceinline__ void update_fast(const BasinDev& B, const Node& x, co
     const float Ud = lNE + lNW, Ux = lNW - lNE;
     const float pa = (Ha - cy.cN) + lN;
     const float pd = Ud - cy.cBd;                      // Bd = -cBd
-    const float mp = __builtin_fmaf(B.cma, pa, B.cmd * pd);
-    const float pxm = __builtin_fmaf(B.cqa, -Hs, B.cqd * (cy.cBx + Ux));
-    const float pym = __builtin_fmaf(B.cqa, -(cy.cN + lN), B.cqd * -(cy.cBd + Ud));
     const float so = (C.E1 + S.S1) + N.N1;
     const float mxo = (C.E2 + S.S2) + N.N2;
     const float myo = S.S1 - N.N1;
-    qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
-    qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
-    finish<IMPL, COMP>(x, (so - x.kk) + mp, en, enl, qxn, qyn);
+    qxn = __builtin_fmaf(B.e, mxo, __builtin_fmaf(B.cqa, -Hs, __builtin_fmaf(B.cqd, cy.cBx + Ux, x.fpx)));
+    qyn = __builtin_fmaf(B.e, myo, __builtin_fmaf(B.cqa, -(cy.cN + lN), __builtin_fmaf(B.cqd, -(cy.cBd + Ud), x.fpy)));
+    finish<IMPL, COMP>(x, __builtin_fmaf(B.cma, pa, __builtin_fmaf(B.cmd, pd, __builtin_fmaf(-B.ckk, x.kq, so))),
+                       en, enl, qxn, qyn);
 }
 
 // The same from the link products P[a] and gathered equilibria oy[a] = Out_a(y_a).
@@ -286,18 +288,16 @@ __device__ __forceinline__ void update_edge(const BasinDev& B, const Node& x, co
     const float Ud = P[6] + P[8], Ux = P[8] - P[6];
     const float pa = (Ha + P[3]) + P[7];
     const float pd = Bd + Ud;
-    const float mp = __builtin_fmaf(B.cma, pa, B.cmd * pd);
-    const float pxm = __builtin_fmaf(B.cqa, Hx, B.cqd * (Bx + Ux));
-    const float pym = __builtin_fmaf(B.cqa, P[3] - P[7], B.cqd * (Bd - Ud));
     const float E1 = oy[1] + oy[5], E2 = oy[1] - oy[5];
     const float S1 = (oy[2] + oy[3]) + oy[4], S2 = oy[2] - oy[4];
     const float N1 = (oy[6] + oy[7]) + oy[8], N2 = oy[8] - oy[6];
     const float so = (E1 + S1) + N1;
     const float mxo = (E2 + S2) + N2;
     const float myo = S1 - N1;
-    qxn = x.fpx + __builtin_fmaf(B.e, mxo, pxm);
-    qyn = x.fpy + __builtin_fmaf(B.e, myo, pym);
-    finish<IMPL, COMP>(x, (so - x.kk) + mp, en, enl, qxn, qyn);
+    qxn = __builtin_fmaf(B.e, mxo, __builtin_fmaf(B.cqa, Hx, __builtin_fmaf(B.cqd, Bx + Ux, x.fpx)));
+    qyn = __builtin_fmaf(B.e, myo, __builtin_fmaf(B.cqa, P[3] - P[7], __builtin_fmaf(B.cqd, Bd - Ud, x.fpy)));
+    finish<IMPL, COMP>(x, __builtin_fmaf(B.cma, pa, __builtin_fmaf(B.cmd, pd, __builtin_fmaf(-B.ckk, x.kq, so))),
+                       en, enl, qxn, qyn);
 }
 
 struct Raw { float eta, qx, qy, H; int m; float iw, ikx, iky; float el; };   // m: node kind (masked tiles)
@@ -898,10 +898,11 @@ struct CoherentStep {
 // One pass of one step.  One wave per tile, tiles in list order (largest
 // basins first): the hardware dispatcher hands out workgroups in index
 // order, so the list is consumed as a queue without a software loop.
-// (the checked step of the implicit link depth or of a compensated surface
-// needs more than 128 VGPRs)
+// (two or more of the checked step, the mask, the implicit link depth and
+// the compensated surface together need more than 128 VGPRs)
 template <bool DIAG, bool MASKED, bool IMPL, bool COMP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((DIAG && (IMPL || COMP)) ? 3 : 4)))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((int(DIAG) + int(MASKED) + int(IMPL) + int(COMP) >= 2) ? 3 : 4)))
 void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                  int parity, double* __restrict__ partials)
 {
