@@ -61,7 +61,9 @@ enum { MLB_EDGE_WALL = 0, MLB_EDGE_PERIODIC = 1, MLB_EDGE_DEPTH = 2, MLB_EDGE_DI
 enum { MLB_W = 0, MLB_E = 1, MLB_S = 2, MLB_N = 3 };
 
 typedef struct {
-    int32_t nx, ny;        /* nodes per direction, >= 4 each (>= 5 with open edges)        */
+    int32_t nx, ny;        /* nodes per direction, >= 4 each (>= 5 with open edges); nx
+                              rounded up to a multiple of 64, times ny, < 2^30 (about
+                              32768 x 32767 nodes, 4 GiB per field)                   */
     double  dx;            /* lattice size [m]                                             */
     double  nu;            /* eddy viscosity [m^2/s]; e = 6 nu / dx, dt = dx / e (Eq. mlb-viscosity) */
     double  g;             /* gravity, 9.81 in the paper                                   */

@@ -325,6 +325,13 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     return MLB_OK;
 }
 
+// Row pitch: nx rounded up to 64 floats (256 B), plus MLB_LD_PAD floats
+// (build-time knob; breaks power-of-two pitches).
+#ifndef MLB_LD_PAD
+#define MLB_LD_PAD 0
+#endif
+int64_t row_pitch(int nx) { return (int64_t)align_up((size_t)nx, 64) + MLB_LD_PAD; }
+
 mlb_status validate_params(const mlb_params* p)
 {
     if (!p) return fail(MLB_E_INVAL, "params is NULL");
@@ -339,21 +346,19 @@ mlb_status validate_params(const mlb_params* p)
     if (ox && oy) return fail(MLB_E_INVAL, "two adjacent edges may not both be open");
     const int minx = px ? 3 : (ox ? 5 : 4), miny = py ? 3 : (oy ? 5 : 4);
     if (p->nx < minx || p->ny < miny) return fail(MLB_E_INVAL, "grid too small for its edges");
-    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return fail(MLB_E_INVAL, "grid too large");
+    // the kernels address a field plane with 32-bit byte offsets: the padded
+    // plane (row pitch x ny) must hold fewer than 2^30 floats
+    if ((int64_t)row_pitch(p->nx) * p->ny >= ((int64_t)1 << 30))
+        return fail(MLB_E_INVAL, "grid too large: row pitch x ny must stay below 2^30 nodes");
     if (!(p->dx > 0) || !(p->nu > 0) || !(p->g > 0) || !(p->rho_w > 0))
         return fail(MLB_E_INVAL, "dx, nu, g and rho_w must be positive");
     if (p->extrap_order != 1 && p->extrap_order != 2) return fail(MLB_E_INVAL, "extrap_order must be 1 or 2");
     return MLB_OK;
 }
 
-// Row pitch: nx rounded up to 64 floats (256 B), plus MLB_LD_PAD floats
-// (build-time knob; breaks power-of-two pitches).
-#ifndef MLB_LD_PAD
-#define MLB_LD_PAD 0
-#endif
 size_t field_bytes(const mlb_params* p, int* ld_out)
 {
-    const int ld = (int)align_up((size_t)p->nx, 64) + MLB_LD_PAD;
+    const int ld = (int)row_pitch(p->nx);
     if (ld_out) *ld_out = ld;
     return 256 + 7 * align_up((size_t)ld * p->ny * sizeof(float), 256);
 }

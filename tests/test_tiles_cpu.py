@@ -93,3 +93,18 @@ def test_plan_argument_errors():
     bad[3, 3] = 7
     with pytest.raises(mlb.MlbError):
         mlb.plan_tiles(p, 9, 1, bad)
+
+
+def test_size_limit_is_the_plane_addressing_limit():
+    """A field plane is addressed with 32-bit byte offsets: nx rounded up to
+    64, times ny, must stay below 2^30 nodes."""
+    ok = [(32768, 32767), (32769, 32704), (32704, 32831), (1 << 20, 1023)]
+    bad = [(32768, 32768), (32769, 32705), (32705, 32769), (1 << 20, 1024), (1 << 30, 4)]
+    for nx, ny in ok:
+        assert ((nx + 63) // 64 * 64) * ny < (1 << 30)
+        t = mlb.plan_tiles(mlb.make_params(nx, ny, 1.0, 1.0, 2.0), 4096, 2)
+        assert len(t) > 0
+    for nx, ny in bad:
+        assert ((nx + 63) // 64 * 64) * ny >= (1 << 30)
+        with pytest.raises(mlb.MlbError, match="too large"):
+            mlb.plan_tiles(mlb.make_params(nx, ny, 1.0, 1.0, 2.0), 4096, 2)
