@@ -32,6 +32,12 @@ namespace {
 
 inline bool is_open(int k) { return k == MLB_EDGE_DEPTH || k == MLB_EDGE_DISCHARGE; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline bool has_open_edge(const mlb_grid* g)
+{
+    for (int k = 0; k < 4; ++k)
+        if (is_open(g->p.edge[k])) return true;
+    return false;
+}
 
 }  // namespace
 
@@ -206,6 +212,7 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.masked = g->dmask != nullptr;
         g->plan.implicit = g->hbar == MLB_HBAR_IMPLICIT;
         g->plan.comp = g->etal != nullptr;
+        g->plan.closed = !has_open_edge(g);
         CHK(plan_alloc(c, g->plan));
         g->stale_plan = false;
         g->dirty = false;
@@ -246,7 +253,8 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     int64_t nl = 0;
     auto eager = [&](int k, bool diag) -> mlb_status {
         HIPCHK(launch_step(P.db, k == 2 ? P.dt2 : P.dt, k == 2 ? nt2 : nt1, P.parity, P.dpart, diag ? 1 : 0, k,
-                           P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, dyn, c->stream));
+                           P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, P.closed ? 1 : 0, dyn,
+                           c->stream));
         P.parity ^= 1;
         ++nl;
         return MLB_OK;
@@ -295,7 +303,8 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
             hipError_t le = hipSuccess;
             for (int i = 0; i < glaunch && le == hipSuccess; ++i) {
                 le = launch_step(P.db, kind == 2 ? P.dt2 : P.dt, kind == 2 ? nt2 : nt1, par, P.dpart, 0, kind,
-                                 P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, dyn, c->stream);
+                                 P.masked ? 1 : 0, P.implicit ? 1 : 0, P.comp ? 1 : 0, P.closed ? 1 : 0, dyn,
+                                 c->stream);
                 par ^= 1;
             }
             hipGraph_t gr = nullptr;
@@ -1065,6 +1074,8 @@ static mlb_status batch_plan(mlb_batch* b)
     b->plan.masked = masked;
     b->plan.implicit = implicit;
     b->plan.comp = comp;
+    b->plan.closed = true;
+    for (auto* g : b->grids) b->plan.closed = b->plan.closed && !has_open_edge(g);
     CHK(plan_alloc(b->ctx, b->plan));
     b->stale_plan = false;
     return MLB_OK;

@@ -407,7 +407,9 @@ struct Lane {
     float bqx_x, bqy_x, bqxS, bqyS, bqxN, bqyN;
 };
 
-template <bool EDGE>
+// OPEN false: no lane of the tile reaches an open edge (walls and periodic
+// edges only), so the open-edge logic is compiled out.
+template <bool EDGE, bool OPEN>
 __device__ __forceinline__ Lane lane_setup(const BasinDev& B, const TileDev& T, int x, bool own_lane, int xlo,
                                            int xhi)
 {
@@ -422,26 +424,26 @@ __device__ __forceinline__ Lane lane_setup(const BasinDev& B, const TileDev& T, 
     L.wout = EDGE && !B.per_x && x == 0;
     L.eout = EDGE && !B.per_x && x == nx - 1;
     L.wall_x = (L.wout && kW == EDGE_WALL) || (L.eout && kE == EDGE_WALL);
-    L.oW = L.wout && is_open(kW);
-    L.oE = L.eout && is_open(kE);
+    L.oW = OPEN && L.wout && is_open(kW);
+    L.oE = OPEN && L.eout && is_open(kE);
     L.ox_lane = L.oW || L.oE;
     L.dep_x = (L.oW && kW == EDGE_DEPTH) || (L.oE && kE == EDGE_DEPTH);
     // some lane with valid values (columns xlo .. xhi) lies on an open W / E edge
-    L.open_x = EDGE && ((is_open(kW) && xlo <= 0) || (is_open(kE) && xhi >= nx - 1));
-    L.open_s = EDGE && is_open(L.kS) && T.y0 == 0;
+    L.open_x = EDGE && OPEN && ((is_open(kW) && xlo <= 0) || (is_open(kE) && xhi >= nx - 1));
+    L.open_s = EDGE && OPEN && is_open(L.kS) && T.y0 == 0;
     L.bqx_x = L.oW ? B.bc_qx[0] : B.bc_qx[1];
     L.bqy_x = L.oW ? B.bc_qy[0] : B.bc_qy[1];
     L.bqxS = B.bc_qx[2]; L.bqyS = B.bc_qy[2]; L.bqxN = B.bc_qx[3]; L.bqyN = B.bc_qy[3];
     return L;
 }
 
-template <bool EDGE>
+template <bool EDGE, bool OPEN>
 __device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, double tn, Stage& V)
 {
     V.h1e = V.h1x = V.h1y = V.h2e = V.h2x = V.h2y = 0.0f;
     V.pe = V.pqx = V.pqy = V.pH = V.poqx = V.poqy = V.pl = 0.0f;
     V.hbS = V.hbN = V.hb_x = 0.0;
-    if (EDGE) {
+    if (EDGE && OPEN) {
         const int kW = B.kind[0], kE = B.kind[1];
         if (L.kS == EDGE_DEPTH) V.hbS = depth_bc(B, 2, tn);
         if (L.kN == EDGE_DEPTH) V.hbN = depth_bc(B, 3, tn);
@@ -520,7 +522,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             /* pre-override values of the x-neighbours (inward normals of W / E) */               \
             float re1 = 0.f, rx1 = 0.f, ry1 = 0.f, re2 = 0.f, rx2 = 0.f, ry2 = 0.f;               \
             float le1 = 0.f, lx1 = 0.f, ly1 = 0.f, le2 = 0.f, lx2 = 0.f, ly2 = 0.f;               \
-            if (L.open_x) {                                                                       \
+            if (OPEN && L.open_x) {                                                               \
                 re1 = from_right(en); rx1 = from_right(qxn); ry1 = from_right(qyn);               \
                 re2 = from_right(re1); rx2 = from_right(rx1); ry2 = from_right(ry1);              \
                 le1 = from_left(en); lx1 = from_left(qxn); ly1 = from_left(qyn);                  \
@@ -534,8 +536,8 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                 fx = 0.0f; fy = 0.0f;                                                             \
             } else {                                                                              \
                 /* a node lies on at most one open edge (adjacent open edges are rejected) */     \
-                const bool oN = onN && is_open(L.kN);                                             \
-                if (L.ox_lane || oN) {                                                            \
+                const bool oN = OPEN && onN && is_open(L.kN);                                     \
+                if ((OPEN && L.ox_lane) || oN) {                                                  \
                     const float n1e = L.oW ? re1 : (L.oE ? le1 : V.h1e);                          \
                     const float n2e = L.oW ? re2 : (L.oE ? le2 : V.h2e);                          \
                     const float n1x = L.oW ? rx1 : (L.oE ? lx1 : V.h1x);                          \
@@ -556,7 +558,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                     }                                                                             \
                 }                                                                                 \
             }                                                                                     \
-            if (L.open_s) {                                                                       \
+            if (OPEN && L.open_s) {                                                               \
                 if ((r) == 0) { /* row 0 waits for rows 1 (and 2) of this step */                 \
                     V.pe = en; V.pqx = qxn; V.pqy = qyn; V.pH = DC.H; V.poqx = DC.q0x; V.poqy = DC.q0y; \
                     V.pl = enl;                                                                   \
@@ -579,8 +581,10 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                     EMIT0(ge, gx, gy, gl);                                                        \
                 }                                                                                 \
             }                                                                                     \
-            V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                          \
-            V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                            \
+            if (OPEN) { /* history of the open N edge's extrapolation */                          \
+                V.h2e = V.h1e; V.h2x = V.h1x; V.h2y = V.h1y;                                      \
+                V.h1e = en;    V.h1x = qxn;   V.h1y = qyn;                                        \
+            }                                                                                     \
             en = fe; qxn = fx; qyn = fy; enl = fl;                                                \
         }                                                                                         \
         if (emit) { EMIT(en, qxn, qyn, DC, enl); }                                                \
@@ -599,7 +603,8 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
-    const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
+    constexpr bool OPEN = EDGE;   // one-step edge tiles keep the general boundary logic
+    const Lane L = lane_setup<EDGE, OPEN>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
     const int wr = rd ^ 1;
     // fields are device (global) memory: typed so, loads and stores are
     // global_* instructions with exact wait counts rather than flat ones
@@ -615,7 +620,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     const gfloat* __restrict__ EL0 = (const gfloat*)B.etal[rd];
     gfloat* __restrict__ EL1 = (gfloat*)B.etal[wr];
     Stage V;
-    stage_setup<EDGE>(B, L, (double)(step + 1) * B.dt, V);
+    stage_setup<EDGE, OPEN>(B, L, (double)(step + 1) * B.dt, V);
     Sums sums = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
@@ -704,7 +709,8 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // is final only after A's row `extrap`, so B starts once A has done row r0+2.
 // MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only); the
 // kinds travel with stage A's rows through the queue to stage B.
-template <bool EDGE, bool FRIC, bool MASK>
+// OPEN: some lane of the tile reaches an open edge (see lane_setup).
+template <bool EDGE, bool FRIC, bool MASK, bool OPEN>
 __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step)
 {
     static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
@@ -714,7 +720,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     constexpr bool COMP = false;   // so do grids with a compensated surface
     gcu8* __restrict__ MK = (gcu8*)B.mask;
     const Coef K = {nullptr, nullptr, nullptr};
-    const Lane L = lane_setup<EDGE>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
+    const Lane L = lane_setup<EDGE, OPEN>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
     const int wr = rd ^ 1;
     const gfloat* __restrict__ E0 = (const gfloat*)B.eta[rd];
@@ -726,8 +732,8 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
     const double tn0 = (double)step * B.dt;
     Stage SA, SB;
-    stage_setup<EDGE>(B, L, tn0 + B.dt, SA);
-    stage_setup<EDGE>(B, L, tn0 + 2.0 * B.dt, SB);
+    stage_setup<EDGE, OPEN>(B, L, tn0 + B.dt, SA);
+    stage_setup<EDGE, OPEN>(B, L, tn0 + 2.0 * B.dt, SB);
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
@@ -794,13 +800,15 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
             stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
         }                                                                                         \
     } while (0)
-    // B row rb consumes A's row rb+1; then A computes row rb+3.  Interior
-    // tiles pad their rows to 3 nk + 2: nk rounds of three (B, A) pairs, then
-    // B's last two rows alone, which need no further A row (A ends at r1 when
-    // the tile's rows are 2 mod 3).  Edge tiles, whose boundary state leaves
-    // no registers for that tail, pad to 3 nk and let A run two rows past the
-    // tile.  Pad rows and A's surplus rows are computed but never stored.
-    const int nk = EDGE ? (T.rows + 2) / 3 : T.rows / 3;   // T.rows >= 4, so nk >= 1
+    // B row rb consumes A's row rb+1; then A computes row rb+3.  Tiles pad
+    // their rows to 3 nk + 2: nk rounds of three (B, A) pairs, then B's last
+    // two rows alone, which need no further A row (A ends at r1 when the
+    // tile's rows are 2 mod 3).  Tiles with open edges, whose boundary state
+    // leaves no registers for that tail, pad to 3 nk and let A run two rows
+    // past the tile.  Pad rows and A's surplus rows are computed but never
+    // stored.
+    constexpr bool TAIL = !(EDGE && OPEN);
+    const int nk = TAIL ? T.rows / 3 : (T.rows + 2) / 3;   // T.rows >= 4, so nk >= 1
     for (int k = 0; k < nk; ++k) {
         MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
         ++rb;
@@ -815,7 +823,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_NOTHING);
         ++ra;
     }
-    if (!EDGE) {
+    if (TAIL) {
         MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
         ++rb;
         MLB_ROW(SB, rb, q0, B1, B2, B0, b2, b0, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
@@ -835,8 +843,10 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 // with the fused reduction when DIAG) or two (KIND 2).  `step` reads the
 // basin's step counter at buffer rd; the basin's first tile advances it.
 // MASKED: the tile list may hold TILE_MASKED tiles (a separate kernel, so
-// that grids without a mask keep the smaller register budget).
-template <int KIND, bool DIAG, bool MASKED, bool IMPL, bool COMP, class StepRead>
+// that grids without a mask keep the smaller register budget).  CLOSED: no
+// basin of the launch has an open edge (two-step passes compile the
+// open-edge logic out).
+template <int KIND, bool DIAG, bool MASKED, bool IMPL, bool COMP, bool CLOSED, class StepRead>
 __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles,
                                           int t, int parity, double* __restrict__ partials, StepRead step_at)
 {
@@ -866,18 +876,20 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         }
     } else {
         // a two-step tile needs the boundary logic when stage A's rows
-        // r0-1 .. r1 or lanes 1..62 touch an edge
+        // r0-1 .. r1 or lanes 1..62 touch an edge; the open-edge part of it
+        // only when some basin of the launch has an open edge
         const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
                           (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
         const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
+        constexpr bool OPEN = !CLOSED;
         if (B.cfr != 0.0f) {
-            if (masked) run_tile2<true, true, MASKED>(B, T, rd, step);
-            else if (edge) run_tile2<true, true, false>(B, T, rd, step);
-            else run_tile2<false, true, false>(B, T, rd, step);
+            if (masked) run_tile2<true, true, MASKED, OPEN>(B, T, rd, step);
+            else if (edge) run_tile2<true, true, false, OPEN>(B, T, rd, step);
+            else run_tile2<false, true, false, false>(B, T, rd, step);
         } else {
-            if (masked) run_tile2<true, false, MASKED>(B, T, rd, step);
-            else if (edge) run_tile2<true, false, false>(B, T, rd, step);
-            else run_tile2<false, false, false>(B, T, rd, step);
+            if (masked) run_tile2<true, false, MASKED, OPEN>(B, T, rd, step);
+            else if (edge) run_tile2<true, false, false, OPEN>(B, T, rd, step);
+            else run_tile2<false, false, false, false>(B, T, rd, step);
         }
     }
 }
@@ -908,19 +920,19 @@ void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict_
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<1, DIAG, MASKED, IMPL, COMP>(basins, tiles, t, parity, partials, PlainStep{});
+    pass_tile<1, DIAG, MASKED, IMPL, COMP, false>(basins, tiles, t, parity, partials, PlainStep{});
 }
 
 // One pass of two steps, over tiles of 60-column strips (MASKED: the list
-// may hold TILE_MASKED tiles).
-template <bool MASKED>
+// may hold TILE_MASKED tiles; CLOSED: walls and periodic edges only).
+template <bool MASKED, bool CLOSED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                   int parity)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false, MASKED, false, false>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, MASKED, false, false, CLOSED>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -943,7 +955,8 @@ void persistent_kernel(const BasinDev* __restrict__ basins, const TileDev* __res
     if (abort_flag) return;
     for (int p = 0; p < npasses; ++p) {
         if (t < ntiles)
-            pass_tile<KIND, false, MASKED, false, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr, CoherentStep{});
+            pass_tile<KIND, false, MASKED, false, false, false>(basins, tiles, t, parity0 ^ (p & 1), nullptr,
+                                                                CoherentStep{});
         __threadfence();   // release: this wave's stores, device-wide
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1083,17 +1096,18 @@ static void launch_one(dim3 grid, unsigned dyn_lds, hipStream_t s, const BasinDe
 
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
                        double* d_partials, int diag, int tblock, int masked, int implicit, int comp,
-                       unsigned dyn_lds, hipStream_t s)
+                       int closed, unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
     if (tblock != 1 && (tblock != 2 || diag || implicit || comp)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (tblock == 2) {
-        if (masked)
-            hipLaunchKernelGGL(step2_kernel<true>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
-        else
-            hipLaunchKernelGGL(step2_kernel<false>, grid, dim3(kBlock), dyn_lds, s, d_basins, d_tiles, ntiles, parity);
+        using K2 = void (*)(const BasinDev*, const TileDev*, int, int);
+        static const K2 k2[4] = {step2_kernel<false, false>, step2_kernel<false, true>, step2_kernel<true, false>,
+                                 step2_kernel<true, true>};
+        hipLaunchKernelGGL(k2[(masked ? 2 : 0) + (closed ? 1 : 0)], grid, dim3(kBlock), dyn_lds, s, d_basins,
+                           d_tiles, ntiles, parity);
         return hipGetLastError();
     }
     using L = void (*)(dim3, unsigned, hipStream_t, const BasinDev*, const TileDev*, int, int, double*);

@@ -67,6 +67,7 @@ struct Plan {
     bool masked = false;       // some basin has a node mask: one-step passes, masked kernel
     bool implicit = false;     // the basins use the implicit link depth: one-step passes
     bool comp = false;         // the basins have a compensated surface: one-step passes
+    bool closed = false;       // no basin has an open edge: the two-step kernel without open-edge logic
     bool built = false;
 
     void release()
