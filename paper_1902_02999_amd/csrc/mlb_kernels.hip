@@ -587,6 +587,28 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
             }                                                                                     \
             en = fe; qxn = fx; qyn = fy; enl = fl;                                                \
         }                                                                                         \
+        if (XO) {                                                                                 \
+            /* interior arithmetic on a tile whose only edges are open W / E ones: the values of  \
+               an open-edge node are replaced whole (as in the edge path), from its inner        \
+               neighbours' new values and the boundary data */                                    \
+            const float re1 = from_right(en), rx1 = from_right(qxn), ry1 = from_right(qyn);       \
+            const float re2 = from_right(re1), rx2 = from_right(rx1), ry2 = from_right(ry1);      \
+            const float le1 = from_left(en), lx1 = from_left(qxn), ly1 = from_left(qyn);          \
+            const float le2 = from_left(le1), lx2 = from_left(lx1), ly2 = from_left(ly1);         \
+            if (L.ox_lane) {                                                                      \
+                const float n1e = L.oW ? re1 : le1, n2e = L.oW ? re2 : le2;                       \
+                const float n1x = L.oW ? rx1 : lx1, n2x = L.oW ? rx2 : lx2;                       \
+                const float n1y = L.oW ? ry1 : ly1, n2y = L.oW ? ry2 : ly2;                       \
+                const float xe = L.two ? __builtin_fmaf(2.0f, n1e, -n2e) : n1e;                   \
+                const float xx = L.two ? __builtin_fmaf(2.0f, n1x, -n2x) : n1x;                   \
+                const float xy = L.two ? __builtin_fmaf(2.0f, n1y, -n2y) : n1y;                   \
+                if (L.dep_x) {                                                                    \
+                    en = (float)(V.hb_x - (double)DC.H); qxn = xx; qyn = xy;                      \
+                } else {                                                                          \
+                    en = xe; qxn = L.bqx_x; qyn = L.bqy_x;                                        \
+                }                                                                                 \
+            }                                                                                     \
+        }                                                                                         \
         if (emit) { EMIT(en, qxn, qyn, DC, enl); }                                                \
     } while (0)
 
@@ -604,6 +626,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
     constexpr bool OPEN = EDGE;   // one-step edge tiles keep the general boundary logic
+    constexpr bool XO = false;
     const Lane L = lane_setup<EDGE, OPEN>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
     const int wr = rd ^ 1;
     // fields are device (global) memory: typed so, loads and stores are
@@ -710,7 +733,9 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // MASK: the tile's window holds WALL or SOLID nodes (EDGE tiles only); the
 // kinds travel with stage A's rows through the queue to stage B.
 // OPEN: some lane of the tile reaches an open edge (see lane_setup).
-template <bool EDGE, bool FRIC, bool MASK, bool OPEN>
+// XO: the tile's only edges are open W / E ones (EDGE false): interior
+// arithmetic, then the open-edge nodes' values replaced as the edge path does.
+template <bool EDGE, bool FRIC, bool MASK, bool OPEN, bool XO = false>
 __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step)
 {
     static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
@@ -720,7 +745,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     constexpr bool COMP = false;   // so do grids with a compensated surface
     gcu8* __restrict__ MK = (gcu8*)B.mask;
     const Coef K = {nullptr, nullptr, nullptr};
-    const Lane L = lane_setup<EDGE, OPEN>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
+    const Lane L = lane_setup<EDGE || XO, OPEN>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
     const int wr = rd ^ 1;
     const gfloat* __restrict__ E0 = (const gfloat*)B.eta[rd];
@@ -732,8 +757,8 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     gfloat* __restrict__ QY1 = (gfloat*)B.qy[wr];
     const double tn0 = (double)step * B.dt;
     Stage SA, SB;
-    stage_setup<EDGE, OPEN>(B, L, tn0 + B.dt, SA);
-    stage_setup<EDGE, OPEN>(B, L, tn0 + 2.0 * B.dt, SB);
+    stage_setup<EDGE || XO, OPEN>(B, L, tn0 + B.dt, SA);
+    stage_setup<EDGE || XO, OPEN>(B, L, tn0 + 2.0 * B.dt, SB);
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
@@ -878,16 +903,22 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         // a two-step tile needs the boundary logic when stage A's rows
         // r0-1 .. r1 or lanes 1..62 touch an edge; the open-edge part of it
         // only when some basin of the launch has an open edge
-        const bool edge = (!B.per_x && (T.x0 < 2 || T.x0 + kStripOut2 + 2 > B.nx)) ||
-                          (!B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny));
+        const bool tw = !B.per_x && T.x0 < 2, te = !B.per_x && T.x0 + kStripOut2 + 2 > B.nx;
+        const bool ty = !B.per_y && (T.y0 < 2 || T.y0 + T.rows + 2 > B.ny);
+        const bool edge = tw || te || ty;
+        // only open W / E edges in reach: interior arithmetic plus the edge
+        // nodes' replacement (a wall or an S / N edge needs the edge path)
+        const bool xo = !CLOSED && edge && !ty && (!tw || is_open(B.kind[0])) && (!te || is_open(B.kind[1]));
         const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         constexpr bool OPEN = !CLOSED;
         if (B.cfr != 0.0f) {
             if (masked) run_tile2<true, true, MASKED, OPEN>(B, T, rd, step);
+            else if (xo) run_tile2<false, true, false, true, true>(B, T, rd, step);
             else if (edge) run_tile2<true, true, false, OPEN>(B, T, rd, step);
             else run_tile2<false, true, false, false>(B, T, rd, step);
         } else {
             if (masked) run_tile2<true, false, MASKED, OPEN>(B, T, rd, step);
+            else if (xo) run_tile2<false, false, false, true, true>(B, T, rd, step);
             else if (edge) run_tile2<true, false, false, OPEN>(B, T, rd, step);
             else run_tile2<false, false, false, false>(B, T, rd, step);
         }

@@ -250,6 +250,12 @@ def test_two_step_batch_bitwise(ctx):
         for a, r in zip(g.get_state(), ref):
             assert np.array_equal(a, r)
         g.close()
+    # the closed basins on their own take the kernel without open-edge logic,
+    # in the batch with the open channel the general one: same bits
+    for s, ref in zip(specs[:3], solo):
+        got = run_gpu(ctx, s, 77, opts=dict(tile_rows=15, tblock=2, graph_chunk=8))
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r)
 
 
 _PERSIST = [c for c in _TB2 if c[0] in ("closed64", "closed61x9_rows6", "periodic70x40", "channel_order2",
