@@ -28,6 +28,7 @@ FP32_PEAK_TFLOPS = 78.6
 # derive 48 (41 without bed friction), row partial sums 8, links 12, update 34,
 # carried link sums 2.
 FLOP_PER_LUP = {True: 104, False: 97}
+FLOP_IMPLICIT = 5              # implicit link depth: scale the increment, correct qx and qy (two FMAs)
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
                  2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
@@ -102,8 +103,8 @@ def main():
                          "elab: the eLABSWE baseline (nine stored distributions) against the streaming-only "
                          "step on a closed 4096^2 basin")
     ap.add_argument("--implicit", action="store_true",
-                    help="bump: the implicit link depth (new-time depth at the node; one step per pass, "
-                         "12 more bytes per node)")
+                    help="bump: the implicit link depth (new-time depth at the node; 12 more bytes per node "
+                         "per pass, 5 more FP32 operations per update)")
     ap.add_argument("--compensated", action="store_true",
                     help="bump: surface stored as a compensated FP32 pair (one step per pass, 8 more bytes per node)")
     ap.add_argument("--elab-tile-rows", type=int, default=0,
@@ -165,19 +166,21 @@ def main():
     tb = grid.exec_opts().tblock
     # Dominant kernel: one launch per step (tblock 1) or per two steps (tblock
     # 2; the one or two closing single steps of the call are < 0.3 % of it).
-    if args.implicit or args.compensated:
+    if args.compensated:
         tb = 1   # one step per pass whatever was requested
     launch_s = tb * ev_ms / 1e3 / args.steps
     # + 1/(1+kappa), kappa_x, kappa_y; + the low part of eta read and written
     bpl = BYTES_PER_LUP + (12 if args.implicit else 0) + (8 if args.compensated else 0)
     gbs = bpl * nodes / launch_s / 1e9
-    traffic = None if args.compensated else measured_traffic(nodes, "implicit" if args.implicit else tb)
+    traffic = None if args.compensated else measured_traffic(nodes, ("implicit" if tb == 1 else None) if args.implicit
+                                                             else tb)
     if tb == 1:
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     else:
         # two steps per HBM pass: the kernel is bound by vector ALU issue
-        tfl = FLOP_PER_LUP[spec.chezy > 0] * 2 * nodes / launch_s / 1e12
+        flop = FLOP_PER_LUP[spec.chezy > 0] + (FLOP_IMPLICIT if args.implicit else 0)
+        tfl = flop * 2 * nodes / launch_s / 1e12
         roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
     out = {

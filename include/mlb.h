@@ -177,8 +177,9 @@ mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind
  *                  recomputed by mlb_set_bathymetry and mlb_set_mask; 12 more
  *                  bytes per node read per step).  The volume is then
  *                  conserved only to O(dt) of the bed-term asymmetry.  Grids
- *                  in this form run one step per pass with ordinary launches
- *                  (tblock 2 and persistent are accepted and run as one-step
+ *                  in this form take one or two steps per pass (the
+ *                  coefficients travel with the two-step kernel's rows) with
+ *                  ordinary launches (persistent is accepted and runs as
  *                  graph / stream launches).
  * MLB_E_UNSTABLE if 1 + kappa <= 0 at some node (a bed far too rough for the
  * lattice); MLB_E_STATE if the grid belongs to a live batch.  The grids of a

@@ -202,8 +202,8 @@ mlb_status grid_plan(mlb_grid* g)
         g->plan.ht.clear();
         g->plan.ht2.clear();
         make_tiles(g, 0, g->opts.tile_rows, g->plan.ht, kStripOut);
-        // the implicit link depth and the compensated surface run one step per pass
-        const bool one = g->hbar == MLB_HBAR_IMPLICIT || g->etal;
+        // the compensated surface runs one step per pass
+        const bool one = g->etal != nullptr;
         if (g->opts.tblock == 2 && !one) make_tiles(g, 0, g->opts.tile_rows, g->plan.ht2, kStripOut2);
         g->plan.hb[0].first_tile = 0;
         g->plan.hb[0].ntiles = (int)g->plan.ht.size();
@@ -1066,7 +1066,7 @@ static mlb_status batch_plan(mlb_batch* b)
         make_tiles(g, i, b->opts.tile_rows, b->plan.ht, kStripOut);
         d.ntiles = (int)b->plan.ht.size() - d.first_tile;
         d.first_tile2 = (int)b->plan.ht2.size();
-        if (b->opts.tblock == 2 && !implicit && !comp)
+        if (b->opts.tblock == 2 && !comp)
             make_tiles(g, i, b->opts.tile_rows, b->plan.ht2, kStripOut2);
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
@@ -1292,8 +1292,8 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     mlb_exec_opts best = base;
     double best_t = 1e300;
     const int n = std::max(2, steps & ~1);
-    bool one = false;   // the implicit link depth and the compensated surface run one step per pass
-    for (auto* g : gs) one |= g->hbar == MLB_HBAR_IMPLICIT || g->etal != nullptr;
+    bool one = false;   // the compensated surface runs one step per pass
+    for (auto* g : gs) one |= g->etal != nullptr;
     for (int ps = 0; ps < 2; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))

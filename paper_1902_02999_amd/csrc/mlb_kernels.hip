@@ -396,6 +396,7 @@ struct Stage {
     Carry cy;
     float h1e, h1x, h1y, h2e, h2x, h2y;
     float pe, pqx, pqy, pH, poqx, poqy, pl;
+    float piw, pikx, piky;   // implicit link depth: the deferred row's coefficients
     double hbS, hbN, hb_x;
 };
 
@@ -442,6 +443,7 @@ __device__ __forceinline__ void stage_setup(const BasinDev& B, const Lane& L, do
 {
     V.h1e = V.h1x = V.h1y = V.h2e = V.h2x = V.h2y = 0.0f;
     V.pe = V.pqx = V.pqy = V.pH = V.poqx = V.poqy = V.pl = 0.0f;
+    V.piw = 1.0f; V.pikx = V.piky = 0.0f;
     V.hbS = V.hbN = V.hb_x = 0.0;
     if (EDGE && OPEN) {
         const int kW = B.kind[0], kE = B.kind[1];
@@ -562,6 +564,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
                 if ((r) == 0) { /* row 0 waits for rows 1 (and 2) of this step */                 \
                     V.pe = en; V.pqx = qxn; V.pqy = qyn; V.pH = DC.H; V.poqx = DC.q0x; V.poqy = DC.q0y; \
                     V.pl = enl;                                                                   \
+                    if (IMPL) { V.piw = DC.iw; V.pikx = DC.ikx; V.piky = DC.iky; }                \
                     emit = false;                                                                 \
                 } else if ((r) == extrap) {                                                       \
                     const float m1e = L.two ? V.h1e : en, m1x = L.two ? V.h1x : qxn;              \
@@ -735,16 +738,17 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // OPEN: some lane of the tile reaches an open edge (see lane_setup).
 // XO: the tile's only edges are open W / E ones (EDGE false): interior
 // arithmetic, then the open-edge nodes' values replaced as the edge path does.
-template <bool EDGE, bool FRIC, bool MASK, bool OPEN, bool XO = false>
+// IMPL: the basin uses the implicit link depth; each node's coefficients
+// travel with stage A's rows through the queue to stage B.
+template <bool EDGE, bool FRIC, bool MASK, bool OPEN, bool IMPL, bool XO = false>
 __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step)
 {
     static_assert(EDGE || !MASK, "the mask logic lives in the edge path");
     const int lane = threadIdx.x & (kWave - 1);
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
-    constexpr bool IMPL = false;   // grids with the implicit link depth run one step per pass
-    constexpr bool COMP = false;   // so do grids with a compensated surface
+    constexpr bool COMP = false;   // grids with a compensated surface run one step per pass
     gcu8* __restrict__ MK = (gcu8*)B.mask;
-    const Coef K = {nullptr, nullptr, nullptr};
+    const Coef K = {(const gfloat*)B.cw, (const gfloat*)B.ckx, (const gfloat*)B.cky};
     const Lane L = lane_setup<EDGE || XO, OPEN>(B, T, T.x0 + lane - 2, lane >= 2 && lane <= kStripOut2 + 1, T.x0 - 1,
                                     T.x0 + kStripOut2);
     const int wr = rd ^ 1;
@@ -762,7 +766,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 
     const int r0 = T.y0, r1 = T.y0 + T.rows;
     const int alast = r1 + 1;     // last level-n row stage A reads
-#define MLB_LD(row) load_raw<MASK, false, false>(E0, QX0, QY0, HH, nullptr, MK, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
+#define MLB_LD(row) load_raw<MASK, IMPL, false>(E0, QX0, QY0, HH, nullptr, MK, K, (uint32_t)(wrap_or_clamp(min((row), alast), ny, per_y) * ld) + (uint32_t)L.xl)
     // stage A: prefetch of rows r0 .. r0+2, window rows r0-2 (S) and r0-1 (C)
     Raw wa = MLB_LD(r0), wb = MLB_LD(r0 + 1), wc = MLB_LD(r0 + 2);
     Node a0, a1, a2;
@@ -770,12 +774,14 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     {
         const Raw w = MLB_LD(r0 - 2);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a0);
+        take_coef<IMPL, false>(w, a0);
         exchange<EDGE>(a0, A0);
         if (MASK) { mask_row(w.m, A0); a0.mk = w.m; }
     }
     {
         const Raw w = MLB_LD(r0 - 1);
         derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a1);
+        take_coef<IMPL, false>(w, a1);
         exchange<EDGE>(a1, A1);
         if (MASK) { mask_row(w.m, A1); a1.mk = w.m; }
     }
@@ -786,16 +792,19 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     int ra = r0 - 1;
     // every lane's row goes into the queue, SOLID nodes included (their values
     // only meet bounced links, and stage B does not store them)
-#define MLB_Q0(en_, qx_, qy_, D_, el_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; if (MASK) q0.m = D_.mk; } while (0)
-#define MLB_Q1(en_, qx_, qy_, D_, el_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; if (MASK) q1.m = D_.mk; } while (0)
-#define MLB_Q2(en_, qx_, qy_, D_, el_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; if (MASK) q2.m = D_.mk; } while (0)
+#define MLB_QC(q_, D_) do { if (IMPL) { q_.iw = D_.iw; q_.ikx = D_.ikx; q_.iky = D_.iky; } } while (0)
+#define MLB_Q0(en_, qx_, qy_, D_, el_) do { q0.eta = en_; q0.qx = qx_; q0.qy = qy_; q0.H = D_.H; if (MASK) q0.m = D_.mk; MLB_QC(q0, D_); } while (0)
+#define MLB_Q1(en_, qx_, qy_, D_, el_) do { q1.eta = en_; q1.qx = qx_; q1.qy = qy_; q1.H = D_.H; if (MASK) q1.m = D_.mk; MLB_QC(q1, D_); } while (0)
+#define MLB_Q2(en_, qx_, qy_, D_, el_) do { q2.eta = en_; q2.qx = qx_; q2.qy = qy_; q2.H = D_.H; if (MASK) q2.m = D_.mk; MLB_QC(q2, D_); } while (0)
     // A's deferred row 0 (open S edge: r0 == 0, so its slot is q1; nodes next
     // to an open edge are FLUID)
-#define MLB_A0(ge_, gx_, gy_, gl_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; if (MASK) q1.m = NODE_FLUID; } while (0)
+#define MLB_A0(ge_, gx_, gy_, gl_) do { q1.eta = ge_; q1.qx = gx_; q1.qy = gy_; q1.H = SA.pH; if (MASK) q1.m = NODE_FLUID; \
+                                         if (IMPL) { q1.iw = SA.piw; q1.ikx = SA.pikx; q1.iky = SA.piky; } } while (0)
     MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0-1
     ++ra;
     // B's window row r0-1
     derive<FRIC>(B, q0.eta, q0.qx, q0.qy, q0.H, b0);
+    take_coef<IMPL, false>(q0, b0);
     exchange<EDGE>(b0, B0);
     if (MASK) { mask_row(q0.m, B0); b0.mk = q0.m; }
     MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_A0);   // row r0
@@ -806,6 +815,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     ++ra;
     // B's window row r0 (final now) and its links towards row r0-1
     derive<FRIC>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
+    take_coef<IMPL, false>(q1, b1);
     exchange<EDGE>(b1, B1);
     if (MASK) { mask_row(q1.m, B1); b1.mk = q1.m; }
     carry_init<EDGE, false>(b0, B1, SB.cy);
@@ -858,6 +868,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
 #undef MLB_Q0
 #undef MLB_Q1
 #undef MLB_Q2
+#undef MLB_QC
 #undef MLB_A0
 #undef MLB_LD
 }
@@ -912,15 +923,15 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
         const bool masked = MASKED && (T.flags & TILE_MASKED) != 0;
         constexpr bool OPEN = !CLOSED;
         if (B.cfr != 0.0f) {
-            if (masked) run_tile2<true, true, MASKED, OPEN>(B, T, rd, step);
-            else if (xo) run_tile2<false, true, false, true, true>(B, T, rd, step);
-            else if (edge) run_tile2<true, true, false, OPEN>(B, T, rd, step);
-            else run_tile2<false, true, false, false>(B, T, rd, step);
+            if (masked) run_tile2<true, true, MASKED, OPEN, IMPL>(B, T, rd, step);
+            else if (xo) run_tile2<false, true, false, true, IMPL, true>(B, T, rd, step);
+            else if (edge) run_tile2<true, true, false, OPEN, IMPL>(B, T, rd, step);
+            else run_tile2<false, true, false, false, IMPL>(B, T, rd, step);
         } else {
-            if (masked) run_tile2<true, false, MASKED, OPEN>(B, T, rd, step);
-            else if (xo) run_tile2<false, false, false, true, true>(B, T, rd, step);
-            else if (edge) run_tile2<true, false, false, OPEN>(B, T, rd, step);
-            else run_tile2<false, false, false, false>(B, T, rd, step);
+            if (masked) run_tile2<true, false, MASKED, OPEN, IMPL>(B, T, rd, step);
+            else if (xo) run_tile2<false, false, false, true, IMPL, true>(B, T, rd, step);
+            else if (edge) run_tile2<true, false, false, OPEN, IMPL>(B, T, rd, step);
+            else run_tile2<false, false, false, false, IMPL>(B, T, rd, step);
         }
     }
 }
@@ -955,15 +966,16 @@ void step_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict_
 }
 
 // One pass of two steps, over tiles of 60-column strips (MASKED: the list
-// may hold TILE_MASKED tiles; CLOSED: walls and periodic edges only).
-template <bool MASKED, bool CLOSED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+// may hold TILE_MASKED tiles; CLOSED: walls and periodic edges only; IMPL:
+// the implicit link depth, whose coefficients need more registers).
+template <bool MASKED, bool CLOSED, bool IMPL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IMPL ? 2 : 3)))
 void step2_kernel(const BasinDev* __restrict__ basins, const TileDev* __restrict__ tiles, int ntiles,
                   int parity)
 {
     const int t = uniform(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    pass_tile<2, false, MASKED, false, false, CLOSED>(basins, tiles, t, parity, nullptr, PlainStep{});
+    pass_tile<2, false, MASKED, IMPL, false, CLOSED>(basins, tiles, t, parity, nullptr, PlainStep{});
 }
 
 // Many passes in one cooperative launch, every tile's wave resident: a grid
@@ -1130,15 +1142,17 @@ hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int nti
                        int closed, unsigned dyn_lds, hipStream_t s)
 {
     // dyn_lds: unused dynamic LDS that caps resident workgroups per CU
-    if (tblock != 1 && (tblock != 2 || diag || implicit || comp)) return hipErrorInvalidValue;
+    if (tblock != 1 && (tblock != 2 || diag || comp)) return hipErrorInvalidValue;
     const int per = kBlock / kWave;
     const dim3 grid((ntiles + per - 1) / per);
     if (tblock == 2) {
         using K2 = void (*)(const BasinDev*, const TileDev*, int, int);
-        static const K2 k2[4] = {step2_kernel<false, false>, step2_kernel<false, true>, step2_kernel<true, false>,
-                                 step2_kernel<true, true>};
-        hipLaunchKernelGGL(k2[(masked ? 2 : 0) + (closed ? 1 : 0)], grid, dim3(kBlock), dyn_lds, s, d_basins,
-                           d_tiles, ntiles, parity);
+        static const K2 k2[8] = {step2_kernel<false, false, false>, step2_kernel<false, true, false>,
+                                 step2_kernel<true, false, false>,  step2_kernel<true, true, false>,
+                                 step2_kernel<false, false, true>,  step2_kernel<false, true, true>,
+                                 step2_kernel<true, false, true>,   step2_kernel<true, true, true>};
+        hipLaunchKernelGGL(k2[(implicit ? 4 : 0) + (masked ? 2 : 0) + (closed ? 1 : 0)], grid, dim3(kBlock), dyn_lds,
+                           s, d_basins, d_tiles, ntiles, parity);
         return hipGetLastError();
     }
     using L = void (*)(dim3, unsigned, hipStream_t, const BasinDev*, const TileDev*, int, int, double*);

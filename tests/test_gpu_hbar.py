@@ -1,5 +1,5 @@
-"""Implicit link depth on the GPU (one-step kernel with the static per-node
-sums) against the oracle's exact solve, and its invariants.
+"""Implicit link depth on the GPU (the static per-node sums, one or two steps
+per pass) against the oracle's exact solve, and its invariants.
 
 Bar as for the other parity tests: max |dh| <= 1e-5 max h, max |du| <= 1e-4
 max |u|.  Over a flat bed the implicit form is Eq. h-bar's map bit for bit
@@ -137,6 +137,53 @@ def test_implicit_execution_variants_bitwise(ctx):
         got = run_gpu(ctx, spec, 101, state, o)
         for u, v in zip(base, got):
             assert np.array_equal(u, v)
+
+
+def _two_step_cases():
+    """(name, spec, state, steps, tile_rows): every edge kind (the open S edge's
+    deferred row carries its coefficients through the queue), both
+    extrapolation orders, a node mask, narrow and odd strips."""
+    cases = []
+    for nx, ny, rows in ((125, 70, 15), (5, 4, 4), (61, 9, 6), (59, 31, 30)):
+        sp = closed(nx, ny, nx + ny, omega=1e-3)
+        cases.append(("closed%dx%d_rows%d" % (nx, ny, rows), sp, wl.seeded_state(sp, 2, q_amp=0.1), 37, rows))
+    sp = closed(70, 40, 5, edges=(wl.PERIODIC,) * 4)
+    cases.append(("periodic70x40", sp, wl.seeded_state(sp, 5, q_amp=0.2), 101, 9))
+    kind = wl.random_geometry(np.random.Generator(np.random.PCG64(4)), 130, 67, holes=4)
+    sp = closed(130, 67, 4, kind=kind)
+    cases.append(("masked130x67", sp, wl.seeded_state(sp, 4, q_amp=0.1), 61, 14))
+    for order in (1, 2):
+        sp = implicit(wl.bump_channel(150, 67, sigma=12.0, bump=0.4))
+        sp.extrap_order = order
+        cases.append(("channel_order%d" % order, sp, None, 120, 15))
+        nx, ny = 40, 90
+        sp = implicit(wl.Spec("ychannel", nx, ny, 1.0, 25.0 / 6.0, bumpy(nx, ny, 7, amp=0.2), 2.0,
+                              edges=(wl.PERIODIC, wl.PERIODIC, wl.DISCHARGE, wl.DEPTH), extrap_order=order,
+                              depth_bc={wl.N: (2.0, 0.05, 30.0, 0.0)}, discharge_bc={wl.S: (0.1, 1.5)},
+                              qy0=np.full((ny, nx), 1.5)))
+        cases.append(("ychannel_order%d" % order, sp, None, 99, 12))
+    sp = implicit(wl.Spec("ydepth", 70, 46, 1.0, 25.0 / 6.0, bumpy(70, 46, 9, amp=0.2), 2.0,
+                          edges=(wl.WALL, wl.WALL, wl.DEPTH, wl.DISCHARGE), extrap_order=2,
+                          depth_bc={wl.S: (2.0, 0.03, 20.0, 0.5)}, discharge_bc={wl.N: (0.0, 0.5)}))
+    cases.append(("ydepth_walls", sp, None, 66, 15))
+    cases.append(("hump", implicit(wl.hump_channel()), None, 51, 17))
+    return cases
+
+
+_TB2 = _two_step_cases()
+
+
+@pytest.mark.parametrize("case", _TB2, ids=[c[0] for c in _TB2])
+def test_implicit_two_step_passes_bitwise(ctx, case):
+    """Two steps per pass give the bits of one step per pass (whose parity
+    with the oracle the tests above check)."""
+    name, spec, state, steps, rows = case
+    say("implicit two-step case", name, spec.nx, spec.ny, "steps", steps, "rows", rows)
+    one = run_gpu(ctx, spec, steps, state, {"tile_rows": rows, "tblock": 1})
+    for opts in ({"tile_rows": rows, "tblock": 2}, {"tile_rows": rows, "tblock": 2, "use_graph": True, "graph_chunk": 8}):
+        two = run_gpu(ctx, spec, steps, state, opts)
+        for a, b in zip(two, one):
+            assert np.array_equal(a, b), (name, opts)
 
 
 def test_implicit_batch_and_errors(ctx):
