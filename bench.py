@@ -33,8 +33,25 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
                  2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
                  "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
+                 "implicit2": os.path.join(ROOT, "profiles", "step2_kernel_implicit_bump4096_traffic.json"),
                  "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
                  "elab": os.path.join(ROOT, "profiles", "elab_step_kernel_lake4096_traffic.json")}
+
+
+def roofline_of(bytes_per_launch: float, flop_per_launch: float, launch_s: float, traffic):
+    """Roofline of the dominant kernel from its algorithmic bytes and FP32
+    operations per launch: HBM-bound where the arithmetic intensity lies
+    below the ridge point (peak FP32 rate over peak HBM rate, 9.8 FLOP/B),
+    ALU-bound above it.  Also returns the achieved FP32 rate in TFLOP/s."""
+    gbs = bytes_per_launch / launch_s / 1e9
+    tfl = flop_per_launch / launch_s / 1e12
+    if flop_per_launch / bytes_per_launch < FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    else:
+        r = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
+    return r, round(tfl, 2)
 
 
 def measured_traffic(nodes: int, key):
@@ -172,17 +189,10 @@ def main():
     # + 1/(1+kappa), kappa_x, kappa_y; + the low part of eta read and written
     bpl = BYTES_PER_LUP + (12 if args.implicit else 0) + (8 if args.compensated else 0)
     gbs = bpl * nodes / launch_s / 1e9
-    traffic = None if args.compensated else measured_traffic(nodes, ("implicit" if tb == 1 else None) if args.implicit
-                                                             else tb)
-    if tb == 1:
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
-    else:
-        # two steps per HBM pass: the kernel is bound by vector ALU issue
-        flop = FLOP_PER_LUP[spec.chezy > 0] + (FLOP_IMPLICIT if args.implicit else 0)
-        tfl = flop * 2 * nodes / launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": traffic}
+    traffic = None if args.compensated else measured_traffic(nodes, ("implicit" if tb == 1 else "implicit2")
+                                                             if args.implicit else tb)
+    flop = FLOP_PER_LUP[spec.chezy > 0] + (FLOP_IMPLICIT if args.implicit else 0)
+    roofline, tfl = roofline_of(bpl * nodes, flop * tb * nodes, launch_s, traffic)
     out = {
         "metric": "MLUPS",
         "value": round(mlups, 1),
@@ -200,7 +210,7 @@ def main():
                    "tile_rows": grid.exec_opts().tile_rows, "blocks_per_cu": grid.exec_opts().blocks_per_cu,
                    "tblock": grid.exec_opts().tblock, "hbar": "implicit" if args.implicit else "eq_h-bar",
                    "surface": "compensated" if args.compensated else "fp32",
-                   "autotuned": tuned is not None, "graph": not args.no_graph,
+                   "autotuned": tuned is not None, "graph": not args.no_graph, "fp32_TFLOPs": tfl,
                    # per-step bytes of the one-step formulation x update rate
                    "effective_GBps": round(mlups * 1e6 * bpl / 1e9, 1),
                    "launch_GBps": round(gbs, 1),
@@ -244,20 +254,15 @@ def bench_ensemble(args, ctx, copy_gbps):
     tb = tuned["tblock"] if tuned else 1
     launch_s = tb * ev_ms / 1e3 / args.steps
     gbs = BYTES_PER_LUP * nodes / launch_s / 1e9
-    if tb == 1:
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    else:
-        tfl = FLOP_PER_LUP[True] * 2 * nodes / launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    roofline, tfl = roofline_of(BYTES_PER_LUP * nodes, FLOP_PER_LUP[True] * tb * nodes, launch_s, None)
     print(json.dumps({
         "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "ensemble_512_basins_64-512_seed1902", "basins": len(specs), "nodes": nodes,
                    "tuned": tuned, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1),
-                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1)},
+                   "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1),
+                   "fp32_TFLOPs": tfl},
         "roofline": roofline,
         "cpu_baseline": None}), flush=True)
 
@@ -296,15 +301,8 @@ def bench_geometry(args, ctx, copy_gbps):
     tb = opts["tblock"]
     launch_s = tb * ev_ms / 1e3 / args.steps
     bpl = (BYTES_PER_LUP + kind_bytes) * water
-    gbs = bpl / launch_s / 1e9
-    if tb == 1:
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(water, args.workload) if args.workload == "dish4096" else None}
-    else:
-        tfl = FLOP_PER_LUP[spec.chezy > 0] * 2 * water / launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    traffic = measured_traffic(water, args.workload) if (args.workload == "dish4096" and tb == 1) else None
+    roofline, tfl = roofline_of(bpl, FLOP_PER_LUP[spec.chezy > 0] * tb * water, launch_s, traffic)
     steady = None
     if spec.nodes <= 200 * 200:
         g = mlb.grid_from_spec(ctx, spec)
@@ -324,7 +322,7 @@ def bench_geometry(args, ctx, copy_gbps):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": spec.name, "nodes": spec.nodes, "water_nodes": water, "dx_m": spec.dx,
                       "nu": spec.nu, "exec": opts, "autotuned": tuned is not None, "nonfinite": d["nonfinite"],
-                      "launch_us": round(launch_s * 1e6, 3), "copy_probe_GBps": round(copy_gbps, 1),
+                      "launch_us": round(launch_s * 1e6, 3), "copy_probe_GBps": round(copy_gbps, 1), "fp32_TFLOPs": tfl,
                       "steady_1e-6": steady},
            "roofline": roofline}
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(spec, args.cpu_seconds)
