@@ -102,7 +102,7 @@ hipError_t launch_elab_dist(const ElabDev& D, int rd, float* out, hipStream_t s)
 // tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
 // of kStripOut2 columns, no diag.  masked: the tile list may hold
 // TILE_MASKED tiles; implicit: every basin has the implicit link-depth
-// planes; comp: every basin has a compensated surface (all one-step only);
+// planes; comp: every basin has a compensated surface (one step only);
 // closed: no basin has an open (DEPTH or DISCHARGE) edge, so the two-step
 // kernel is the one without the open-edge logic.
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
