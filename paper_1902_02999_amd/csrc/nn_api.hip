@@ -93,6 +93,12 @@ void net_free(mlb_net* n)
     n->allocs.clear();
 }
 
+// Pixel chunks of the bias-gradient sums (partials of kBiasChunks x channels)
+// and of the head's weight gradient (kHeadChunks x out x in, in the split-K
+// buffer; its bias partials use the bias buffer).
+constexpr int kBiasChunks = 1024;
+constexpr int kHeadChunks = 2048;
+
 int nsplit_for(const Layer& ly, int64_t npix)
 {
     const int per = (ly.cout / 32) * 9 * (ly.cin / 32);
@@ -188,10 +194,10 @@ mlb_status build(mlb_net* n)
         const int64_t P = (int64_t)px(lev);
         wl = std::max(wl, (size_t)nsplit_for(ly, P) * ly.cout * 9 * ly.cin);
     }
-    wl = std::max(wl, (size_t)256 * c.out_ch * n->ch(0));
+    wl = std::max(wl, (size_t)kHeadChunks * c.out_ch * n->ch(0));
     n->wpart_len = wl;
     CHK(dalloc(n, &n->wpart, wl));
-    CHK(dalloc(n, &n->cpart, (size_t)256 * std::max(n->ch(Lv - 1), c.out_ch)));
+    CHK(dalloc(n, &n->cpart, std::max((size_t)kBiasChunks * n->ch(Lv - 1), (size_t)kHeadChunks * c.out_ch)));
     CHK(dalloc(n, &n->lpart, (px(0) * c.out_ch + 255) / 256 + 1));
     CHK(dalloc(n, &n->dloss, 1));
     CHK(dalloc(n, &n->xstage, (size_t)c.height * c.width * nn::kNetFeatures));
@@ -236,7 +242,7 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     const int h = n->hh(lev), w = n->ww(lev);
     const int64_t P = (int64_t)nb * h * w;
     HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->dzf, s));
-    HIPCHK(nn::chan_sum(n->dzf, P, ly.cout, ly.cout, n->cpart, 256, n->grad + ly.boff, s));
+    HIPCHK(nn::chan_sum(n->dzf, P, ly.cout, ly.cout, n->cpart, kBiasChunks, n->grad + ly.boff, s));
     nn::WgradArgs g{};
     g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff;
     g.n = nb; g.h = h; g.w = w; g.cin = ly.cin; g.cout = ly.cout;
@@ -297,7 +303,7 @@ mlb_status backward(mlb_net* n, int nb)
     hipStream_t s = n->ctx->stream;
     const int64_t P0 = (int64_t)nb * c.height * c.width;
     const Layer& hd = n->L[n->head()];
-    HIPCHK(nn::head_back(n->g_y, n->decb[0], P0, hd.cout, hd.cin, n->theta + hd.woff, n->g_decb[0], n->wpart, 256,
+    HIPCHK(nn::head_back(n->g_y, n->decb[0], P0, hd.cout, hd.cin, n->theta + hd.woff, n->g_decb[0], n->wpart, kHeadChunks,
                          n->grad + hd.woff, n->grad + hd.boff, n->cpart, s));
     for (int l = 0; l <= Lv - 2; ++l) {
         const int cl = n->ch(l), cu = n->ch(l + 1);

@@ -12,6 +12,7 @@
 //   A (16 x 32):  lane holds A[l16][8 lq .. 8 lq + 7]
 //   B (32 x 16):  lane holds B[8 lq .. 8 lq + 7][l16]
 //   D (16 x 16):  lane holds D[4 lq .. 4 lq + 3][l16]
+#include <algorithm>
 #include <cmath>
 
 #include "nn_internal.h"
@@ -43,61 +44,61 @@ __device__ __forceinline__ bf16x8 zero8()
 
 // ------------------------------------------------------------------ conv 3x3
 // Y[p][n] = act(bias[n] + sum_{t,c} X[p + off_t][c] W[n][t][c]); one wave
-// computes 32 consecutive pixels of one image row x 32 output channels.
-// OUT_F32: FP32 output (optionally accumulated into), else BF16.
-template <bool OUT_F32>
+// computes 16 MB consecutive pixels of one image row x 16 NB output channels
+// (MB, NB in {2, 4}: each A fragment then serves NB products and each B
+// fragment MB).  Every output sums its taps and channel blocks in the same
+// order for any MB, NB.  OUT_F32: FP32 output (optionally accumulated into),
+// else BF16.
+template <bool OUT_F32, int MB, int NB>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
 {
+    constexpr int PT = 16 * MB, NT = 16 * NB;
     const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int ntile = a.cout / 32;
-    const int total = a.n * a.h * (a.w / 32) * ntile;
+    const int ntile = a.cout / NT, xtiles = a.w / PT;
+    const int total = a.n * a.h * xtiles * ntile;
     if (wave >= total) return;
     const int nt = wave % ntile;
-    const int pt = wave / ntile;            // pixel tile: 32 pixels of one row
-    const int xt = pt % (a.w / 32);
-    const int row = pt / (a.w / 32);        // image * h + y
+    const int pt = wave / ntile;            // pixel tile: PT pixels of one row
+    const int xt = pt % xtiles;
+    const int row = pt / xtiles;            // image * h + y
     const int y = row % a.h, img = row / a.h;
-    const int x0 = xt * 32, n0 = nt * 32;
+    const int x0 = xt * PT, n0 = nt * NT;
 
-    f32x4 acc[2][2];
+    f32x4 acc[MB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         const int yy = y + dy;
         const bool rowok = yy >= 0 && yy < a.h;
+        const __bf16* xrow = a.x + ((size_t)img * a.h + (rowok ? yy : 0)) * a.w * a.ldx + a.xoff + lq * 8;
         for (int c0 = 0; c0 < a.cin; c0 += 32) {
-            bf16x8 A[2], Bm[2];
+            bf16x8 A[MB], Bm[NB];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
+            for (int mb = 0; mb < MB; ++mb) {
                 const int xx = x0 + mb * 16 + l16 + dx;
-                if (rowok && xx >= 0 && xx < a.w) {
-                    const size_t p = ((size_t)img * a.h + yy) * a.w + xx;
-                    A[mb] = load8(a.x + p * a.ldx + a.xoff + c0 + lq * 8);
-                } else {
-                    A[mb] = zero8();
-                }
+                A[mb] = (rowok && xx >= 0 && xx < a.w) ? load8(xrow + (size_t)xx * a.ldx + c0) : zero8();
             }
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
+            for (int nb = 0; nb < NB; ++nb) {
                 const int n = n0 + nb * 16 + l16;
                 Bm[nb] = load8(a.wt + ((size_t)n * 9 + t) * a.cin + c0 + lq * 8);
             }
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
         }
     }
     // epilogue: D[mb][nb] lane holds pixels x0 + 16 mb + 4 lq + i, channel n0 + 16 nb + l16
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
+        for (int nb = 0; nb < NB; ++nb) {
             const int n = n0 + nb * 16 + l16;
             const float bn = a.bias ? a.bias[n] : 0.0f;
 #pragma unroll
@@ -151,14 +152,17 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
 #pragma unroll
             for (int e = 0; e < 8; ++e) A[mb][e] = a.dz[(p0 + lq * 8 + e) * a.cout + n];
         }
-        // B (K = pixels, cols c): X at the tap-shifted pixel (zero outside the image)
+        // B (K = pixels, cols c): X at the tap-shifted pixel (zero outside the
+        // image).  The width is a multiple of 32, so the chunk lies in one row.
+        const int64_t ry = p0 / a.w;
+        const int xb = (int)(p0 - ry * a.w) + lq * 8 + dx;
+        const int yy = (int)(ry % a.h) + dy;
+        const bool rowok = yy >= 0 && yy < a.h;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t p = p0 + lq * 8 + e;
-            const int xx = (int)(p % a.w) + dx;
-            const int64_t ry = p / a.w;
-            const int yy = (int)(ry % a.h) + dy;
-            const bool ok = xx >= 0 && xx < a.w && yy >= 0 && yy < a.h;
+            const int xx = xb + e;
+            const bool ok = rowok && xx >= 0 && xx < a.w;
             const int64_t q = p + (int64_t)dy * a.w + dx;
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
@@ -184,43 +188,65 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
             }
 }
 
-// Sum of nsplit partial arrays in a fixed order, written (not added) to dst.
-__global__ void sum_splits_kernel(const float* __restrict__ part, int nsplit, size_t len,
-                                  float* __restrict__ dst)
+// Column sums in a fixed order: out[y][j] = sum over rows i of chunk y
+// (rows y chunk .. min((y+1) chunk, nrows) - 1) of a[i ld + j], j < ncols.
+// A block covers kColSumCols consecutive columns (fewer when ncols is
+// smaller) with the rest of its 256 threads as row lanes: lane l sums rows
+// l, l + lanes, ... of the chunk, then lane 0 adds the lanes' sums in lane
+// order.  Serves the split-K weight gradients and the bias gradients.
+constexpr int kColSumCols = 32;
+__global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ a, int64_t nrows, int64_t ncols,
+                                                      int64_t ld, int64_t chunk, float* __restrict__ out)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
+    __shared__ float red[256];
+    const int cw = (int)min<int64_t>(ncols, kColSumCols);
+    const int lanes = 256 / cw;
+    const int t = threadIdx.x, jl = t % cw, rl = t / cw;
+    const int64_t j = (int64_t)blockIdx.x * cw + jl;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min<int64_t>(r0 + chunk, nrows);
+    const bool act = rl < lanes && j < ncols;
     float s = 0.0f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + i];
-    dst[i] = s;
-}
-
-// Per-channel sums over pixels (bias gradients): part[chunk][c] then a fixed-order sum.
-__global__ void chan_sum_partial_kernel(const float* __restrict__ g, int64_t npix, int c, int ld,
-                                        int chunk, float* __restrict__ part)
-{
-    const int ch = threadIdx.x + blockIdx.y * blockDim.x;
-    if (ch >= c) return;
-    const int64_t b = (int64_t)blockIdx.x * chunk, e = min<int64_t>(b + chunk, npix);
-    float s = 0.0f;
-    for (int64_t p = b; p < e; ++p) s += g[p * ld + ch];
-    part[(size_t)blockIdx.x * c + ch] = s;
+    if (act)
+        for (int64_t i = r0 + rl; i < r1; i += lanes) s += a[i * ld + j];
+    red[t] = s;
+    __syncthreads();
+    if (act && rl == 0) {
+        for (int k = 1; k < lanes; ++k) s += red[t + k * cw];
+        out[(int64_t)blockIdx.y * ncols + j] = s;
+    }
 }
 
 // ------------------------------------------------------------------ elementwise
 // dz (BF16 and FP32, contiguous [p][c]) = dy (FP32, stride ldd at doff) where
 // the activation y (BF16, stride ldy at yoff) > 0.
+// One thread per 8 channels of a pixel (channel counts, strides and offsets
+// are multiples of 8: 16-byte BF16 and 32-byte FP32 accesses).
 __global__ void relu_mask_kernel(const float* __restrict__ dy, int ldd, int doff, const __bf16* __restrict__ y,
                                  int ldy, int yoff, int64_t npix, int c, __bf16* __restrict__ dz,
                                  float* __restrict__ dzf)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npix * c) return;
-    const int64_t p = i / c;
-    const int ch = (int)(i % c);
-    const float v = (float)y[p * ldy + yoff + ch] > 0.0f ? dy[p * ldd + doff + ch] : 0.0f;
-    dz[i] = (__bf16)v;
-    dzf[i] = v;
+    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8 = c / 8;
+    if (i8 >= npix * c8) return;
+    const int64_t p = i8 / c8;
+    const int ch = (int)(i8 - p * c8) * 8;
+    const bf16x8 yv = load8(y + p * ldy + yoff + ch);
+    const f32x4* d = (const f32x4*)(dy + p * ldd + doff + ch);
+    const f32x4 d0 = d[0], d1 = d[1];
+    f32x4 o0, o1;
+    bf16x8 ob;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        o0[e] = (float)yv[e] > 0.0f ? d0[e] : 0.0f;
+        o1[e] = (float)yv[e + 4] > 0.0f ? d1[e] : 0.0f;
+        ob[e] = (__bf16)o0[e];
+        ob[e + 4] = (__bf16)o1[e];
+    }
+    const int64_t o = i8 * 8;
+    *(bf16x8*)(dz + o) = ob;
+    f32x4* of = (f32x4*)(dzf + o);
+    of[0] = o0;
+    of[1] = o1;
 }
 
 // Rotated, transposed weights for the data gradient: wr[c][t][n] = w[n][8 - t][c].
@@ -237,63 +263,83 @@ __global__ void weight_flip_kernel(const __bf16* __restrict__ w, int cout, int c
 __global__ void pool2_kernel(const __bf16* __restrict__ x, int ldx, int xoff, int n, int h, int w, int c,
                              __bf16* __restrict__ y)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ho = h / 2, wo = w / 2;
-    if (i >= (int64_t)n * ho * wo * c) return;
-    const int ch = (int)(i % c);
-    int64_t r = i / c;
+    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 8 channels per thread
+    const int ho = h / 2, wo = w / 2, c8 = c / 8;
+    if (i8 >= (int64_t)n * ho * wo * c8) return;
+    int64_t r = i8 / c8;
+    const int ch = (int)(i8 - r * c8) * 8;
     const int xo = (int)(r % wo); r /= wo;
     const int yo = (int)(r % ho);
     const int img = (int)(r / ho);
-    auto at = [&](int yy, int xx) { return (float)x[(((int64_t)img * h + yy) * w + xx) * ldx + xoff + ch]; };
-    const float s = (at(2 * yo, 2 * xo) + at(2 * yo, 2 * xo + 1)) + (at(2 * yo + 1, 2 * xo) + at(2 * yo + 1, 2 * xo + 1));
-    y[i] = (__bf16)(0.25f * s);
+    auto at = [&](int yy, int xx) { return load8(x + (((int64_t)img * h + yy) * w + xx) * ldx + xoff + ch); };
+    const bf16x8 a = at(2 * yo, 2 * xo), b = at(2 * yo, 2 * xo + 1), cc = at(2 * yo + 1, 2 * xo),
+                 d = at(2 * yo + 1, 2 * xo + 1);
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        o[e] = (__bf16)(0.25f * (((float)a[e] + (float)b[e]) + ((float)cc[e] + (float)d[e])));
+    *(bf16x8*)(y + i8 * 8) = o;
 }
 
 // dx[fine] (+)= dy[coarse] / 4; dx has channel stride ldx at offset xoff
 __global__ void pool2_back_kernel(const float* __restrict__ dy, int n, int h, int w, int c,
                                   float* __restrict__ dx, int ldx, int xoff, int accumulate)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n * h * w * c) return;
-    const int ch = (int)(i % c);
-    const int64_t r0 = i / c;
+    const int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 4 channels per thread
+    const int c4 = c / 4;
+    if (i4 >= (int64_t)n * h * w * c4) return;
+    const int64_t r0 = i4 / c4;
+    const int ch = (int)(i4 - r0 * c4) * 4;
     int64_t r = r0;
     const int xx = (int)(r % w); r /= w;
     const int yy = (int)(r % h);
     const int img = (int)(r / h);
-    const float v = 0.25f * dy[(((int64_t)img * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch];
-    float* o = dx + r0 * ldx + xoff + ch;
-    *o = accumulate ? *o + v : v;
+    const f32x4 g = *(const f32x4*)(dy + (((int64_t)img * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch);
+    f32x4* o = (f32x4*)(dx + r0 * ldx + xoff + ch);
+    f32x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = 0.25f * g[e];
+    if (accumulate) {
+        const f32x4 old = *o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = old[e] + v[e];
+    }
+    *o = v;
 }
 
 // nearest x2: y[fine] = x[coarse]
 __global__ void up2_kernel(const __bf16* __restrict__ x, int n, int h, int w, int c, __bf16* __restrict__ y)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int hf = 2 * h, wf = 2 * w;
-    if (i >= (int64_t)n * hf * wf * c) return;
-    const int ch = (int)(i % c);
-    int64_t r = i / c;
+    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 8 channels per thread
+    const int hf = 2 * h, wf = 2 * w, c8 = c / 8;
+    if (i8 >= (int64_t)n * hf * wf * c8) return;
+    int64_t r = i8 / c8;
+    const int ch = (int)(i8 - r * c8) * 8;
     const int xx = (int)(r % wf); r /= wf;
     const int yy = (int)(r % hf);
     const int img = (int)(r / hf);
-    y[i] = x[(((int64_t)img * h + yy / 2) * w + xx / 2) * c + ch];
+    *(bf16x8*)(y + i8 * 8) = load8(x + (((int64_t)img * h + yy / 2) * w + xx / 2) * c + ch);
 }
 
 // dx[coarse] = sum of the 4 fine gradients
 __global__ void up2_back_kernel(const float* __restrict__ dy, int n, int h, int w, int c, float* __restrict__ dx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n * h * w * c) return;
-    const int ch = (int)(i % c);
-    int64_t r = i / c;
+    const int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 4 channels per thread
+    const int c4 = c / 4;
+    if (i4 >= (int64_t)n * h * w * c4) return;
+    int64_t r = i4 / c4;
+    const int ch = (int)(i4 - r * c4) * 4;
     const int xx = (int)(r % w); r /= w;
     const int yy = (int)(r % h);
     const int img = (int)(r / h);
     const int wf = 2 * w;
-    auto at = [&](int fy, int fx) { return dy[(((int64_t)img * 2 * h + fy) * wf + fx) * c + ch]; };
-    dx[i] = (at(2 * yy, 2 * xx) + at(2 * yy, 2 * xx + 1)) + (at(2 * yy + 1, 2 * xx) + at(2 * yy + 1, 2 * xx + 1));
+    auto at = [&](int fy, int fx) { return *(const f32x4*)(dy + (((int64_t)img * 2 * h + fy) * wf + fx) * c + ch); };
+    const f32x4 a = at(2 * yy, 2 * xx), b = at(2 * yy, 2 * xx + 1), cc = at(2 * yy + 1, 2 * xx),
+                d = at(2 * yy + 1, 2 * xx + 1);
+    f32x4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = (a[e] + b[e]) + (cc[e] + d[e]);
+    *(f32x4*)(dx + i4 * 4) = o;
 }
 
 // ------------------------------------------------------------------ head (1x1), loss
@@ -305,7 +351,11 @@ __global__ void head_kernel(const __bf16* __restrict__ x, int64_t npix, int cin,
     if (p >= npix) return;
     for (int o = 0; o < cout; ++o) {
         float s = b[o];
-        for (int c = 0; c < cin; ++c) s = __builtin_fmaf((float)x[p * cin + c], w[o * cin + c], s);
+        for (int c8 = 0; c8 < cin; c8 += 8) {   // cin: a multiple of 8
+            const bf16x8 v = load8(x + p * cin + c8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s = __builtin_fmaf((float)v[e], w[o * cin + c8 + e], s);
+        }
         y[p * cout + o] = s;
     }
 }
@@ -358,12 +408,21 @@ __global__ void mse_kernel(const float* __restrict__ y, const float* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void sum_f64_kernel(const double* __restrict__ part, int n, double scale, double* __restrict__ out)
+// One block of 256 threads: thread t sums part[t], part[t + 256], ..., then a
+// fixed-order tree over the threads.
+__global__ __launch_bounds__(256) void sum_f64_kernel(const double* __restrict__ part, int n, double scale,
+                                                      double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[256];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // ------------------------------------------------------------------ AdamW
@@ -406,11 +465,31 @@ __global__ void pack_input_kernel(const float* __restrict__ x, int64_t npix, int
 // ------------------------------------------------------------------ launchers
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// out[y][j] for nchunk row chunks of a [nrows][ld] array (see col_sum_kernel).
+static void col_sum(const float* a, int64_t nrows, int64_t ncols, int64_t ld, int nchunk, float* out, hipStream_t s)
+{
+    const int64_t chunk = (nrows + nchunk - 1) / nchunk;
+    const int cw = (int)std::min<int64_t>(ncols, kColSumCols);
+    hipLaunchKernelGGL(col_sum_kernel, dim3(blocks_for(ncols, cw), (unsigned)((nrows + chunk - 1) / chunk)), dim3(256),
+                       0, s, a, nrows, ncols, ld, chunk, out);
+}
+
+template <int MB, int NB>
+static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
+{
+    const int64_t waves = (int64_t)a.n * a.h * (a.w / (16 * MB)) * (a.cout / (16 * NB));
+    if (a.yf) hipLaunchKernelGGL((conv3x3_kernel<true, MB, NB>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv3x3_kernel<false, MB, NB>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+}
+
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
 {
-    const int64_t waves = (int64_t)a.n * a.h * (a.w / 32) * (a.cout / 32);
-    if (a.yf) hipLaunchKernelGGL(conv3x3_kernel<true>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(conv3x3_kernel<false>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    // widths are multiples of 32 and channel counts of 32 (checked at net creation)
+    const bool wide = a.w % 64 == 0, deep = a.cout % 64 == 0;
+    if (wide && deep) conv3x3_launch<4, 4>(a, s);
+    else if (wide) conv3x3_launch<4, 2>(a, s);
+    else if (deep) conv3x3_launch<2, 4>(a, s);
+    else conv3x3_launch<2, 2>(a, s);
     return hipGetLastError();
 }
 
@@ -418,23 +497,25 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
 {
     const int64_t waves = (int64_t)(a.cout / 32) * 9 * (a.cin / 32) * a.nsplit;
     hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
-    const size_t len = (size_t)a.cout * 9 * a.cin;
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, a.part, a.nsplit, len, dw);
+    const int64_t len = (int64_t)a.cout * 9 * a.cin;
+    col_sum(a.part, a.nsplit, len, len, 1, dw, s);
     return hipGetLastError();
 }
 
 hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, int nchunk, float* dst, hipStream_t s)
 {
-    const int chunk = (int)((npix + nchunk - 1) / nchunk);
-    hipLaunchKernelGGL(chan_sum_partial_kernel, dim3(nchunk, (c + 255) / 256), dim3(256), 0, s, g, npix, c, ld, chunk, part);
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(c, 256)), dim3(256), 0, s, part, nchunk, (size_t)c, dst);
+    // part holds nchunk x c partial sums (the chunk count can come out lower)
+    col_sum(g, npix, c, ld, nchunk, part, s);
+    const int64_t chunk = (npix + nchunk - 1) / nchunk;
+    col_sum(part, (npix + chunk - 1) / chunk, c, c, 1, dst, s);
     return hipGetLastError();
 }
 
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
                      __bf16* dz, float* dzf, hipStream_t s)
 {
-    hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c, 256)), dim3(256), 0, s, dy, ldd, doff, y, ldy,
+    if (c % 8 || ldd % 4 || doff % 4 || ldy % 8 || yoff % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c / 8, 256)), dim3(256), 0, s, dy, ldd, doff, y, ldy,
                        yoff, npix, c, dz, dzf);
     return hipGetLastError();
 }
@@ -447,7 +528,8 @@ hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream
 
 hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c, __bf16* y, hipStream_t s)
 {
-    hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * c, 256)), dim3(256), 0, s,
+    if (c % 8 || ldx % 8 || xoff % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * c / 8, 256)), dim3(256), 0, s,
                        x, ldx, xoff, n, h, w, c, y);
     return hipGetLastError();
 }
@@ -455,20 +537,23 @@ hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c,
 hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, int ldx, int xoff, int accumulate,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL(pool2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c, 256)), dim3(256), 0, s,
+    if (c % 4 || ldx % 4 || xoff % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c / 4, 256)), dim3(256), 0, s,
                        dy, n, h, w, c, dx, ldx, xoff, accumulate);
     return hipGetLastError();
 }
 
 hipError_t up2(const __bf16* x, int n, int h, int w, int c, __bf16* y, hipStream_t s)
 {
-    hipLaunchKernelGGL(up2_kernel, dim3(blocks_for((int64_t)n * 4 * h * w * c, 256)), dim3(256), 0, s, x, n, h, w, c, y);
+    if (c % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(up2_kernel, dim3(blocks_for((int64_t)n * 4 * h * w * c / 8, 256)), dim3(256), 0, s, x, n, h, w, c, y);
     return hipGetLastError();
 }
 
 hipError_t up2_back(const float* dy, int n, int h, int w, int c, float* dx, hipStream_t s)
 {
-    hipLaunchKernelGGL(up2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c, 256)), dim3(256), 0, s, dy, n, h, w, c, dx);
+    if (c % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(up2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c / 4, 256)), dim3(256), 0, s, dy, n, h, w, c, dx);
     return hipGetLastError();
 }
 
@@ -485,8 +570,7 @@ hipError_t head_back(const float* dy, const __bf16* x, int64_t npix, int cout, i
     const int chunk = (int)((npix + nchunk - 1) / nchunk);
     hipLaunchKernelGGL(head_wgrad_partial_kernel, dim3(nchunk, (cout * cin + 255) / 256), dim3(256), 0, s,
                        dy, x, npix, cout, cin, chunk, part);
-    hipLaunchKernelGGL(sum_splits_kernel, dim3(blocks_for(cout * cin, 256)), dim3(256), 0, s, part, nchunk,
-                       (size_t)cout * cin, dw);
+    col_sum(part, nchunk, (int64_t)cout * cin, (int64_t)cout * cin, 1, dw, s);
     return chan_sum(dy, npix, cout, cout, bpart, nchunk, db, s);
 }
 
@@ -495,7 +579,7 @@ hipError_t mse(const float* y, const float* t, const float* mask, int64_t npix, 
 {
     const unsigned nb = blocks_for(npix * c, 256);
     hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, y, t, mask, npix, c, inv_cnt, dy, part);
-    hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(64), 0, s, part, (int)nb, inv_cnt, out);
+    hipLaunchKernelGGL(sum_f64_kernel, dim3(1), dim3(256), 0, s, part, (int)nb, inv_cnt, out);
     return hipGetLastError();
 }
 
