@@ -110,7 +110,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (by default it picks tile rows and the CU cap before timing)")
     ap.add_argument("--workload", default="bump",
-                    choices=["bump", "ensemble", "lake_steady", "warm_start", "dish", "dish4096", "hump", "elab"],
+                    choices=["bump", "ensemble", "lake_steady", "warm_start", "dish", "dish4096", "hump", "elab",
+                             "net"],
                     help="bump: 4096^2 channel (default line); ensemble: 512 basins 64^2..512^2 in "
                          "one launch per step; lake_steady: 256^2 wind lake to residual 1e-6; "
                          "warm_start: learned warm start vs cold start on held-out 256^2 basins; "
@@ -118,7 +119,8 @@ def main():
                          "time to steady state; dish4096: the same basin on 4096^2 nodes; "
                          "hump: the paper's 2D hump channel (200^2) with its time to steady state; "
                          "elab: the eLABSWE baseline (nine stored distributions) against the streaming-only "
-                         "step on a closed 4096^2 basin")
+                         "step on a closed 4096^2 basin; net: the warm-start network's forward pass and "
+                         "training step (256^2, batch 8) against the BF16 MFMA roofline")
     ap.add_argument("--implicit", action="store_true",
                     help="bump: the implicit link depth (new-time depth at the node; 12 more bytes per node "
                          "per pass, 5 more FP32 operations per update)")
@@ -156,6 +158,8 @@ def main():
         return bench_geometry(args, ctx, copy_gbps)
     if args.workload == "elab":
         return bench_elab(args, ctx, copy_gbps)
+    if args.workload == "net":
+        return bench_net(args, ctx)
     spec = wl.bump_channel(args.n)
     spec.hbar_implicit = args.implicit
     spec.compensated = args.compensated
@@ -433,6 +437,77 @@ def bench_lake_steady(args, ctx):
                       "higher_is_better": False, "converged": ok, "steps": d["step"],
                       "residual": d["residual"], "t_model_s": d["t"],
                       "config": {"workload": spec.name, "nodes": spec.nodes, "exec": g_opts}}), flush=True)
+
+
+BF16_PEAK_TFLOPS = 2500.0       # MI355X dense BF16 MFMA, published
+
+
+def net_layers(h: int, w: int, in_ch: int = 32, base_ch: int = 32, levels: int = 4, out_ch: int = 3):
+    """(pixels, cin, cout, k) of every layer of the warm-start network in
+    forward order: two 3x3 convolutions per encoder level, then per decoder
+    level one after the upsampling and two after the skip concatenation, and
+    the 1x1 head."""
+    ch = [base_ch << l for l in range(levels)]
+    px = [(h >> l) * (w >> l) for l in range(levels)]
+    out, cin = [], in_ch
+    for l in range(levels):
+        out += [(px[l], cin, ch[l], 3), (px[l], ch[l], ch[l], 3)]
+        cin = ch[l]
+    for l in range(levels - 2, -1, -1):
+        out += [(px[l], ch[l + 1], ch[l], 3), (px[l], 2 * ch[l], ch[l], 3), (px[l], ch[l], ch[l], 3)]
+    out.append((px[0], ch[0], out_ch, 1))
+    return out
+
+
+def bench_net(args, ctx):
+    """Forward pass and AdamW training step of the warm-start network at
+    256^2, batch 8, random weights and inputs.  FLOPs count the
+    convolutions' multiply-adds (2 per MAC); the roofline floor of a pass is
+    the sum over layers of max(FLOPs / BF16 MFMA peak, activation bytes /
+    HBM peak), activations in BF16, read once and written once."""
+    import torch
+    from paper_1902_02999_amd import mlb
+    n, hw = 8, 256
+    net = mlb.Net(ctx, hw, hw, base_ch=32, levels=4, in_ch=32, max_batch=n, seed=1)
+    gen = torch.Generator().manual_seed(0)
+    x = torch.randn((n, hw, hw, mlb.NET_FEATURES), generator=gen).cuda()
+    t = torch.randn((n, hw, hw, 3), generator=gen).cuda()
+    y = torch.empty((n, hw, hw, 3), device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(3):
+        net.forward(x, n, y)
+    ctx.sync()
+    reps = max(10, args.steps // 100)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x, n, y)
+    ctx.sync()
+    fwd = (time.perf_counter() - t0) / reps
+    net.train(x, t, n, 1, n, 1e-4)
+    ctx.sync()
+    t0 = time.perf_counter()
+    net.train(x, t, n, reps, n, 1e-4)
+    ctx.sync()
+    step = (time.perf_counter() - t0) / reps
+    net.close()
+    ctx.close()
+    flop, floor = 0.0, 0.0
+    for px, ci, co, k in net_layers(hw, hw):
+        f = 2.0 * n * px * k * k * ci * co
+        b = 2.0 * n * px * (ci + co)
+        flop += f
+        floor += max(f / (BF16_PEAK_TFLOPS * 1e12), b / (HBM_PEAK_GBS * 1e9))
+    tfl = flop / fwd / 1e12
+    print(json.dumps({
+        "metric": "TFLOP/s", "value": round(tfl, 1), "unit": "TFLOP/s", "n_gpus": 1, "steps": reps,
+        "warmup": 3, "ms_per_step": round(fwd * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulation)", "data": "synthetic",
+        "config": {"workload": "warm_start_net_256_batch8", "forward_gflop": round(flop / 1e9, 1),
+                   "forward_ms": round(fwd * 1e3, 3), "train_step_ms": round(step * 1e3, 3),
+                   "roofline_floor_ms": round(floor * 1e3, 4), "of_floor": round(floor / fwd, 4)},
+        "roofline": {"bound": "mfma", "achieved": round(tfl, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tfl / BF16_PEAK_TFLOPS, 4), "traffic": None},
+        "cpu_baseline": None}), flush=True)
 
 
 def bench_warm_start(args, ctx):
