@@ -43,27 +43,33 @@ __device__ __forceinline__ bf16x8 zero8()
 }
 
 // ------------------------------------------------------------------ conv 3x3
-// Y[p][n] = act(bias[n] + sum_{t,c} X[p + off_t][c] W[n][t][c]); one wave
-// computes 16 MB consecutive pixels of one image row x 16 NB output channels
-// (MB, NB in {2, 4}: each A fragment then serves NB products and each B
-// fragment MB).  Every output sums its taps and channel blocks in the same
-// order for any MB, NB.  OUT_F32: FP32 output (optionally accumulated into),
-// else BF16.
+// Y[p][n] = act(bias[n] + sum_{t,c} X[p + off_t][c] W[n][t][c]) as an
+// implicit GEMM on MFMA.  A workgroup of four waves computes kConvRows image
+// rows (one per wave) of PT = 16 MB pixels x NT = 16 NB output channels (MB,
+// NB in {2, 4}: each A fragment serves NB products and each B fragment MB).
+// Per block of 32 input channels the workgroup loads the rows' input with
+// its one-pixel halo, (kConvRows + 2) x (PT + 2) x 32 values (zero outside
+// the image), once into LDS; the nine taps then read their shifted A
+// fragments from there instead of from global memory.  Every
+// output sums over channel blocks, then taps, in that order.  OUT_F32: FP32
+// output (optionally accumulated into), else BF16.
+constexpr int kConvRows = 4;
 template <bool OUT_F32, int MB, int NB>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+__global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
 {
-    constexpr int PT = 16 * MB, NT = 16 * NB;
-    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int ntile = a.cout / NT, xtiles = a.w / PT;
-    const int total = a.n * a.h * xtiles * ntile;
-    if (wave >= total) return;
-    const int nt = wave % ntile;
-    const int pt = wave / ntile;            // pixel tile: PT pixels of one row
-    const int xt = pt % xtiles;
-    const int row = pt / xtiles;            // image * h + y
-    const int y = row % a.h, img = row / a.h;
-    const int x0 = xt * PT, n0 = nt * NT;
+    constexpr int PT = 16 * MB, NT = 16 * NB, TW = PT + 2;
+    constexpr int CHUNKS = (kConvRows + 2) * TW * 4;   // 16-byte chunks of 8 channels
+    __shared__ __attribute__((aligned(16))) __bf16 tile[(kConvRows + 2) * TW * 32];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    const int ntile = a.cout / NT, xtiles = a.w / PT, ygroups = (a.h + kConvRows - 1) / kConvRows;
+    int b = blockIdx.x;                     // (image, row group, pixel tile, channel tile), channels fastest
+    const int nt = b % ntile; b /= ntile;
+    const int xt = b % xtiles; b /= xtiles;
+    const int yg = b % ygroups;
+    const int img = b / ygroups;
+    const int x0 = xt * PT, n0 = nt * NT, y0 = yg * kConvRows;
+    const int y = y0 + wv;
+    const bool active = y < a.h;            // every wave still takes part in the loads and barriers
 
     f32x4 acc[MB][NB];
 #pragma unroll
@@ -71,30 +77,36 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const int yy = y + dy;
-        const bool rowok = yy >= 0 && yy < a.h;
-        const __bf16* xrow = a.x + ((size_t)img * a.h + (rowok ? yy : 0)) * a.w * a.ldx + a.xoff + lq * 8;
-        for (int c0 = 0; c0 < a.cin; c0 += 32) {
-            bf16x8 A[MB], Bm[NB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int xx = x0 + mb * 16 + l16 + dx;
-                A[mb] = (rowok && xx >= 0 && xx < a.w) ? load8(xrow + (size_t)xx * a.ldx + c0) : zero8();
-            }
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int n = n0 + nb * 16 + l16;
-                Bm[nb] = load8(a.wt + ((size_t)n * 9 + t) * a.cin + c0 + lq * 8);
-            }
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        for (int i = threadIdx.x; i < CHUNKS; i += 256) {
+            const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
+            const int yy = y0 + rr - 1, xx = x0 + px - 1;
+            bf16x8 v = zero8();
+            if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
+                v = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
+            *(bf16x8*)&tile[(rr * TW + px) * 32 + ch8 * 8] = v;
         }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3 - 1, dx = t % 3 - 1;
+                bf16x8 A[MB], Bm[NB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    A[mb] = *(const bf16x8*)&tile[((wv + 1 + dy) * TW + mb * 16 + l16 + 1 + dx) * 32 + lq * 8];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    Bm[nb] = load8(a.wt + ((size_t)(n0 + nb * 16 + l16) * 9 + t) * a.cin + c0 + lq * 8);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+            }
+        }
+        __syncthreads();
     }
-    // epilogue: D[mb][nb] lane holds pixels x0 + 16 mb + 4 lq + i, channel n0 + 16 nb + l16
+    if (!active) return;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -477,9 +489,10 @@ static void col_sum(const float* a, int64_t nrows, int64_t ncols, int64_t ld, in
 template <int MB, int NB>
 static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
 {
-    const int64_t waves = (int64_t)a.n * a.h * (a.w / (16 * MB)) * (a.cout / (16 * NB));
-    if (a.yf) hipLaunchKernelGGL((conv3x3_kernel<true, MB, NB>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((conv3x3_kernel<false, MB, NB>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    const int64_t blocks = (int64_t)a.n * ((a.h + kConvRows - 1) / kConvRows) * (a.w / (16 * MB)) *
+                           (a.cout / (16 * NB));
+    if (a.yf) hipLaunchKernelGGL((conv3x3_lds_kernel<true, MB, NB>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv3x3_lds_kernel<false, MB, NB>), dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
