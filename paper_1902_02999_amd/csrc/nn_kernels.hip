@@ -131,32 +131,37 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
 
 // ------------------------------------------------------------------ weight gradient
 // Partial dW over a pixel range: part[s][n][t][c] = sum_{p in chunk s} dz[p][n] X[p + off_t][c].
-// One wave: 32 output channels x (one tap, 32 input channels), K = pixels.
+// One wave: 32 output channels x (one tap row dy, its three taps dx = -1, 0, 1,
+// 32 input channels), K = pixels.  The dz fragment serves all three taps, and
+// each lane loads its ten input pixels (8 + the two neighbours) once for the
+// three shifted B fragments.
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
 {
     const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int ntile = a.cout / 32, ctile = a.cin / 32;
-    const int per_split = ntile * 9 * ctile;
+    const int per_split = ntile * 3 * ctile;
     if (wave >= per_split * a.nsplit) return;
     const int s = wave / per_split;
     int r = wave % per_split;
     const int ct = r % ctile; r /= ctile;
-    const int t = r % 9;
-    const int nt = r / 9;
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int ty = r % 3;                   // taps 3 ty .. 3 ty + 2
+    const int nt = r / 3;
+    const int dy = ty - 1;
     const int64_t nch = (int64_t)a.n * a.h * a.w / 32;                     // 32-pixel chunks
     const int64_t pbeg = nch * s / a.nsplit * 32, pend = nch * (s + 1) / a.nsplit * 32;
     const int n0 = nt * 32, c0 = ct * 32;
 
-    f32x4 acc[2][2];
+    f32x4 acc[3][2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
-        bf16x8 A[2], Bm[2];
+        bf16x8 A[2];
         // A (rows n, K = pixels): dz[p][n] for 8 consecutive pixels
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
@@ -167,37 +172,45 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
         // B (K = pixels, cols c): X at the tap-shifted pixel (zero outside the
         // image).  The width is a multiple of 32, so the chunk lies in one row.
         const int64_t ry = p0 / a.w;
-        const int xb = (int)(p0 - ry * a.w) + lq * 8 + dx;
+        const int xb = (int)(p0 - ry * a.w) + lq * 8 - 1;   // pixel of xv[.][0]
         const int yy = (int)(ry % a.h) + dy;
         const bool rowok = yy >= 0 && yy < a.h;
+        const int64_t q0 = p0 + lq * 8 - 1 + (int64_t)dy * a.w;
+        __bf16 xv[2][10];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t p = p0 + lq * 8 + e;
+        for (int e = 0; e < 10; ++e) {
             const int xx = xb + e;
             const bool ok = rowok && xx >= 0 && xx < a.w;
-            const int64_t q = p + (int64_t)dy * a.w + dx;
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const int c = c0 + nb * 16 + l16;
-                Bm[nb][e] = ok ? a.x[q * a.ldx + a.xoff + c] : (__bf16)0.0f;
-            }
+            for (int nb = 0; nb < 2; ++nb)
+                xv[nb][e] = ok ? a.x[(q0 + e) * a.ldx + a.xoff + c0 + nb * 16 + l16] : (__bf16)0.0f;
         }
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int d = 0; d < 3; ++d) {       // dx = d - 1
+            bf16x8 Bm[2];
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma(A[mb], Bm[nb], acc[mb][nb]);
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) Bm[nb][e] = xv[nb][e + d];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) acc[d][mb][nb] = mfma(A[mb], Bm[nb], acc[d][mb][nb]);
+        }
     }
     float* out = a.part + (size_t)s * a.cout * 9 * a.cin;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int n = n0 + mb * 16 + lq * 4 + i;
-                const int c = c0 + nb * 16 + l16;
-                out[((size_t)n * 9 + t) * a.cin + c] = acc[mb][nb][i];
-            }
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int n = n0 + mb * 16 + lq * 4 + i;
+                    const int c = c0 + nb * 16 + l16;
+                    out[((size_t)n * 9 + 3 * ty + d) * a.cin + c] = acc[d][mb][nb][i];
+                }
 }
 
 // Column sums in a fixed order: out[y][j] = sum over rows i of chunk y
@@ -508,7 +521,7 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
 
 hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
 {
-    const int64_t waves = (int64_t)(a.cout / 32) * 9 * (a.cin / 32) * a.nsplit;
+    const int64_t waves = (int64_t)(a.cout / 32) * 3 * (a.cin / 32) * a.nsplit;
     hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
     const int64_t len = (int64_t)a.cout * 9 * a.cin;
     col_sum(a.part, a.nsplit, len, len, 1, dw, s);
