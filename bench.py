@@ -31,7 +31,9 @@ FLOP_PER_LUP = {True: 104, False: 97}
 FLOP_IMPLICIT = 5              # implicit link depth: scale the increment, correct qx and qy (two FMAs)
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
-                 2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
+                 2: [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
+                     os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows17_traffic.json"),
+                     os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows20_traffic.json")],
                  "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
                  "implicit2": os.path.join(ROOT, "profiles", "step2_kernel_implicit_bump4096_traffic.json"),
                  "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
@@ -54,21 +56,26 @@ def roofline_of(bytes_per_launch: float, flop_per_launch: float, launch_s: float
     return r, round(tfl, 2)
 
 
-def measured_traffic(nodes: int, key):
+def measured_traffic(nodes: int, key, tile_rows=None):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when it was taken on a different
-    kernel source or problem size."""
+    rocprofv3 counter summaries, or None when none was taken on this kernel
+    source, problem size and (where the summary records it) tile height."""
     from paper_1902_02999_amd.profiling import kernel_sha
-    try:
-        with open(TRAFFIC_FILES[key]) as f:
-            t = json.load(f)
-        src = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", t.get("kernel_source", "mlb_kernels.hip"))
-        sha = kernel_sha(src)
-    except (OSError, ValueError, KeyError):
-        return None
-    if t.get("kernel_sha") != sha or t.get("nodes") != nodes:
-        return None
-    return t.get("bytes_per_launch")
+    files = TRAFFIC_FILES.get(key)
+    for path in ([files] if isinstance(files, str) else files or []):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+            src = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", t.get("kernel_source", "mlb_kernels.hip"))
+            sha = kernel_sha(src)
+        except (OSError, ValueError, KeyError):
+            continue
+        if t.get("kernel_sha") != sha or t.get("nodes") != nodes:
+            continue
+        if tile_rows is not None and t.get("tile_rows") not in (None, tile_rows):
+            continue
+        return t.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(spec, budget_s: float = 12.0):
@@ -194,7 +201,7 @@ def main():
     bpl = BYTES_PER_LUP + (12 if args.implicit else 0) + (8 if args.compensated else 0)
     gbs = bpl * nodes / launch_s / 1e9
     traffic = None if args.compensated else measured_traffic(nodes, ("implicit" if tb == 1 else "implicit2")
-                                                             if args.implicit else tb)
+                                                             if args.implicit else tb, grid.exec_opts().tile_rows)
     flop = FLOP_PER_LUP[spec.chezy > 0] + (FLOP_IMPLICIT if args.implicit else 0)
     roofline, tfl = roofline_of(bpl * nodes, flop * tb * nodes, launch_s, traffic)
     out = {
@@ -305,7 +312,8 @@ def bench_geometry(args, ctx, copy_gbps):
     tb = opts["tblock"]
     launch_s = tb * ev_ms / 1e3 / args.steps
     bpl = (BYTES_PER_LUP + kind_bytes) * water
-    traffic = measured_traffic(water, args.workload) if (args.workload == "dish4096" and tb == 1) else None
+    traffic = (measured_traffic(water, args.workload, opts["tile_rows"]) if (args.workload == "dish4096" and tb == 1)
+               else None)
     roofline, tfl = roofline_of(bpl, FLOP_PER_LUP[spec.chezy > 0] * tb * water, launch_s, traffic)
     steady = None
     if spec.nodes <= 200 * 200:

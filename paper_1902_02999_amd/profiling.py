@@ -96,6 +96,7 @@ def cmd_traffic(a):
     alg = a.bytes_per_unit * a.nodes
     src = os.path.join(HERE, "csrc", a.source)
     res = {"kernel": a.kernel, "kernel_source": a.source, "kernel_sha": kernel_sha(src), "nodes": a.nodes,
+           "tile_rows": a.tile_rows,
            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
            "bytes_per_launch": fetch_b + write_b, "algorithmic_bytes_per_launch": alg,
            "fetch_scale": sf, "write_scale": sw,
@@ -133,6 +134,7 @@ def main():
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--kernel", default="step_kernel")
+    t.add_argument("--tile-rows", type=int, default=None, help="tile rows of the profiled launches (recorded)")
     t.add_argument("--nodes", type=int, required=True)
     t.add_argument("--bytes-per-unit", type=int, default=28)
     t.add_argument("--source", default="mlb_kernels.hip", help="kernel source file under csrc/ (for its hash)")
