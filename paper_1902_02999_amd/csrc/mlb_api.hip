@@ -116,6 +116,10 @@ bool classify_tile(const mlb_grid* g, TileDev& t, int strip)
     return owned_water;
 }
 
+#ifndef MLB_COSTLY_FIRST
+#define MLB_COSTLY_FIRST 1
+#endif
+
 // Wave tiles of one basin: strips of `strip` output columns (62 for one step
 // per pass, 60 for two), tiles of `rows` rows.  The last strip / tile is
 // shifted inward so that edge extrapolation always finds its inner nodes in
@@ -134,6 +138,7 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
     // pass) and 9 % slower (one step).
     const int nx = g->p.nx, ny = g->p.ny;
     const int ty = std::max(4, rows);
+    const size_t first = out.size();
     for (int yo = 0; yo < ny; yo += ty) {
         int y0 = std::min(yo, std::max(0, ny - ty));
         if (strip == kStripOut2 && y0 == 1) y0 = 0;
@@ -150,6 +155,21 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
             out.push_back(t);
         }
     }
+#if MLB_COSTLY_FIRST
+    // Tiles on an edge or with a mask cost up to a few interior tiles each:
+    // dispatched first, they overlap the bulk of the pass instead of running
+    // alone at its end (tiles are independent within a pass).  Measured on the
+    // 4096^2 channel: 287 -> 310 GLUPS with two steps per pass.
+    const int k = strip == kStripOut2 ? 2 : 1;
+    const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
+    auto costly = [&](const TileDev& t) {
+        return (t.flags & TILE_MASKED) || (!px && (t.x0 < k || t.x0 + strip + k > nx)) ||
+               (!py && (t.y0 < k || t.y0 + t.rows + k > ny));
+    };
+    std::stable_partition(out.begin() + first, out.end(), costly);
+#else
+    (void)first;
+#endif
 }
 
 mlb_status check_stream(mlb_ctx* c)
