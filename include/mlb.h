@@ -160,8 +160,10 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
  * y0 .. y0 + rows - 1; it stores the nodes of columns max(x0, xo) ..
  * x0 + 61 - (k - 1) * 2 (below nx) and rows yo .. y0 + rows - 1.  flags bit 0:
  * the tile's window holds a WALL or SOLID node (masked kernel path).  Tiles
- * that would own only SOLID nodes are left out.  Writes at most `capacity`
- * tiles; *count receives the number of tiles.  No device memory is used. */
+ * that would own only SOLID nodes are left out.  The list is in dispatch
+ * order: tiles on a non-periodic edge or with the masked flag first, then the
+ * rest, each group band by band.  Writes at most `capacity` tiles; *count
+ * receives the number of tiles.  No device memory is used. */
 mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
                           int32_t tblock, int32_t* tiles, int64_t capacity, int64_t* count);
 

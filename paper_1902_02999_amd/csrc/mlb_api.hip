@@ -127,7 +127,8 @@ bool classify_tile(const mlb_grid* g, TileDev& t, int strip)
 // start at row 1: their first stage would then compute row 0 of an open S
 // edge, which waits for rows 1 and 2 (such a tile starts at row 0 instead).
 // With a mask, tiles are classified by classify_tile.
-void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out, int strip)
+void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& out, int strip,
+                bool costly_first = true)
 {
     // List order = dispatch order: row band by row band, so one workgroup's
     // waves take neighbouring strips of one band (contiguous row segments).
@@ -166,9 +167,9 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
         return (t.flags & TILE_MASKED) || (!px && (t.x0 < k || t.x0 + strip + k > nx)) ||
                (!py && (t.y0 < k || t.y0 + t.rows + k > ny));
     };
-    std::stable_partition(out.begin() + first, out.end(), costly);
+    if (costly_first) std::stable_partition(out.begin() + first, out.end(), costly);
 #else
-    (void)first;
+    (void)first; (void)costly_first;
 #endif
 }
 
@@ -528,7 +529,8 @@ mlb_status read_diag(mlb_ctx* c, Plan& P)
 
 namespace mlb {
 mlb_status grid_set_step(mlb_grid* g, int64_t s) { return set_step(g, s); }
-void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out) { make_tiles(g, 0, rows, out, kStripOut); }
+// (band order: the eLABSWE kernel measured 2.5 % slower with its edge tiles first)
+void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out) { make_tiles(g, 0, rows, out, kStripOut, false); }
 }  // namespace mlb
 
 // ====================================================================== C ABI

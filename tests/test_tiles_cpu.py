@@ -108,3 +108,25 @@ def test_size_limit_is_the_plane_addressing_limit():
         assert ((nx + 63) // 64 * 64) * ny >= (1 << 30)
         with pytest.raises(mlb.MlbError, match="too large"):
             mlb.plan_tiles(mlb.make_params(nx, ny, 1.0, 1.0, 2.0), 4096, 2)
+
+
+@pytest.mark.parametrize("tb", [1, 2])
+def test_costly_tiles_are_dispatched_first(tb):
+    """Edge and masked tiles lead the list (they overlap the pass instead of
+    forming its tail); each group keeps band order."""
+    k, strip = tb, STRIP[tb]
+    for nx, ny, edges, kind in ((300, 170, (wl.WALL,) * 4, None),
+                                (200, 200, (wl.WALL,) * 4, wl.circular_dish().kind),
+                                (130, 90, (wl.PERIODIC,) * 4, None)):
+        p = mlb.make_params(nx, ny, 1.0, 1.0, 2.0, edges)
+        t = mlb.plan_tiles(p, 9, tb, kind)
+        per = edges[0] == wl.PERIODIC
+        costly = [bool(x[5] & 1) or (not per and (x[0] < k or x[0] + strip + k > nx or x[1] < k
+                                                   or x[1] + x[2] + k > ny)) for x in t]
+        n = sum(costly)
+        assert all(costly[:n]) and not any(costly[n:])
+        for part in (t[:n], t[n:]):
+            keys = [(x[4], x[3]) for x in part]       # (band, strip) in list order
+            assert keys == sorted(keys)
+        if per:
+            assert n == 0
