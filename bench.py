@@ -31,9 +31,9 @@ FLOP_PER_LUP = {True: 104, False: 97}
 FLOP_IMPLICIT = 5              # implicit link depth: scale the increment, correct qx and qy (two FMAs)
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
-                 2: [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
-                     os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows17_traffic.json"),
-                     os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows20_traffic.json")],
+                 2: [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json")] +
+                    [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows%d_traffic.json" % r)
+                     for r in (14, 17, 20, 23, 26)],
                  "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
                  "implicit2": os.path.join(ROOT, "profiles", "step2_kernel_implicit_bump4096_traffic.json"),
                  "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
