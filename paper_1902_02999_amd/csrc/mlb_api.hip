@@ -120,6 +120,16 @@ bool classify_tile(const mlb_grid* g, TileDev& t, int strip)
 #define MLB_COSTLY_FIRST 1
 #endif
 
+// A tile whose window reaches a non-periodic edge, or holds a WALL or SOLID
+// node: it takes the kernels' boundary path.
+bool tile_costly(const mlb_grid* g, const TileDev& t, int strip)
+{
+    const int k = strip == kStripOut2 ? 2 : 1, nx = g->p.nx, ny = g->p.ny;
+    const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
+    return (t.flags & TILE_MASKED) || (!px && (t.x0 < k || t.x0 + strip + k > nx)) ||
+           (!py && (t.y0 < k || t.y0 + t.rows + k > ny));
+}
+
 // Wave tiles of one basin: strips of `strip` output columns (62 for one step
 // per pass, 60 for two), tiles of `rows` rows.  The last strip / tile is
 // shifted inward so that edge extrapolation always finds its inner nodes in
@@ -161,13 +171,9 @@ void make_tiles(const mlb_grid* g, int basin, int rows, std::vector<TileDev>& ou
     // dispatched first, they overlap the bulk of the pass instead of running
     // alone at its end (tiles are independent within a pass).  Measured on the
     // 4096^2 channel: 287 -> 310 GLUPS with two steps per pass.
-    const int k = strip == kStripOut2 ? 2 : 1;
-    const bool px = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC, py = g->p.edge[MLB_S] == MLB_EDGE_PERIODIC;
-    auto costly = [&](const TileDev& t) {
-        return (t.flags & TILE_MASKED) || (!px && (t.x0 < k || t.x0 + strip + k > nx)) ||
-               (!py && (t.y0 < k || t.y0 + t.rows + k > ny));
-    };
-    if (costly_first) std::stable_partition(out.begin() + first, out.end(), costly);
+    if (costly_first)
+        std::stable_partition(out.begin() + first, out.end(),
+                              [&](const TileDev& t) { return tile_costly(g, t, strip); });
 #else
     (void)first; (void)costly_first;
 #endif
@@ -1093,6 +1099,9 @@ static mlb_status batch_plan(mlb_batch* b)
         d.ntiles2 = (int)b->plan.ht2.size() - d.first_tile2;
         b->plan.hb[i] = d;
     }
+    // (Putting all basins' costly two-step tiles ahead of all others, across
+    // basins, was measured 6 % slower on the 512-basin ensemble than ordering
+    // within each basin: the basins' tiles then no longer run together.)
     b->plan.masked = masked;
     b->plan.implicit = implicit;
     b->plan.comp = comp;
