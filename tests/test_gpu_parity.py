@@ -112,6 +112,22 @@ def test_open_channel_parity(ctx, order):
     assert dh <= H_TOL and du <= U_TOL
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_open_channel_periodic_y_two_step_parity(ctx, order):
+    """Open W / E edges with periodic S / N, two steps per pass (the edge
+    tiles take the interior arithmetic and replace the open-edge nodes)."""
+    spec = wl.bump_channel(190, 64, sigma=9.0)
+    spec.edges = (wl.DISCHARGE, wl.DEPTH, wl.PERIODIC, wl.PERIODIC)
+    spec.extrap_order = order
+    say("case periodic-y channel, order", order)
+    got = run_gpu(ctx, spec, 400, opts={"tblock": 2, "tile_rows": 14})
+    ref = oracle_from_spec(spec)
+    ref.run(400)
+    dh, du = compare(*got, ref.h, ref.qx, ref.qy)
+    say("dh", dh, "du", du)
+    assert dh <= H_TOL and du <= U_TOL
+
+
 def test_open_edges_on_y_parity(ctx):
     """Inflow on the south edge, outflow depth on the north edge (row pipeline
     deferral / history), periodic across."""
@@ -184,6 +200,13 @@ def _two_step_cases():
         sp = wl.bump_channel(181, 22, sigma=6.0)
         sp.extrap_order = order
         cases.append(("channel181x22_rows21_order%d" % order, sp, None, 77, 21))
+    for order in (1, 2):
+        # open W / E edges with periodic S / N: every edge tile takes the
+        # interior arithmetic plus the open-edge replacement
+        sp = wl.bump_channel(190, 64, sigma=9.0)
+        sp.edges = (wl.DISCHARGE, wl.DEPTH, wl.PERIODIC, wl.PERIODIC)
+        sp.extrap_order = order
+        cases.append(("channel_periodic_y_order%d" % order, sp, None, 91, 17))
     nx, ny = 40, 90
     for order in (1, 2):
         sp = wl.Spec("ychannel", nx, ny, 1.0, 25.0 / 6.0, bumpy(nx, ny, 7, amp=0.2), 2.0,
