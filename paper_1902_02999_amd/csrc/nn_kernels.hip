@@ -49,8 +49,9 @@ __device__ __forceinline__ bf16x8 zero8()
 // NB in {2, 4}: each A fragment serves NB products and each B fragment MB).
 // Per block of 32 input channels the workgroup loads the rows' input with
 // its one-pixel halo, (kConvRows + 2) x (PT + 2) x 32 values (zero outside
-// the image), once into LDS; the nine taps then read their shifted A
-// fragments from there instead of from global memory.  Every
+// the image), and the NT x 9 x 32 weights once into LDS; the nine taps then
+// read their shifted A fragments and their B fragments from there instead of
+// from global memory.  Every
 // output sums over channel blocks, then taps, in that order.  OUT_F32: FP32
 // output (optionally accumulated into), else BF16.
 constexpr int kConvRows = 4;
@@ -59,7 +60,10 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
 {
     constexpr int PT = 16 * MB, NT = 16 * NB, TW = PT + 2;
     constexpr int CHUNKS = (kConvRows + 2) * TW * 4;   // 16-byte chunks of 8 channels
+    constexpr int WS = 9 * 32 + 8;                    // per output channel: 9 taps x 32 inputs, padded
+    constexpr int WCHUNKS = NT * 9 * 4;
     __shared__ __attribute__((aligned(16))) __bf16 tile[(kConvRows + 2) * TW * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 wtile[NT * WS];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int ntile = a.cout / NT, xtiles = a.w / PT, ygroups = (a.h + kConvRows - 1) / kConvRows;
     int b = blockIdx.x;                     // (image, row group, pixel tile, channel tile), channels fastest
@@ -86,6 +90,11 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
                 v = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
             *(bf16x8*)&tile[(rr * TW + px) * 32 + ch8 * 8] = v;
         }
+        for (int i = threadIdx.x; i < WCHUNKS; i += 256) {
+            const int ch8 = i & 3, t = (i >> 2) % 9, n = (i >> 2) / 9;
+            *(bf16x8*)&wtile[n * WS + t * 32 + ch8 * 8] =
+                load8(a.wt + ((size_t)(n0 + n) * 9 + t) * a.cin + c0 + ch8 * 8);
+        }
         __syncthreads();
         if (active) {
 #pragma unroll
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
                     A[mb] = *(const bf16x8*)&tile[((wv + 1 + dy) * TW + mb * 16 + l16 + 1 + dx) * 32 + lq * 8];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    Bm[nb] = load8(a.wt + ((size_t)(n0 + nb * 16 + l16) * 9 + t) * a.cin + c0 + lq * 8);
+                    Bm[nb] = *(const bf16x8*)&wtile[(nb * 16 + l16) * WS + t * 32 + lq * 8];
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
