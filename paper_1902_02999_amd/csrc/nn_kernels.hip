@@ -44,7 +44,7 @@ __device__ __forceinline__ bf16x8 zero8()
 
 // ------------------------------------------------------------------ conv 3x3
 // Y[p][n] = act(bias[n] + sum_{t,c} X[p + off_t][c] W[n][t][c]) as an
-// implicit GEMM on MFMA.  A workgroup of four waves computes kConvRows image
+// implicit GEMM on MFMA.  A workgroup of eight waves computes kConvRows image
 // rows (one per wave) of PT = 16 MB pixels x NT = 16 NB output channels (MB,
 // NB in {2, 4}: each A fragment serves NB products and each B fragment MB).
 // Per block of 32 input channels the workgroup loads the rows' input with
@@ -54,9 +54,10 @@ __device__ __forceinline__ bf16x8 zero8()
 // from global memory.  Every
 // output sums over channel blocks, then taps, in that order.  OUT_F32: FP32
 // output (optionally accumulated into), else BF16.
-constexpr int kConvRows = 4;
+constexpr int kConvRows = 8;               // one wave per row: kConvRows x 64 threads
+constexpr int kConvThreads = kConvRows * 64;
 template <bool OUT_F32, int MB, int NB>
-__global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
+__global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 {
     constexpr int PT = 16 * MB, NT = 16 * NB, TW = PT + 2;
     constexpr int CHUNKS = (kConvRows + 2) * TW * 4;   // 16-byte chunks of 8 channels
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
         for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int c0 = 0; c0 < a.cin; c0 += 32) {
-        for (int i = threadIdx.x; i < CHUNKS; i += 256) {
+        for (int i = threadIdx.x; i < CHUNKS; i += kConvThreads) {
             const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
             const int yy = y0 + rr - 1, xx = x0 + px - 1;
             bf16x8 v = zero8();
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void conv3x3_lds_kernel(ConvArgs a)
                 v = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
             *(bf16x8*)&tile[(rr * TW + px) * 32 + ch8 * 8] = v;
         }
-        for (int i = threadIdx.x; i < WCHUNKS; i += 256) {
+        for (int i = threadIdx.x; i < WCHUNKS; i += kConvThreads) {
             const int ch8 = i & 3, t = (i >> 2) % 9, n = (i >> 2) / 9;
             *(bf16x8*)&wtile[n * WS + t * 32 + ch8 * 8] =
                 load8(a.wt + ((size_t)(n0 + n) * 9 + t) * a.cin + c0 + ch8 * 8);
@@ -513,8 +514,8 @@ static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
 {
     const int64_t blocks = (int64_t)a.n * ((a.h + kConvRows - 1) / kConvRows) * (a.w / (16 * MB)) *
                            (a.cout / (16 * NB));
-    if (a.yf) hipLaunchKernelGGL((conv3x3_lds_kernel<true, MB, NB>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((conv3x3_lds_kernel<false, MB, NB>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.yf) hipLaunchKernelGGL((conv3x3_lds_kernel<true, MB, NB>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
+    else hipLaunchKernelGGL((conv3x3_lds_kernel<false, MB, NB>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
 }
 
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
