@@ -246,7 +246,7 @@ def bench_ensemble(args, ctx, copy_gbps):
     nodes = sum(s.nodes for s in specs)
     b = mlb.Batch(ctx, grids)
     b.set_exec_opts(tile_rows=args.tile_rows, graph_chunk=100, blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
-    tuned = None if args.no_autotune else b.autotune(steps=10)
+    tuned = None if args.no_autotune else b.autotune(steps=30)
     b.step(args.warmup)
     ctx.sync()
     t0 = time.perf_counter()
