@@ -135,6 +135,10 @@ def main():
                     help="bump: surface stored as a compensated FP32 pair (one step per pass, 8 more bytes per node)")
     ap.add_argument("--elab-tile-rows", type=int, default=0,
                     help="elab: tile rows of the eLABSWE baseline (0: the fastest of 6, 9, 12, 15)")
+    ap.add_argument("--pcie", action="store_true",
+                    help="bump: also time the same steps with the state handed over in host memory "
+                         "(FP64 upload before, download after) and report that rate in config; "
+                         "value stays the HBM-resident rate")
     ap.add_argument("--net", default=None, help="warm_start: load this trained net instead of training")
     ap.add_argument("--ws-train", type=int, default=512, help="warm_start: training basins")
     ap.add_argument("--ws-epochs", type=int, default=40, help="warm_start: training epochs")
@@ -191,6 +195,22 @@ def main():
 
     nodes = spec.nodes
     mlups = nodes * args.steps / wall / 1e6
+    pcie = None
+    if args.pcie:
+        # host FP64 state in, the same steps, host FP64 state out
+        h0, qx0, qy0 = spec.initial()
+        ctx.sync()
+        t1 = time.perf_counter()
+        grid.set_state(h0, qx0, qy0)
+        ctx.sync()
+        t2 = time.perf_counter()
+        grid.step(args.steps)
+        ctx.sync()
+        t3 = time.perf_counter()
+        grid.get_state()
+        t4 = time.perf_counter()
+        pcie = {"MLUPS": round(nodes * args.steps / (t4 - t1) / 1e6, 1), "upload_ms": round((t2 - t1) * 1e3, 2),
+                "steps_ms": round((t3 - t2) * 1e3, 2), "download_ms": round((t4 - t3) * 1e3, 2)}
     tb = grid.exec_opts().tblock
     # Dominant kernel: one launch per step (tblock 1) or per two steps (tblock
     # 2; the one or two closing single steps of the call are < 0.3 % of it).
@@ -228,6 +248,8 @@ def main():
                    "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": roofline,
     }
+    if pcie is not None:
+        out["config"]["host_state_inclusive"] = pcie
     grid.close()
     ctx.close()
     if not args.no_cpu:
