@@ -37,6 +37,10 @@ TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic
                  "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
                  "implicit2": os.path.join(ROOT, "profiles", "step2_kernel_implicit_bump4096_traffic.json"),
                  "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
+                 "dish4096_2": [os.path.join(ROOT, "profiles", "step2_kernel_masked_dish4096_rows%d_traffic.json" % r)
+                                for r in (17, 26)],
+                 "ensemble": [os.path.join(ROOT, "profiles", "step2_kernel_closed_ensemble512_rows%d_traffic.json" % r)
+                              for r in (14, 17, 20, 26)],
                  "elab": os.path.join(ROOT, "profiles", "elab_step_kernel_lake4096_traffic.json")}
 
 
@@ -267,8 +271,11 @@ def bench_ensemble(args, ctx, copy_gbps):
     grids = [mlb.grid_from_spec(ctx, s) for s in specs]
     nodes = sum(s.nodes for s in specs)
     b = mlb.Batch(ctx, grids)
-    b.set_exec_opts(tile_rows=args.tile_rows, graph_chunk=100, blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
+    b.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
+                    blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
     tuned = None if args.no_autotune else b.autotune(steps=30)
+    opts = tuned or {"tile_rows": args.tile_rows, "tblock": args.tblock, "use_graph": int(not args.no_graph),
+                     "graph_chunk": 100, "blocks_per_cu": args.blocks_per_cu, "persistent": 0}
     b.step(args.warmup)
     ctx.sync()
     t0 = time.perf_counter()
@@ -284,16 +291,17 @@ def bench_ensemble(args, ctx, copy_gbps):
         g.close()
     ctx.close()
     mlups = nodes * args.steps / wall / 1e6
-    tb = tuned["tblock"] if tuned else 1
+    tb = opts["tblock"]
     launch_s = tb * ev_ms / 1e3 / args.steps
     gbs = BYTES_PER_LUP * nodes / launch_s / 1e9
-    roofline, tfl = roofline_of(BYTES_PER_LUP * nodes, FLOP_PER_LUP[True] * tb * nodes, launch_s, None)
+    traffic = measured_traffic(nodes, "ensemble", opts["tile_rows"]) if tb == 2 else None
+    roofline, tfl = roofline_of(BYTES_PER_LUP * nodes, FLOP_PER_LUP[True] * tb * nodes, launch_s, traffic)
     print(json.dumps({
         "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "ensemble_512_basins_64-512_seed1902", "basins": len(specs), "nodes": nodes,
-                   "tuned": tuned, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1),
+                   "exec": opts, "autotuned": tuned is not None, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1),
                    "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1),
                    "fp32_TFLOPs": tfl},
         "roofline": roofline,
@@ -317,7 +325,8 @@ def bench_geometry(args, ctx, copy_gbps):
     water = spec.nodes if spec.kind is None else int((spec.kind != wl.SOLID).sum())
     kind_bytes = 0 if spec.kind is None else 1
     g = mlb.grid_from_spec(ctx, spec)
-    g.set_exec_opts(tile_rows=args.tile_rows, graph_chunk=100, blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
+    g.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
+                    blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
     tuned = None if args.no_autotune else g.autotune(steps=40)
     g.step(args.warmup)
     ctx.sync()
@@ -334,8 +343,8 @@ def bench_geometry(args, ctx, copy_gbps):
     tb = opts["tblock"]
     launch_s = tb * ev_ms / 1e3 / args.steps
     bpl = (BYTES_PER_LUP + kind_bytes) * water
-    traffic = (measured_traffic(water, args.workload, opts["tile_rows"]) if (args.workload == "dish4096" and tb == 1)
-               else None)
+    traffic = (measured_traffic(water, args.workload if tb == 1 else "dish4096_2", opts["tile_rows"])
+               if args.workload == "dish4096" else None)
     roofline, tfl = roofline_of(bpl, FLOP_PER_LUP[spec.chezy > 0] * tb * water, launch_s, traffic)
     steady = None
     if spec.nodes <= 200 * 200:
