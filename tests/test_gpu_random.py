@@ -9,6 +9,7 @@ passes.  The draws cover combinations no hand-written case lists: masks with
 periodic edges, the implicit link depth on narrow open channels, tile heights
 that leave ragged last bands, and so on.
 """
+import copy
 import sys
 
 import numpy as np
@@ -112,3 +113,41 @@ def test_random_configuration(ctx, case):
     dh, du = compare(*one, ref.h, ref.qx, ref.qy, where=where)
     say("dh", dh, "du", du)
     assert dh <= H_TOL and du <= U_TOL
+
+
+def _plain(spec):
+    s = copy.copy(spec)
+    s.hbar_implicit = False
+    s.compensated = False
+    return s
+
+
+@pytest.mark.parametrize("group", range(4))
+def test_random_batches_bitwise(ctx, group):
+    """Ten of the draws (old-time link depth, FP32 surface) in one batch give
+    the bits of each basin run on its own.  A batch holding an open or a
+    masked basin launches the general or masked kernel for every basin, while
+    a closed, unmasked basin on its own takes the kernel without open-edge
+    logic, so this also checks that the kernel variants agree bit for bit."""
+    from paper_1902_02999_amd import mlb
+    members = CASES[10 * group:10 * group + 10]
+    rows = (5, 9, 14, 17)[group]
+    steps = 24
+    opts = dict(tile_rows=rows, tblock=2, use_graph=True, graph_chunk=8)
+    say("batch group", group, "rows", rows, [c[0].name for c in members])
+    specs = [_plain(c[0]) for c in members]
+    solo = [run_gpu(ctx, s, steps, c[1], opts) for s, c in zip(specs, members)]
+    grids = []
+    for s, c in zip(specs, members):
+        g = mlb.grid_from_spec(ctx, s)
+        if c[1] is not None:
+            g.set_state(*c[1])
+        grids.append(g)
+    b = mlb.Batch(ctx, grids)
+    b.set_exec_opts(**opts)
+    b.step(steps)
+    b.close()
+    for g, ref, s in zip(grids, solo, specs):
+        for a, r in zip(g.get_state(), ref):
+            assert np.array_equal(a, r), s.name
+        g.close()
