@@ -7,7 +7,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mlb_runtime.h"
@@ -399,28 +401,58 @@ size_t field_bytes(const mlb_params* p, int* ld_out)
     return 256 + 7 * align_up((size_t)ld * p->ny * sizeof(float), 256);
 }
 
+// fn(j0, j1) over row ranges covering 0 .. ny-1, on up to 16 host threads for
+// large grids (each row is converted independently, so the split does not
+// change any value).
+template <class F>
+void for_rows(int ny, size_t nodes, F fn)
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nt = nodes < ((size_t)1 << 18) ? 1 : (int)std::min<unsigned>(16u, std::max(1u, hw));
+    if (nt <= 1 || ny < 2 * nt) { fn(0, ny); return; }
+    std::vector<std::thread> pool;
+    const int per = (ny + nt - 1) / nt;
+    for (int t = 1; t < nt; ++t) {
+        const int j0 = t * per, j1 = std::min(ny, j0 + per);
+        if (j0 < j1) pool.emplace_back(fn, j0, j1);
+    }
+    fn(0, std::min(ny, per));
+    for (auto& th : pool) th.join();
+}
+
 mlb_status upload_host_state(mlb_grid* g, const double* h, const double* hu, const double* hv,
                              int64_t ld)
 {
     const int nx = g->p.nx, ny = g->p.ny;
-    std::vector<float> e((size_t)g->ld * ny, 0.f), a((size_t)g->ld * ny, 0.f), b((size_t)g->ld * ny, 0.f);
-    std::vector<float> el(g->etal ? e.size() : 0, 0.f);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            const size_t s = (size_t)j * ld + i, d = (size_t)j * g->ld + i;
-            const double ed = h ? h[s] - g->Hd[d] : 0.0;
-            e[d] = (float)ed;
-            if (g->etal) el[d] = (float)(ed - (double)e[d]);   // compensated surface: the remainder
-            a[d] = hu ? (float)hu[s] : 0.f;
-            b[d] = hv ? (float)hv[s] : 0.f;
+    const size_t n = (size_t)g->ld * ny;
+    std::unique_ptr<float[]> e(new (std::nothrow) float[n]), a(new (std::nothrow) float[n]),
+        b(new (std::nothrow) float[n]);
+    std::unique_ptr<float[]> el(g->etal ? new (std::nothrow) float[n] : nullptr);
+    if (!e || !a || !b || (g->etal && !el)) return fail(MLB_E_NOMEM, "host staging of the state");
+    for_rows(ny, (size_t)nx * ny, [&](int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                const size_t s = (size_t)j * ld + i, d = (size_t)j * g->ld + i;
+                const double ed = h ? h[s] - g->Hd[d] : 0.0;
+                e[d] = (float)ed;
+                if (g->etal) el[d] = (float)(ed - (double)e[d]);   // compensated surface: the remainder
+                a[d] = hu ? (float)hu[s] : 0.f;
+                b[d] = hv ? (float)hv[s] : 0.f;
+            }
+            for (int i = nx; i < g->ld; ++i) {   // row padding: zero
+                const size_t d = (size_t)j * g->ld + i;
+                e[d] = a[d] = b[d] = 0.f;
+                if (g->etal) el[d] = 0.f;
+            }
         }
-    const size_t bytes = e.size() * sizeof(float);
+    });
+    const size_t bytes = n * sizeof(float);
     for (int k = 0; k < 2; ++k) {
-        HIPCHK(hipMemcpyAsync(g->eta[k], e.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
-        HIPCHK(hipMemcpyAsync(g->qx[k], a.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
-        HIPCHK(hipMemcpyAsync(g->qy[k], b.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->eta[k], e.get(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qx[k], a.get(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qy[k], b.get(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
         if (g->etal)
-            HIPCHK(hipMemcpyAsync(g->etal + k * g->plane, el.data(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
+            HIPCHK(hipMemcpyAsync(g->etal + k * g->plane, el.get(), bytes, hipMemcpyHostToDevice, g->ctx->stream));
     }
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     return MLB_OK;
@@ -906,22 +938,27 @@ mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t
     GRID_OK(g);
     if (ld < g->p.nx) return fail(MLB_E_INVAL, "ld < nx");
     const int nx = g->p.nx, ny = g->p.ny;
-    std::vector<float> e((size_t)g->ld * ny), a((size_t)g->ld * ny), b((size_t)g->ld * ny);
-    const size_t bytes = e.size() * sizeof(float);
-    HIPCHK(hipMemcpyAsync(e.data(), g->eta[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
-    HIPCHK(hipMemcpyAsync(a.data(), g->qx[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
-    HIPCHK(hipMemcpyAsync(b.data(), g->qy[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
-    std::vector<float> el(g->etal ? e.size() : 0, 0.f);
+    const size_t n = (size_t)g->ld * ny;
+    std::unique_ptr<float[]> e(new (std::nothrow) float[n]), a(new (std::nothrow) float[n]),
+        b(new (std::nothrow) float[n]);
+    std::unique_ptr<float[]> el(g->etal ? new (std::nothrow) float[n] : nullptr);
+    if (!e || !a || !b || (g->etal && !el)) return fail(MLB_E_NOMEM, "host staging of the state");
+    const size_t bytes = n * sizeof(float);
+    HIPCHK(hipMemcpyAsync(e.get(), g->eta[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipMemcpyAsync(a.get(), g->qx[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipMemcpyAsync(b.get(), g->qy[g->cur], bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     if (g->etal)
-        HIPCHK(hipMemcpyAsync(el.data(), g->etal + g->cur * g->plane, bytes, hipMemcpyDeviceToHost, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(el.get(), g->etal + g->cur * g->plane, bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            const size_t s = (size_t)j * g->ld + i, d = (size_t)j * ld + i;
-            if (h) h[d] = g->Hd[s] + (double)e[s] + (g->etal ? (double)el[s] : 0.0);
-            if (hu) hu[d] = a[s];
-            if (hv) hv[d] = b[s];
-        }
+    for_rows(ny, (size_t)nx * ny, [&](int j0, int j1) {
+        for (int j = j0; j < j1; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t s = (size_t)j * g->ld + i, d = (size_t)j * ld + i;
+                if (h) h[d] = g->Hd[s] + (double)e[s] + (g->etal ? (double)el[s] : 0.0);
+                if (hu) hu[d] = a[s];
+                if (hv) hv[d] = b[s];
+            }
+    });
     return MLB_OK;
 }
 
