@@ -86,8 +86,7 @@ def cpu_baseline(spec, budget_s: float = 12.0):
     """The FP64 oracle (as is) on the host cores: steps of the same workload
     until the time budget is spent."""
     import oracle
-    from tests.helpers import oracle_from_spec  # noqa: E402
-    b = oracle_from_spec(spec)
+    b = oracle.from_spec(spec)
     threads = oracle.default_threads()
     b.threads = threads
     t0 = time.perf_counter()

@@ -254,6 +254,27 @@ class Basin:
         return None
 
 
+def from_spec(spec, h=None, qx=None, qy=None, step0=0) -> "Basin":
+    """The oracle problem described by a workload spec (any object with the
+    attributes of ``paper_1902_02999_amd.workloads.Spec``: shape, dx, nu, bed,
+    forcing, edges and their data, node kinds, link-depth form).  The oracle
+    derives its own e, dt, wind stress and friction coefficient from them."""
+    if h is None:
+        h, qx, qy = spec.initial()
+    tx = ty = 0.0
+    if spec.wind_speed is not None:
+        tx, ty = wind_stress(*spec.wind_speed)
+    if spec.wind_stress is not None:
+        tx, ty = spec.wind_stress
+    b = Basin(spec.nx, spec.ny, spec.dx, spec.nu, spec.zb, tx=tx, ty=ty,
+              cb=bed_coeff(spec.chezy) if spec.chezy > 0 else 0.0,
+              omega=spec.omega, edges=spec.edges, extrap_order=spec.extrap_order,
+              depth_bc=dict(spec.depth_bc), discharge_bc=dict(spec.discharge_bc),
+              h=h, qx=qx, qy=qy, kind=spec.kind, hbar_implicit=spec.hbar_implicit)
+    b.step_index = step0
+    return b
+
+
 class ElabBasin:
     """The eLABSWE baseline (Eq. lb.1; nine stored distributions, relaxation
     time tau) on the problem of a ``Basin``: same bed, forcing, edges (walls

@@ -2,26 +2,10 @@
 import numpy as np
 
 import oracle
-from paper_1902_02999_amd import workloads as wl
 
 
-def oracle_from_spec(spec: wl.Spec, h=None, qx=None, qy=None, step0=0) -> "oracle.Basin":
-    """The FP64 oracle problem described by a workload spec (the oracle derives
-    its own e, dt, wind stress and friction coefficient)."""
-    if h is None:
-        h, qx, qy = spec.initial()
-    tx = ty = 0.0
-    if spec.wind_speed is not None:
-        tx, ty = oracle.wind_stress(*spec.wind_speed)
-    if spec.wind_stress is not None:
-        tx, ty = spec.wind_stress
-    b = oracle.Basin(spec.nx, spec.ny, spec.dx, spec.nu, spec.zb, tx=tx, ty=ty,
-                     cb=oracle.bed_coeff(spec.chezy) if spec.chezy > 0 else 0.0,
-                     omega=spec.omega, edges=spec.edges, extrap_order=spec.extrap_order,
-                     depth_bc=dict(spec.depth_bc), discharge_bc=dict(spec.discharge_bc),
-                     h=h, qx=qx, qy=qy, kind=spec.kind, hbar_implicit=spec.hbar_implicit)
-    b.step_index = step0
-    return b
+# the oracle problem of a workload spec (kept under this name for the tests)
+oracle_from_spec = oracle.from_spec
 
 
 def compare(h_gpu, qx_gpu, qy_gpu, h_ref, qx_ref, qy_ref, where=None):

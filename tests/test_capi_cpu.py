@@ -74,7 +74,10 @@ def test_workspace_size_and_validation():
     # non-positive viscosity
     rc, _ = ws_bytes(nx=10, ny=10, dx=1.0, nu=0.0)
     assert rc == -1
-    assert b"periodic" in mlb.lib().mlb_last_error() or True
+    assert mlb.lib().mlb_last_error() == b"dx, nu, g and rho_w must be positive"
+    rc, _ = ws_bytes(nx=10, ny=10, dx=1.0, nu=1.0, edges=(mlb.PERIODIC, mlb.WALL, mlb.WALL, mlb.WALL))
+    assert rc == -1
+    assert b"periodic" in mlb.lib().mlb_last_error()
     rc, _ = ws_bytes(nx=10, ny=10, dx=1.0, nu=1.0, extrap_order=3)
     assert rc == -1
     assert mlb.lib().mlb_status_str(-4) == b"unstable parameters (g H > e^2)"
