@@ -82,24 +82,58 @@ def measured_traffic(nodes: int, key, tile_rows=None):
     return None
 
 
+def timed_steps(ctx, obj, warmup: int, steps: int):
+    """W warm-up steps, the timed call's plan warmed up untimed (a call of the
+    same length: its graph of passes is captured there), then exactly `steps`
+    steps timed between synchronisations.  Returns the wall time, the HIP
+    event time of the whole call [ms] and (ms per pass, passes, steps per
+    pass) of its bulk passes timed alone on the library stream (None when the
+    call has no bulk pass)."""
+    import torch
+    if warmup:
+        obj.step(warmup)
+    obj.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obj.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ctx.last_step_ms()
+    try:
+        bulk = ctx.last_pass_ms()
+    except Exception:
+        bulk = None
+    return wall, ev_ms, bulk
+
+
 def cpu_baseline(spec, budget_s: float = 12.0):
     """The FP64 oracle (as is) on the host cores: steps of the same workload
-    until the time budget is spent."""
+    until the time budget is spent, on all cores (the reported value) and then
+    on one thread for a third of the budget."""
     import oracle
-    b = oracle.from_spec(spec)
+
+    def rate(threads, budget):
+        b = oracle.from_spec(spec)
+        b.threads = threads
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            b.run(1)
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return n, time.perf_counter() - t0
+
     threads = oracle.default_threads()
-    b.threads = threads
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        b.run(1)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
+    n, dt = rate(threads, budget_s)
+    n1, dt1 = rate(1, budget_s / 3)
     return {"value": round(spec.nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": "%d step(s) of the %dx%d workload, FP64, %.1f s" % (n, spec.nx, spec.ny, dt)}
+            "sample": "%d step(s) of the %dx%d workload, FP64, %.1f s" % (n, spec.nx, spec.ny, dt),
+            "value_1_thread": round(spec.nodes * n1 / dt1 / 1e6, 3),
+            "sample_1_thread": "%d step(s), %.1f s" % (n1, dt1)}
 
 
 def main():
@@ -182,15 +216,7 @@ def main():
                        blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
     tuned = None if args.no_autotune else grid.autotune(steps=40)
 
-    grid.step(args.warmup)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    grid.step(args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ctx.last_step_ms()            # HIP events on the library stream around the launches
+    wall, ev_ms, bulk = timed_steps(ctx, grid, args.warmup, args.steps)
     d = grid.diag()
     if d["nonfinite"]:
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
@@ -214,12 +240,13 @@ def main():
         t4 = time.perf_counter()
         pcie = {"MLUPS": round(nodes * args.steps / (t4 - t1) / 1e6, 1), "upload_ms": round((t2 - t1) * 1e3, 2),
                 "steps_ms": round((t3 - t2) * 1e3, 2), "download_ms": round((t4 - t3) * 1e3, 2)}
-    tb = grid.exec_opts().tblock
-    # Dominant kernel: one launch per step (tblock 1) or per two steps (tblock
-    # 2; the one or two closing single steps of the call are < 0.3 % of it).
-    if args.compensated:
-        tb = 1   # one step per pass whatever was requested
-    launch_s = tb * ev_ms / 1e3 / args.steps
+    # Dominant kernel: the call's bulk passes (one or two steps each), timed
+    # alone on the library stream; without them, the whole call per step.
+    if bulk is not None:
+        launch_s, tb = bulk[0] / 1e3, bulk[2]
+    else:
+        tb = 1
+        launch_s = ev_ms / 1e3 / args.steps
     # + 1/(1+kappa), kappa_x, kappa_y; + the low part of eta read and written
     bpl = BYTES_PER_LUP + (12 if args.implicit else 0) + (8 if args.compensated else 0)
     gbs = bpl * nodes / launch_s / 1e9
@@ -247,7 +274,8 @@ def main():
                    "autotuned": tuned is not None, "graph": not args.no_graph, "fp32_TFLOPs": tfl,
                    # per-step bytes of the one-step formulation x update rate
                    "effective_GBps": round(mlups * 1e6 * bpl / 1e9, 1),
-                   "launch_GBps": round(gbs, 1),
+                   "launch_GBps": round(gbs, 1), "launch_us": round(launch_s * 1e6, 3),
+                   "bulk_passes": None if bulk is None else bulk[1], "call_event_ms": round(ev_ms, 4),
                    "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": roofline,
     }
@@ -275,14 +303,7 @@ def bench_ensemble(args, ctx, copy_gbps):
     tuned = None if args.no_autotune else b.autotune(steps=30)
     opts = tuned or {"tile_rows": args.tile_rows, "tblock": args.tblock, "use_graph": int(not args.no_graph),
                      "graph_chunk": 100, "blocks_per_cu": args.blocks_per_cu, "persistent": 0}
-    b.step(args.warmup)
-    ctx.sync()
-    t0 = time.perf_counter()
-    b.step(args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ctx.last_step_ms()
+    wall, ev_ms, bulk = timed_steps(ctx, b, args.warmup, args.steps)
     ok, diags = b.run_steady(0.0, 1, 1)   # one checked step: finiteness of every basin
     bad = sum(d["nonfinite"] for d in diags)
     b.close()
@@ -290,8 +311,11 @@ def bench_ensemble(args, ctx, copy_gbps):
         g.close()
     ctx.close()
     mlups = nodes * args.steps / wall / 1e6
-    tb = opts["tblock"]
-    launch_s = tb * ev_ms / 1e3 / args.steps
+    if bulk is not None:
+        launch_s, tb = bulk[0] / 1e3, bulk[2]
+    else:
+        tb = 1
+        launch_s = ev_ms / 1e3 / args.steps
     gbs = BYTES_PER_LUP * nodes / launch_s / 1e9
     traffic = measured_traffic(nodes, "ensemble", opts["tile_rows"]) if tb == 2 else None
     roofline, tfl = roofline_of(BYTES_PER_LUP * nodes, FLOP_PER_LUP[True] * tb * nodes, launch_s, traffic)
@@ -302,9 +326,41 @@ def bench_ensemble(args, ctx, copy_gbps):
         "config": {"workload": "ensemble_512_basins_64-512_seed1902", "basins": len(specs), "nodes": nodes,
                    "exec": opts, "autotuned": tuned is not None, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1),
                    "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1),
-                   "fp32_TFLOPs": tfl},
+                   "launch_us": round(launch_s * 1e6, 3), "fp32_TFLOPs": tfl},
         "roofline": roofline,
-        "cpu_baseline": None}), flush=True)
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_ensemble(specs, args.cpu_seconds)}), flush=True)
+
+
+def cpu_baseline_ensemble(specs, budget_s: float = 12.0):
+    """The FP64 oracle on a fixed sample of the ensemble's basins (every
+    32nd, 16 basins of the same size distribution), stepped round-robin until
+    the budget is spent, on all cores and then on one thread."""
+    import oracle
+    sample = specs[::32]
+    nodes = sum(sp.nodes for sp in sample)
+
+    def rate(threads, budget):
+        bs = [oracle.from_spec(sp) for sp in sample]
+        for bb in bs:
+            bb.threads = threads
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            for bb in bs:
+                bb.run(1)
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return n, time.perf_counter() - t0
+
+    threads = oracle.default_threads()
+    n, dt = rate(threads, budget_s)
+    n1, dt1 = rate(1, budget_s / 3)
+    return {"value": round(nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "%d step(s) of %d of the 512 basins (every 32nd, %d nodes), FP64, %.1f s"
+                      % (n, len(sample), nodes, dt),
+            "value_1_thread": round(nodes * n1 / dt1 / 1e6, 3),
+            "sample_1_thread": "%d step(s), %.1f s" % (n1, dt1)}
 
 
 def bench_geometry(args, ctx, copy_gbps):
@@ -327,20 +383,15 @@ def bench_geometry(args, ctx, copy_gbps):
     g.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
                     blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
     tuned = None if args.no_autotune else g.autotune(steps=40)
-    g.step(args.warmup)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ctx.last_step_ms()
+    wall, ev_ms, bulk = timed_steps(ctx, g, args.warmup, args.steps)
     d = g.diag()
     opts = g.exec_opts().as_dict()
     g.close()
-    tb = opts["tblock"]
-    launch_s = tb * ev_ms / 1e3 / args.steps
+    if bulk is not None:
+        launch_s, tb = bulk[0] / 1e3, bulk[2]
+    else:
+        tb = 1
+        launch_s = ev_ms / 1e3 / args.steps
     bpl = (BYTES_PER_LUP + kind_bytes) * water
     traffic = (measured_traffic(water, args.workload if tb == 1 else "dish4096_2", opts["tile_rows"])
                if args.workload == "dish4096" else None)

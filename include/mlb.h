@@ -103,7 +103,8 @@ const char* mlb_last_error(void);
 mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out);
 /* MLB_E_STATE while grids or batches created from it are alive. */
 mlb_status mlb_ctx_destroy(mlb_ctx* ctx);
-/* Blocks until the context's stream is idle. */
+/* Blocks until the context's stream is idle.  MLB_E_DEVICE if a persistent
+ * launch on the context gave up at a pass barrier since the last check. */
 mlb_status mlb_ctx_sync(mlb_ctx* ctx);
 /* Stall rule of the steady-state runs on this context (mlb_run_steady,
  * mlb_warm_start_run): with checks > 0 a run stops with MLB_E_STALLED once
@@ -114,7 +115,8 @@ mlb_status mlb_ctx_sync(mlb_ctx* ctx);
 mlb_status mlb_set_stall_checks(mlb_ctx* ctx, int32_t checks);
 
 /* Device bytes of a grid's fields (two copies of eta, qx, qy; the still-water
- * depth; the step counter) for a caller-owned workspace.  The small tile list
+ * depth; a 256-byte header with the step counter and the last step's
+ * diagnostic sums) for a caller-owned workspace.  The small tile list
  * and reduction buffers are always allocated by the library. */
 mlb_status mlb_grid_workspace_bytes(const mlb_params* p, size_t* bytes);
 /* Creates a grid.  dev_workspace == NULL: the library allocates device memory.
@@ -203,7 +205,9 @@ mlb_status mlb_set_hbar(mlb_grid* g, int32_t mode);
  *                and run as one-step graph / stream launches).  The
  *                free surface extrapolated onto a DISCHARGE edge is rounded
  *                to FP32 (its low part is 0).  Switching it on sets the low
- *                parts to 0; mlb_set_state splits h - H exactly into the
+ *                parts to 0 (switching either way copies the state into the second
+ *                buffer set, so the next residual is 0); mlb_set_state splits
+ *                h - H exactly into the
  *                pair, mlb_get_state returns H + high + low,
  *                mlb_set_state_device sets the low parts to 0 and
  *                mlb_get_state_device returns the high part.
@@ -237,16 +241,28 @@ mlb_status mlb_set_state(mlb_grid* g, const double* h, const double* hu, const d
  * (device-to-device copy on the context stream; the step counter is kept). */
 mlb_status mlb_set_state_device(mlb_grid* g, const float* eta, const float* qx, const float* qy);
 /* Current h = H + eta, hu, hv into host arrays [ny][ld] (any may be NULL);
- * synchronises the stream. */
+ * synchronises the stream.  MLB_E_DEVICE if a persistent launch of the grid
+ * gave up at a pass barrier (its passes are incomplete; set the state again). */
 mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t ld);
-/* Current FP32 fields copied to device arrays [ny][nx] (any may be NULL). */
+/* Current FP32 fields copied to device arrays [ny][nx] (any may be NULL).
+ * Enqueued; it waits for the stream only after a persistent launch, to report
+ * a give-up at a pass barrier (MLB_E_DEVICE). */
 mlb_status mlb_get_state_device(mlb_grid* g, float* eta, float* qx, float* qy, float* H);
 
 /* Advances nsteps steps (enqueued on the context stream; returns without
- * waiting).  MLB_E_STATE if the grid belongs to a live batch. */
+ * waiting).  The call's last pass is a checked one: it also reduces its last
+ * step into the FP64 diagnostic sums of the grid (the residual against the
+ * step before, which a two-step pass holds in registers), kept with the grid
+ * for mlb_diag.  With two steps per pass an odd count starts with one single
+ * step.  MLB_E_STATE if the grid belongs to a live batch; MLB_E_DEVICE if an
+ * earlier persistent launch of the grid gave up at a pass barrier. */
 mlb_status mlb_step(mlb_grid* g, int64_t nsteps);
-/* Diagnostics of the last step (runs one extra reduction pass over the state;
- * the residual needs the previous step and is 0 right after a set_*). Syncs. */
+/* Diagnostics of the last step (a9: FP64 mass, residual, max speed and
+ * non-finite count): those the last checked pass kept, or, when the fields
+ * were set since (set_state*, set_bathymetry, set_mask, set_surface,
+ * mlb_net_infer; both buffers then hold the state), one reduction pass over
+ * the state, whose residual is 0.  Syncs.  MLB_E_DEVICE if a persistent launch
+ * gave up at a pass barrier. */
 mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out);
 /* Steps until the residual of a checked step is <= tol.  Checks every
  * check_every steps (the checked step is reduced in the same kernel pass).
@@ -263,8 +279,8 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
 typedef struct {
     int32_t tile_rows;     /* output rows per wave tile, 4..4096                          */
     int32_t tblock;        /* steps per kernel pass: 1, or 2 (temporal blocking: the first
-                            * step's level stays in registers; a call's last step is
-                            * always a one-step pass)                                     */
+                            * step's level stays in registers; an odd step count takes
+                            * one single-step pass first)                                 */
     int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
     int32_t graph_chunk;   /* steps per captured graph, 2..100000                         */
     int32_t blocks_per_cu; /* 0: no cap; 1..8: at most this many step workgroups per CU   */
@@ -309,6 +325,12 @@ mlb_status mlb_batch_destroy(mlb_batch* b);
 /* Kernel time of the last mlb_step / mlb_batch_step call measured with HIP
  * events on the context stream around the step launches [ms]. */
 mlb_status mlb_last_step_ms(mlb_ctx* ctx, double* ms);
+/* Time per pass of the last call's bulk passes (HIP events on the context
+ * stream around them): its passes of `steps_per_pass` steps (the plan's
+ * kind, 1 or 2), without a leading single step and without the closing
+ * checked pass.  *passes (may be NULL) receives their number.  MLB_E_STATE if
+ * the last call had no such pass (fewer than 3 steps with two per pass). */
+mlb_status mlb_last_pass_ms(mlb_ctx* ctx, double* ms, int64_t* passes, int32_t* steps_per_pass);
 
 /* Practical HBM bandwidth: copies `bytes` (multiple of 16, >= 4096) between
  * two device buffers the library allocates for the call, `reps` times, with a

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlb.so")
-SOURCES = ["mlb_kernels.hip", "mlb_api.hip", "nn_kernels.hip", "nn_api.hip", "elab_kernels.hip", "elab_api.hip"]
+SOURCES = ["mlb_kernels.hip", "mlb_kernels2.hip", "mlb_persist.hip", "mlb_api.hip", "nn_kernels.hip", "nn_api.hip", "elab_kernels.hip", "elab_api.hip"]
 ARCH = os.environ.get("MLB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -24,17 +24,40 @@ FLAGS = [
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compile every source into libmlb.so (always recompiles)."""
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + FLAGS + ["-D" + d for d in defines] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libmlb.so")
-    os.replace(tmp, out)
+    """Compile every source into libmlb.so (always recompiles): one hipcc per
+    translation unit in parallel, then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = "%d" % os.getpid()
+    objs = [out + ".%s.%s.o" % (os.path.splitext(s)[0], tag) for s in SOURCES]
+    base = [f for f in FLAGS if f != "-shared"] + ["-D" + d for d in defines]
+
+    def cc(i):
+        cmd = ["hipcc", "-c"] + base + [os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    try:
+        with ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(cc, range(len(SOURCES))))
+        for r in results:
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError("hipcc failed building libmlb.so")
+        tmp = out + ".tmp" + tag
+        cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libmlb.so")
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

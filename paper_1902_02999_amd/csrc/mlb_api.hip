@@ -58,6 +58,7 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     b.cky = imp ? g->dcoef + 2 * g->plane : nullptr;
     for (int k = 0; k < 2; ++k) b.etal[k] = g->etal ? g->etal + k * g->plane : nullptr;
     b.stepc = g->stepc;
+    b.dres = g->dres;
     b.nx = g->p.nx; b.ny = g->p.ny; b.ld = g->ld;
     b.swap = swap;
     b.per_x = g->p.edge[MLB_W] == MLB_EDGE_PERIODIC;
@@ -190,9 +191,11 @@ mlb_status check_stream(mlb_ctx* c)
 mlb_status plan_alloc(mlb_ctx* c, Plan& P)
 {
     const size_t nb = P.hb.size(), nt = P.ht.size();
+    // partials of a checked pass: one set per tile of either list
+    const size_t np = std::max<size_t>(1, std::max(nt, P.ht2.size()));
     HIPCHK(hipMalloc(&P.db, nb * sizeof(BasinDev)));
     HIPCHK(hipMalloc(&P.dt, nt * sizeof(TileDev)));
-    HIPCHK(hipMalloc(&P.dpart, nt * kPartials * sizeof(double)));
+    HIPCHK(hipMalloc(&P.dpart, np * kPartials * sizeof(double)));
     HIPCHK(hipMalloc(&P.dout, nb * 8 * sizeof(double)));
     HIPCHK(hipHostMalloc(&P.hout, nb * 8 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipMalloc(&P.dsync, sizeof(SyncState)));
@@ -258,6 +261,46 @@ mlb_status grid_plan(mlb_grid* g)
     return MLB_OK;
 }
 
+// A persistent launch gives up at a pass barrier when a bounded wait runs
+// out; its passes are then incomplete and later persistent launches of the
+// plan do nothing.  After each persistent launch the flag is copied to the
+// host in stream order (watch_abort); the calls that hand out state or
+// diagnostics check it (check_abort, after the stream has drained), report
+// MLB_E_DEVICE and clear the flag, so that the state can be set again.
+mlb_status watch_abort(mlb_ctx* c, Plan& P)
+{
+    HIPCHK(hipMemcpyAsync(P.herr, &P.dsync->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    if (!P.err_pending) {
+        P.err_pending = true;
+        P.watch = c;
+        c->watch.push_back(&P);
+    }
+    return MLB_OK;
+}
+
+mlb_status check_abort(mlb_ctx* c, Plan& P)
+{
+    if (!P.err_pending) return MLB_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    plan_unwatch(P);
+    if (*(volatile int32_t*)P.herr) {
+        *P.herr = 0;
+        HIPCHK(hipMemsetAsync(P.dsync, 0, sizeof(SyncState), c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        P.sync_base = 0;
+        return fail(MLB_E_DEVICE, "a persistent launch timed out at a pass barrier; the state is incomplete");
+    }
+    return MLB_OK;
+}
+
+// The same without waiting: reports a give-up whose flag copy has already
+// landed (calls that only enqueue work check this way).
+mlb_status peek_abort(mlb_ctx* c, Plan& P)
+{
+    if (P.err_pending && *(volatile int32_t*)P.herr) return check_abort(c, P);
+    return MLB_OK;
+}
+
 // Launch n steps of a plan; the last one reduces into partials when diag.
 // Advances the plan parity per launch; graph chunks replay when aligned.
 // Dynamic LDS per step workgroup that leaves room for at most
@@ -275,9 +318,11 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
 {
     const int nt1 = (int)P.ht.size(), nt2 = (int)P.ht2.size();
     const unsigned dyn = dyn_lds_for(c, o);
-    // Two steps per launch when the plan has the two-step tiles; the last step
-    // of a call is always a single one, so the buffer left behind holds the
-    // level before the last (the residual of mlb_diag compares the two).
+    // Two steps per launch when the plan has the two-step tiles; an odd count
+    // takes one single step first.  A checked call (diag_last) ends with a
+    // checked pass of the same kind: its last step is reduced into the tile
+    // partials (residual against the level before it, which a two-step pass
+    // holds in registers) and finalised into every basin's result slot.
     const int kind = (o.tblock == 2 && P.dt2) ? 2 : 1;
     int64_t nl = 0;
     auto eager = [&](int k, bool diag) -> mlb_status {
@@ -288,15 +333,17 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
         ++nl;
         return MLB_OK;
     };
-    // launches of `kind` before the closing single steps
-    int64_t multi = 0, singles = n;
-    if (kind == 2 && n >= 2) {
-        multi = (n - 1) / 2;
-        singles = n - 2 * multi;
-    } else if (kind == 1) {
-        multi = diag_last ? n - 1 : n;
-        singles = n - multi;
+    int64_t lead = kind == 2 ? (n & 1) : 0;   // single steps before the passes of `kind`
+    int64_t multi = kind == 2 ? n / 2 : n;     // passes of `kind`
+    int closing = 0;                           // steps of the closing checked pass
+    if (diag_last && n > 0) {
+        if (multi > 0) { closing = kind; --multi; }
+        else { closing = 1; --lead; }
     }
+    for (int64_t i = 0; i < lead; ++i) CHK(eager(1, false));
+    HIPCHK(hipEventRecord(c->ev2, c->stream));
+    c->bulk_passes = multi;
+    c->bulk_kind = kind;
     // persistent: all `multi` passes in cooperative launches with grid barriers
     // (not for the implicit link depth: those basins use ordinary launches)
     if (o.persistent && multi > 0 && !P.coop_failed && !P.implicit && !P.comp) {
@@ -318,11 +365,14 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
                 P.parity ^= np & 1;
                 nl += np;
                 multi -= np;
+                CHK(watch_abort(c, P));
             }
         }
     }
-    // graphs hold an even number of launches, so the parity they start from recurs
-    const int glaunch = kind == 2 ? std::max(2, (o.graph_chunk / 2) & ~1) : std::max(2, o.graph_chunk & ~1);
+    // graphs hold an even number of launches, so the parity they start from
+    // recurs; a call shorter than one chunk captures a graph of its own length
+    int glaunch = kind == 2 ? std::max(2, (o.graph_chunk / 2) & ~1) : std::max(2, o.graph_chunk & ~1);
+    if (multi < glaunch && multi >= 4) glaunch = (int)(multi & ~(int64_t)1);
     if (o.use_graph && multi >= glaunch) {
         if (!P.gexec || P.gsteps != glaunch || P.gkind != kind || P.gdyn != dyn) {
             if (P.gexec) { (void)hipGraphExecDestroy(P.gexec); P.gexec = nullptr; }
@@ -358,7 +408,11 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
         }
     }
     for (int64_t i = 0; i < multi; ++i) CHK(eager(kind, false));
-    for (int64_t i = 0; i < singles; ++i) CHK(eager(1, diag_last && i == singles - 1));
+    HIPCHK(hipEventRecord(c->ev3, c->stream));
+    if (closing) {
+        CHK(eager(closing, true));
+        HIPCHK(launch_finalize(P.db, (int)P.hb.size(), P.dpart, P.dout, closing, c->stream));
+    }
     if (launches) *launches = nl;
     return MLB_OK;
 }
@@ -540,21 +594,13 @@ void fill_diag(const mlb_grid* g, const double* o, mlb_diag_t* d)
     d->rle = o[4] * g->p.dx / g->p.nu;
 }
 
+// The finalised sums of a plan's last checked pass (P.dout) to the host.
 mlb_status read_diag(mlb_ctx* c, Plan& P)
 {
-    HIPCHK(launch_finalize(P.db, (int)P.hb.size(), P.dpart, P.dout, c->stream));
     HIPCHK(hipMemcpyAsync(P.hout, P.dout, P.hb.size() * 8 * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(hipMemcpyAsync(P.herr, &P.dsync->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (*P.herr) {
-        // a persistent launch gave up at a barrier: its passes are incomplete
-        HIPCHK(hipMemsetAsync(P.dsync, 0, sizeof(SyncState), c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        P.sync_base = 0;
-        return fail(MLB_E_DEVICE, "a persistent launch timed out at a pass barrier; the state is incomplete");
-    }
-    return MLB_OK;
+    return check_abort(c, P);
 }
 
 #define GRID_OK(g)                                                         \
@@ -566,6 +612,16 @@ mlb_status read_diag(mlb_ctx* c, Plan& P)
 }  // namespace
 
 namespace mlb {
+void plan_unwatch(Plan& P)
+{
+    if (P.watch) {
+        auto& w = P.watch->watch;
+        w.erase(std::remove(w.begin(), w.end(), &P), w.end());
+    }
+    P.watch = nullptr;
+    P.err_pending = false;
+}
+void grid_state_changed(mlb_grid* g) { g->diag_fresh = false; }
 mlb_status grid_set_step(mlb_grid* g, int64_t s) { return set_step(g, s); }
 // (band order: the eLABSWE kernel measured 2.5 % slower with its edge tiles first)
 void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out) { make_tiles(g, 0, rows, out, kStripOut, false); }
@@ -619,6 +675,8 @@ mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out)
     for (auto& ch : c->arch) if (ch == ' ' || ch == ':') ch = '_';
     (void)hipEventCreate(&c->ev0);
     (void)hipEventCreate(&c->ev1);
+    (void)hipEventCreate(&c->ev2);
+    (void)hipEventCreate(&c->ev3);
     // bounded wait of persistent launches (polls); a small value forces the
     // timeout path from the host
     if (const char* sl = std::getenv("MLB_SPIN_LIMIT")) {
@@ -637,6 +695,8 @@ mlb_status mlb_ctx_destroy(mlb_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev2) (void)hipEventDestroy(c->ev2);
+    if (c->ev3) (void)hipEventDestroy(c->ev3);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return MLB_OK;
@@ -654,6 +714,12 @@ mlb_status mlb_ctx_sync(mlb_ctx* c)
     if (!c) return fail(MLB_E_INVAL, "ctx is NULL");
     CHK(check_stream(c));
     HIPCHK(hipStreamSynchronize(c->stream));
+    mlb_status st = MLB_OK;
+    while (!c->watch.empty()) {   // every watched plan is checked (and cleared)
+        const mlb_status s1 = check_abort(c, *c->watch.back());
+        if (st == MLB_OK) st = s1;
+    }
+    if (st != MLB_OK) return fail(st, "a persistent launch timed out at a pass barrier; the state is incomplete");
     return MLB_OK;
 }
 
@@ -689,6 +755,7 @@ mlb_status mlb_grid_create(mlb_ctx* c, const mlb_params* p, void* ws, size_t ws_
         g->own = true;
     }
     g->stepc = (int64_t*)g->base;
+    g->dres = (double*)(g->base + 64);
     float* f = (float*)(g->base + 256);
     g->eta[0] = f; g->eta[1] = f + g->plane;
     g->qx[0] = f + 2 * g->plane; g->qx[1] = f + 3 * g->plane;
@@ -750,6 +817,7 @@ mlb_status mlb_set_bathymetry(mlb_grid* g, const double* zb, int64_t ld)
     CHK(upload_host_state(g, nullptr, nullptr, nullptr, nx));
     g->cur = 0;
     g->dirty = true;
+    g->diag_fresh = false;
     return set_step(g, 0);
 }
 
@@ -869,6 +937,7 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
         HIPCHK(hipStreamSynchronize(g->ctx->stream));
         g->hmask.swap(m);
     }
+    g->diag_fresh = false;   // the water (and so the sums) changed
     g->sumH = water_depth_sum(g);
     CHK(implicit_coeffs(g));
     g->stale_plan = true;
@@ -881,6 +950,15 @@ mlb_status mlb_set_surface(mlb_grid* g, int32_t mode)
     if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
     if (mode != MLB_SURFACE_FP32 && mode != MLB_SURFACE_COMPENSATED) return fail(MLB_E_INVAL, "unknown surface mode");
     const bool on = mode == MLB_SURFACE_COMPENSATED;
+    if (on != (g->etal != nullptr)) {
+        // the current state into the second buffer set (the next residual is 0)
+        const size_t bytes = g->plane * sizeof(float);
+        const int o = g->cur ^ 1;
+        HIPCHK(hipMemcpyAsync(g->eta[o], g->eta[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qx[o], g->qx[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        HIPCHK(hipMemcpyAsync(g->qy[o], g->qy[g->cur], bytes, hipMemcpyDeviceToDevice, g->ctx->stream));
+        g->diag_fresh = false;
+    }
     if (on && !g->etal) {
         HIPCHK(hipMalloc((void**)&g->etal, 2 * g->plane * sizeof(float)));
         HIPCHK(hipMemsetAsync(g->etal, 0, 2 * g->plane * sizeof(float), g->ctx->stream));
@@ -915,6 +993,7 @@ mlb_status mlb_set_state(mlb_grid* g, const double* h, const double* hu, const d
     if (!h || ld < g->p.nx || step0 < 0) return fail(MLB_E_INVAL, "h is NULL, ld < nx or step0 < 0");
     if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
     CHK(upload_host_state(g, h, hu, hv, ld));
+    g->diag_fresh = false;
     return set_step(g, step0);
 }
 
@@ -930,6 +1009,7 @@ mlb_status mlb_set_state_device(mlb_grid* g, const float* eta, const float* qx, 
         HIPCHK(hipMemcpy2DAsync(g->qy[k], pitch, qy, w, w, g->p.ny, hipMemcpyDeviceToDevice, g->ctx->stream));
     }
     if (g->etal) HIPCHK(hipMemsetAsync(g->etal, 0, 2 * g->plane * sizeof(float), g->ctx->stream));
+    g->diag_fresh = false;
     return MLB_OK;
 }
 
@@ -950,6 +1030,7 @@ mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t
     if (g->etal)
         HIPCHK(hipMemcpyAsync(el.get(), g->etal + g->cur * g->plane, bytes, hipMemcpyDeviceToHost, g->ctx->stream));
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    CHK(check_abort(g->ctx, g->plan));
     for_rows(ny, (size_t)nx * ny, [&](int j0, int j1) {
         for (int j = j0; j < j1; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -965,6 +1046,7 @@ mlb_status mlb_get_state(mlb_grid* g, double* h, double* hu, double* hv, int64_t
 mlb_status mlb_get_state_device(mlb_grid* g, float* eta, float* qx, float* qy, float* H)
 {
     GRID_OK(g);
+    CHK(check_abort(g->ctx, g->plan));   // waits only after a persistent launch
     const size_t w = (size_t)g->p.nx * sizeof(float), pitch = (size_t)g->ld * sizeof(float);
     const int ny = g->p.ny;
     if (eta) HIPCHK(hipMemcpy2DAsync(eta, w, g->eta[g->cur], pitch, w, ny, hipMemcpyDeviceToDevice, g->ctx->stream));
@@ -1017,12 +1099,14 @@ mlb_status mlb_step(mlb_grid* g, int64_t n)
     if (n == 0) return MLB_OK;
     CHK(grid_plan(g));
     mlb_ctx* c = g->ctx;
+    CHK(peek_abort(c, g->plan));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     int64_t nl = 0;
-    CHK(enqueue_steps(c, g->plan, g->opts, n, false, &nl));
+    CHK(enqueue_steps(c, g->plan, g->opts, n, true, &nl));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     advance_grid(g, n, nl);
+    g->diag_fresh = true;   // the closing checked pass filled the result slot
     return MLB_OK;
 }
 
@@ -1033,8 +1117,17 @@ mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out)
     if (g->batch) return fail(MLB_E_STATE, "grid belongs to a live batch");
     CHK(grid_plan(g));
     Plan& P = g->plan;
-    HIPCHK(launch_reduce_state(P.db, P.dt, (int)P.ht.size(), P.parity, P.dpart, g->ctx->stream));
-    CHK(read_diag(g->ctx, P));
+    mlb_ctx* c = g->ctx;
+    if (!g->diag_fresh) {
+        // the fields were set since the last checked pass: reduce the state
+        // (both buffers hold it, so the residual is 0)
+        HIPCHK(launch_reduce_state(P.db, P.dt, (int)P.ht.size(), P.parity, P.dpart, c->stream));
+        HIPCHK(launch_finalize(P.db, 1, P.dpart, P.dout, 1, c->stream));
+        g->diag_fresh = true;
+    }
+    HIPCHK(hipMemcpyAsync(P.hout, g->dres, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(check_abort(c, P));
     fill_diag(g, P.hout, out);
     return MLB_OK;
 }
@@ -1055,6 +1148,7 @@ mlb_status mlb_run_steady(mlb_grid* g, double tol, int64_t max_steps, int32_t ch
         int64_t nl = 0;
         CHK(enqueue_steps(c, g->plan, g->opts, n, true, &nl));
         advance_grid(g, n, nl);
+        g->diag_fresh = true;
         CHK(read_diag(c, g->plan));
         fill_diag(g, g->plan.hout, &d);
         if (out) *out = d;
@@ -1076,6 +1170,21 @@ mlb_status mlb_last_step_ms(mlb_ctx* c, double* ms)
     float f = 0;
     HIPCHK(hipEventElapsedTime(&f, c->ev0, c->ev1));
     *ms = f;
+    return MLB_OK;
+}
+
+mlb_status mlb_last_pass_ms(mlb_ctx* c, double* ms, int64_t* passes, int32_t* steps_per_pass)
+{
+    if (!c || !ms) return fail(MLB_E_INVAL, "NULL argument");
+    if (!c->timed) return fail(MLB_E_STATE, "no timed step yet");
+    if (c->bulk_passes < 1) return fail(MLB_E_STATE, "the last call had no passes besides its checked one");
+    CHK(check_stream(c));
+    HIPCHK(hipEventSynchronize(c->ev3));
+    float f = 0;
+    HIPCHK(hipEventElapsedTime(&f, c->ev2, c->ev3));
+    *ms = f / (double)c->bulk_passes;
+    if (passes) *passes = c->bulk_passes;
+    if (steps_per_pass) *steps_per_pass = c->bulk_kind;
     return MLB_OK;
 }
 
@@ -1198,12 +1307,13 @@ mlb_status mlb_batch_step(mlb_batch* b, int64_t n)
     if (n == 0) return MLB_OK;
     CHK(batch_plan(b));
     mlb_ctx* c = b->ctx;
+    CHK(peek_abort(c, b->plan));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     int64_t nl = 0;
-    CHK(enqueue_steps(c, b->plan, b->opts, n, false, &nl));
+    CHK(enqueue_steps(c, b->plan, b->opts, n, true, &nl));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->timed = true;
-    for (auto* g : b->grids) advance_grid(g, n, nl);
+    for (auto* g : b->grids) { advance_grid(g, n, nl); g->diag_fresh = true; }
     return MLB_OK;
 }
 
@@ -1221,7 +1331,7 @@ mlb_status mlb_batch_run_steady(mlb_batch* b, double tol, int64_t max_steps, int
         const int64_t k = std::min<int64_t>(check_every, max_steps - done);
         int64_t nl = 0;
         CHK(enqueue_steps(c, b->plan, b->opts, k, true, &nl));
-        for (auto* g : b->grids) advance_grid(g, k, nl);
+        for (auto* g : b->grids) { advance_grid(g, k, nl); g->diag_fresh = true; }
         done += k;
         CHK(read_diag(c, b->plan));
         bool all = true, bad = false;
@@ -1305,6 +1415,7 @@ mlb_status restore_states(mlb_ctx* c, const std::vector<mlb_grid*>& gs, Saved& s
                                       hipMemcpyDeviceToDevice, c->stream));
         }
         CHK(set_step(g, sv.step[i]));
+        g->diag_fresh = false;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     return MLB_OK;
@@ -1392,6 +1503,9 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
                 HIPCHK(hipEventElapsedTime(&ms[rep], c->ev0, c->ev1));
                 for (auto* g : gs) advance_grid(g, n, nl);
             }
+            // a persistent candidate whose barrier wait gave up did not run its
+            // passes: never a candidate (the state is restored afterwards)
+            if (check_abort(c, *P) != MLB_OK) continue;
             std::sort(ms, ms + 3);
             const double us = 1e3 * ms[1] / n;
             if (us < best_t) { best_t = us; best = o; }

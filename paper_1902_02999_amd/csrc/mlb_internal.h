@@ -36,6 +36,7 @@ struct BasinDev {
     // compensated surface: low part of eta per buffer (nullptr: plain FP32)
     float* etal[2];
     int64_t* stepc;        // [2]: step counter, read from [rd], written to [1-rd]
+    double* dres;          // [8]: the basin's last finalised diagnostics (grid header), or nullptr
     int32_t nx, ny, ld;
     int32_t swap;          // buffer read by a launch of parity p is p ^ swap
     int32_t per_x, per_y;
@@ -99,8 +100,8 @@ hipError_t launch_elab_macro(const ElabDev& D, int rd, float* eta, float* qx, fl
 hipError_t launch_elab_dist(const ElabDev& D, int rd, float* out, hipStream_t s);
 
 // Host-side launchers (mlb_kernels.hip).
-// tblock 1: one step (diag: reduce into partials); tblock 2: two steps, tiles
-// of kStripOut2 columns, no diag.  masked: the tile list may hold
+// tblock 1: one step, tblock 2: two steps over tiles of kStripOut2 columns;
+// diag: the (last) step is reduced into the tile partials.  masked: the tile list may hold
 // TILE_MASKED tiles; implicit: every basin has the implicit link-depth
 // planes; comp: every basin has a compensated surface (one step only);
 // closed: no basin has an open (DEPTH or DISCHARGE) edge, so the two-step
@@ -108,6 +109,10 @@ hipError_t launch_elab_dist(const ElabDev& D, int rd, float* out, hipStream_t s)
 hipError_t launch_step(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
                        double* d_partials, int diag, int tblock, int masked, int implicit, int comp, int closed,
                        unsigned dyn_lds, hipStream_t s);
+// The two-step kernels (mlb_kernels2.hip); launch_step forwards tblock 2 here.
+hipError_t launch_step2(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles, int parity,
+                        double* d_partials, int diag, int masked, int implicit, int closed, unsigned dyn_lds,
+                        hipStream_t s);
 // npasses passes of `kind` steps in one cooperative launch (all tiles
 // resident); base = sync->count at launch.  Fails (no launch) when the grid
 // cannot be co-resident.
@@ -120,7 +125,9 @@ hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int nblocks, hipStream_t s);
+// Per-basin sums of the tile partials of a pass of `kind` steps (1 also for the
+// state reduction) into d_out[8 * basin] and each basin's result slot.
 hipError_t launch_finalize(const BasinDev* d_basins, int nbasins, const double* d_partials,
-                           double* d_out, hipStream_t s);
+                           double* d_out, int kind, hipStream_t s);
 
 }  // namespace mlb

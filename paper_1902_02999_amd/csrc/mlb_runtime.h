@@ -41,6 +41,12 @@ void grid_tiles(const mlb_grid* g, int rows, std::vector<TileDev>& out);
 
 namespace mlb {
 
+struct Plan;
+// Takes a plan off its context's list of plans with an unchecked persistent launch.
+void plan_unwatch(Plan& P);
+// The grid's fields were replaced: its last checked diagnostics no longer apply.
+void grid_state_changed(mlb_grid* g);
+
 // Device-side plan of a set of basins: descriptors, tile list,
 // reduction partials, and an optional captured chunk of steps.
 struct Plan {
@@ -63,6 +69,8 @@ struct Plan {
     int32_t* herr = nullptr;     // pinned copy of dsync->err
     uint64_t sync_base = 0;      // dsync->count when the next persistent launch starts
     bool coop_failed = false;    // a persistent launch was refused: use ordinary ones
+    bool err_pending = false;    // herr holds a stream-ordered copy of dsync->err not yet checked
+    mlb_ctx* watch = nullptr;    // the context listing this plan while err_pending
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
     bool masked = false;       // some basin has a node mask: one-step passes, masked kernel
     bool implicit = false;     // the basins use the implicit link depth: one-step passes
@@ -72,13 +80,14 @@ struct Plan {
 
     void release()
     {
+        plan_unwatch(*this);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0; gkind = 0;
         (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dt2); (void)hipFree(dpart);
         (void)hipFree(dsync);
         if (herr) (void)hipHostFree(herr);
-        dsync = nullptr; herr = nullptr; sync_base = 0; coop_failed = false;
+        dsync = nullptr; herr = nullptr; sync_base = 0; coop_failed = false; err_pending = false;
         (void)hipFree(dout);
         if (hout) (void)hipHostFree(hout);
         db = nullptr; dt = nullptr; dt2 = nullptr; dpart = nullptr; dout = nullptr; hout = nullptr;
@@ -98,6 +107,12 @@ struct mlb_ctx {
     std::string arch;          // gcnArchName, for autotuner cache keys
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
+    // the last call's bulk passes (its passes of the plan's kind, without a
+    // leading single step and the closing checked pass), timed alone
+    hipEvent_t ev2 = nullptr, ev3 = nullptr;
+    int64_t bulk_passes = 0;
+    int bulk_kind = 0;
+    std::vector<mlb::Plan*> watch;   // plans with an unchecked persistent launch
     int stall_checks = 0;      // 0: off
     int spin_limit = 1 << 22;  // polls of a persistent launch's barrier wait (MLB_SPIN_LIMIT)
 };
@@ -114,6 +129,8 @@ struct mlb_grid {
     float* qy[2] = {nullptr, nullptr};
     float* H = nullptr;
     int64_t* stepc = nullptr;
+    double* dres = nullptr;    // [8] in the workspace header: the last checked pass's finalised sums
+    bool diag_fresh = false;   // dres holds the diagnostics of the current state's last step
     std::vector<float> Hf;     // stored (FP32) still-water depth, host copy
     std::vector<double> Hd;    // still-water depth zeta_ref - z_b as given (FP64):
                                // host conversions h <-> eta and the mass use it

@@ -534,6 +534,7 @@ mlb_status mlb_net_infer(mlb_net* n, mlb_grid* g)
     HIPCHK(nn::guess_to_state(n->yout, g->p.nx, g->p.ny, g->ld, (float)(n->norm.s_eta * f),
                               (float)(n->norm.s_q * f), wall4, n->dloss, n->xstage,
                               g->eta[0], g->qx[0], g->qy[0], g->eta[1], g->qx[1], g->qy[1], s));
+    grid_state_changed(g);
     return MLB_OK;
 }
 

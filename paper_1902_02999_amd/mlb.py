@@ -136,6 +136,7 @@ SIGNATURES = {
     "mlb_batch_set_exec_opts": (C.c_int, [_VP, C.POINTER(ExecOpts)]),
     "mlb_batch_destroy": (C.c_int, [_VP]),
     "mlb_last_step_ms": (C.c_int, [_VP, _DP]),
+    "mlb_last_pass_ms": (C.c_int, [_VP, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "mlb_copy_probe": (C.c_int, [_VP, C.c_size_t, C.c_int32, _DP]),
     "mlb_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
     "mlb_batch_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
@@ -230,6 +231,14 @@ class Context:
         v = C.c_double()
         _check(lib().mlb_last_step_ms(self.h, C.byref(v)), "mlb_last_step_ms")
         return v.value
+
+    def last_pass_ms(self):
+        """(ms per pass, passes, steps per pass) of the last call's bulk passes."""
+        v = C.c_double()
+        n = C.c_int64()
+        k = C.c_int32()
+        _check(lib().mlb_last_pass_ms(self.h, C.byref(v), C.byref(n), C.byref(k)), "mlb_last_pass_ms")
+        return v.value, n.value, k.value
 
     def copy_probe(self, nbytes: int, reps: int = 10) -> float:
         """Read + write GB/s of a plain device copy of nbytes."""

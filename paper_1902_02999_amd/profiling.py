@@ -20,10 +20,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "mlb_kernels.hip")
 
 
+STEP_IMPL = os.path.join(HERE, "csrc", "mlb_step_impl.h")
+STEP_UNITS = ("mlb_kernels.hip", "mlb_kernels2.hip", "mlb_persist.hip")
+
+
 def kernel_sha(src: str = KERNEL_SRC) -> str:
-    """Short hash of a kernel source file (default: the step kernels)."""
+    """Short hash of a kernel source file (default: the one-step kernels); for
+    the step kernels' translation units it covers the device code they share
+    (mlb_step_impl.h) as well."""
+    h = hashlib.sha256()
     with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        h.update(f.read())
+    if os.path.basename(src) in STEP_UNITS:
+        with open(STEP_IMPL, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _find(d: str, suffix: str) -> str:

@@ -42,3 +42,6 @@ def test_default_report_fields():
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS" and cb["value"] > 0 and cb["cores"] >= 1
     assert "512x512" in cb["sample"]
+    assert cb["value_1_thread"] > 0   # the oracle on one thread beside all cores
+    # the roofline comes from the bulk two-step passes timed alone
+    assert d["config"]["launch_us"] > 0

@@ -239,7 +239,12 @@ def test_two_step_passes_bitwise(ctx, case):
 
 
 def test_two_step_diag_and_steady_match(ctx):
-    """Residual, mass and the converged state agree bit for bit with tblock 1."""
+    """Steady-state runs stop at the same check with the same state bit for
+    bit with one or two steps per pass.  The two-step run's checks are fused
+    into its closing two-step pass (the residual against the level it holds
+    in registers): its FP64 sums run over the two-step tiles, so they agree
+    with the one-step checks to summation order (1e-13), and the per-node
+    maximum and the count exactly."""
     from paper_1902_02999_amd import mlb
     spec = closed_spec(90, 70, 4)
     res = []
@@ -247,15 +252,61 @@ def test_two_step_diag_and_steady_match(ctx):
         g = mlb.grid_from_spec(ctx, spec)
         g.set_exec_opts(tblock=tb, tile_rows=12)
         ok, d = g.run_steady(1e-5, 200000, 100)
-        g.step(3)
+        g.step(4)
         res.append((ok, d, g.diag(), g.get_state()))
         g.close()
     (ok1, d1, e1, s1), (ok2, d2, e2, s2) = res
     assert ok1 and ok2
-    for k in ("step", "mass", "residual", "max_speed", "nonfinite"):
+    for k in ("step", "max_speed", "nonfinite"):
         assert d1[k] == d2[k] and e1[k] == e2[k], k
+    for k in ("mass", "residual"):
+        assert d2[k] == pytest.approx(d1[k], rel=1e-13) and e2[k] == pytest.approx(e1[k], rel=1e-13), k
     for a, b in zip(s1, s2):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["closed", "channel", "dish", "implicit", "friction_periodic"])
+@pytest.mark.parametrize("n", [50, 51, 2])
+def test_fused_two_step_diag_equals_one_step_diag(ctx, case, n):
+    """A call of n steps ends with a checked pass of its own kind: with two
+    steps per pass the residual of the last step is taken against the level
+    the pass holds in registers.  It equals the one-step run's (same fields
+    bit for bit) to FP64 summation order; the bulk passes are timed alone."""
+    from paper_1902_02999_amd import mlb
+    if case == "closed":
+        spec = closed_spec(130, 90, 5)
+    elif case == "channel":
+        spec = wl.bump_channel(150, 70, sigma=9.0)
+    elif case == "dish":
+        spec = wl.circular_dish(120, 400.0 / 120)
+    elif case == "implicit":
+        spec = wl.bump_channel(96, 80, sigma=8.0, bump=0.4)
+        spec.hbar_implicit = True
+    else:
+        spec = closed_spec(100, 64, 6)
+        spec.edges = (wl.PERIODIC,) * 4
+    out = []
+    for tb in (1, 2):
+        g = mlb.grid_from_spec(ctx, spec)
+        g.set_exec_opts(tblock=tb, tile_rows=11, graph_chunk=8)
+        g.step(7)
+        say(case, "n", n, "tblock", tb)
+        g.step(n)
+        d = g.diag()
+        if tb == 2 and n == 50:
+            ms, passes, k = ctx.last_pass_ms()
+            assert (passes, k) == (24, 2) and ms > 0
+        out.append((d, g.get_state()))
+        g.close()
+    (d1, s1), (d2, s2) = out
+    for a, b in zip(s1, s2):
+        assert np.array_equal(a, b)
+    assert d1["step"] == d2["step"] == 7 + n
+    assert d1["nonfinite"] == d2["nonfinite"] == 0
+    assert d2["max_speed"] == d1["max_speed"]
+    assert d2["mass"] == pytest.approx(d1["mass"], rel=1e-13)
+    assert d1["residual"] > 0
+    assert d2["residual"] == pytest.approx(d1["residual"], rel=1e-12)
 
 
 def test_two_step_batch_bitwise(ctx):
@@ -343,6 +394,20 @@ def test_persistent_barrier_timeout_is_reported(ctx, monkeypatch):
     with pytest.raises(mlb.MlbError) as ei:
         g.diag()
     assert ei.value.name == "MLB_E_DEVICE"
+    # every call that hands out state reports the give-up, once
+    for call in (lambda: g.get_state(), lambda: c.sync()):
+        g.set_state(*state)
+        g.step(20)
+        with pytest.raises(mlb.MlbError) as ei:
+            call()
+        assert ei.value.name == "MLB_E_DEVICE"
+        c.sync()   # reported and cleared
+    # the autotuner never keeps a persistent candidate whose launches gave up
+    g.set_state(*state)
+    best = g.autotune(steps=8)
+    assert best["persistent"] == 0
+    g.step(20)
+    g.get_state()
     # recovered: ordinary launches from a fresh state match a fresh grid
     g.set_state(*state)
     g.set_exec_opts(tile_rows=4, tblock=1, persistent=0)
