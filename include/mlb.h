@@ -264,6 +264,21 @@ mlb_status mlb_step(mlb_grid* g, int64_t nsteps);
  * the state, whose residual is 0.  Syncs.  MLB_E_DEVICE if a persistent launch
  * gave up at a pass barrier. */
 mlb_status mlb_diag(mlb_grid* g, mlb_diag_t* out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mlb_diag
+ * with the result written to out_dev, an mlb_diag_t in device memory,
+ * enqueued on the context stream without waiting; it never builds the grid's
+ * launch plan and allocates nothing.  When the fields were set since the last
+ * checked pass it reduces the state with partial sums of tiles of 64 x 64
+ * nodes kept in a fixed device array of the library (16384 tiles, 768 KiB
+ * per GPU, held until the process ends; each call writes every partial it
+ * reads, so nothing needs clearing): MLB_E_INVAL for a grid of more tiles
+ * (about 67 M nodes); its sums then equal mlb_diag's to FP64 summation order.
+ * Otherwise it takes the sums the last checked pass kept, as mlb_diag does.
+ * Calls that overlap on one GPU (several streams or host threads) race on
+ * the array.  It does not wait, so it does not report a persistent launch's
+ * give-up (mlb_ctx_sync does).  MLB_E_STATE inside a live batch. */
+mlb_status mlb_diag_noalloc(mlb_grid* g, mlb_diag_t* out_dev);
 /* Steps until the residual of a checked step is <= tol.  Checks every
  * check_every steps (the checked step is reduced in the same kernel pass).
  * MLB_E_NONFINITE on a non-finite value or h <= 0, MLB_E_NOTCONVERGED after

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlb.so")
-SOURCES = ["mlb_kernels.hip", "mlb_kernels2.hip", "mlb_persist.hip", "mlb_api.hip", "nn_kernels.hip", "nn_api.hip", "elab_kernels.hip", "elab_api.hip"]
+SOURCES = ["mlb_kernels.hip", "mlb_kernels2.hip", "mlb_persist.hip", "mlb_noalloc.hip", "mlb_api.hip", "nn_kernels.hip", "nn_api.hip", "elab_kernels.hip", "elab_api.hip"]
 ARCH = os.environ.get("MLB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

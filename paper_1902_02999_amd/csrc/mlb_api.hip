@@ -656,6 +656,7 @@ mlb_status mlb_ctx_create(int device, void* hip_stream, mlb_ctx** out)
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(MLB_E_INVAL, "no such device");
     HIPCHK(hipSetDevice(device));
+    CHK(noalloc_setup(device));
     mlb_ctx* c = new (std::nothrow) mlb_ctx();
     if (!c) return fail(MLB_E_NOMEM, "ctx");
     c->device = device;

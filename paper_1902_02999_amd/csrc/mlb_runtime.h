@@ -17,6 +17,10 @@ mlb_status fail(mlb_status s, const std::string& msg);
 // tolerance (a run from rest passes through transient minima far above it).
 constexpr double kStallBand = 10.0;
 
+// Looks up the device's copy of the allocation-free entry point's scratch
+// array (mlb_noalloc.hip); once per device, with the device current.
+mlb_status noalloc_setup(int device);
+
 // Sets a grid's step counter (host and device copies); syncs the stream.
 mlb_status grid_set_step(mlb_grid* g, int64_t s);
 

@@ -137,6 +137,7 @@ SIGNATURES = {
     "mlb_batch_destroy": (C.c_int, [_VP]),
     "mlb_last_step_ms": (C.c_int, [_VP, _DP]),
     "mlb_last_pass_ms": (C.c_int, [_VP, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "mlb_diag_noalloc": (C.c_int, [_VP, _VP]),
     "mlb_copy_probe": (C.c_int, [_VP, C.c_size_t, C.c_int32, _DP]),
     "mlb_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
     "mlb_batch_autotune": (C.c_int, [_VP, C.c_int32, C.c_char_p, C.POINTER(ExecOpts)]),
@@ -372,6 +373,12 @@ class Grid:
 
     def step(self, n: int = 1):
         _check(lib().mlb_step(self.h, int(n)), "mlb_step")
+
+    def diag_noalloc(self, out_dev):
+        """mlb_diag_noalloc into a device buffer of at least 80 bytes (a torch
+        tensor or a device pointer); enqueued, returns without waiting."""
+        ptr = out_dev if isinstance(out_dev, int) else out_dev.data_ptr()
+        _check(lib().mlb_diag_noalloc(self.h, C.c_void_p(ptr)), "mlb_diag_noalloc")
 
     def diag(self) -> dict:
         d = Diag()
