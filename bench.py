@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run the plain copy kernel on this many MiB and print GB/s")
     ap.add_argument("--blocks-per-cu", type=int, default=3)
+    ap.add_argument("--persistent", type=int, default=0, choices=[0, 1, 2],
+                    help="when not autotuning: 0 one launch per pass, 1 cooperative grid barrier, 2 work queue")
     ap.add_argument("--tblock", type=int, default=1, choices=[1, 2],
                     help="steps per kernel pass when not autotuning")
     ap.add_argument("--no-autotune", action="store_true",
@@ -213,7 +215,7 @@ def main():
     spec.compensated = args.compensated
     grid = mlb.grid_from_spec(ctx, spec)
     grid.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
-                       blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
+                       blocks_per_cu=args.blocks_per_cu, tblock=args.tblock, persistent=args.persistent)
     tuned = None if args.no_autotune else grid.autotune(steps=40)
 
     wall, ev_ms, bulk = timed_steps(ctx, grid, args.warmup, args.steps)
@@ -299,10 +301,10 @@ def bench_ensemble(args, ctx, copy_gbps):
     nodes = sum(s.nodes for s in specs)
     b = mlb.Batch(ctx, grids)
     b.set_exec_opts(tile_rows=args.tile_rows, use_graph=not args.no_graph, graph_chunk=100,
-                    blocks_per_cu=args.blocks_per_cu, tblock=args.tblock)
+                    blocks_per_cu=args.blocks_per_cu, tblock=args.tblock, persistent=args.persistent)
     tuned = None if args.no_autotune else b.autotune(steps=30)
     opts = tuned or {"tile_rows": args.tile_rows, "tblock": args.tblock, "use_graph": int(not args.no_graph),
-                     "graph_chunk": 100, "blocks_per_cu": args.blocks_per_cu, "persistent": 0}
+                     "graph_chunk": 100, "blocks_per_cu": args.blocks_per_cu, "persistent": args.persistent}
     wall, ev_ms, bulk = timed_steps(ctx, b, args.warmup, args.steps)
     ok, diags = b.run_steady(0.0, 1, 1)   # one checked step: finiteness of every basin
     bad = sum(d["nonfinite"] for d in diags)

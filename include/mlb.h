@@ -169,6 +169,19 @@ mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld);
 mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
                           int32_t tblock, int32_t* tiles, int64_t capacity, int64_t* count);
 
+/* The dependency lists the work-queue launches (mlb_exec_opts.persistent = 2)
+ * of such a grid use, without a device, for the tile list of mlb_plan_tiles
+ * (same arguments): the item of tile t in pass p waits until every tile
+ * nbr[off[t]] .. nbr[off[t+1] - 1] (t itself included, ascending) has
+ * completed pass p - 1.  They are the tiles owning a node of t's window (what
+ * its wave loads) and the tiles whose window holds a node t owns.  Writes at
+ * most off_capacity offsets (ntiles + 1 are needed) and nbr_capacity indices;
+ * *ntiles and *nnbr receive the counts.  MLB_E_STATE if a tile would depend
+ * on more than 64 tiles (such grids step with ordinary launches). */
+mlb_status mlb_plan_workqueue(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
+                              int32_t tblock, int32_t* off, int64_t off_capacity, int32_t* nbr,
+                              int64_t nbr_capacity, int64_t* ntiles, int64_t* nnbr);
+
 /* Link depth h-bar of the bed term (Section 3).
  *   SEMI_IMPLICIT  h-bar = (h(x,t) + h(x - e_a dt,t)) / 2, Eq. (h-bar): the
  *                  form the paper prefers; exact volume conservation and the
@@ -299,20 +312,30 @@ typedef struct {
     int32_t use_graph;     /* 1: capture chunks of steps in a hipGraph                    */
     int32_t graph_chunk;   /* steps per captured graph, 2..100000                         */
     int32_t blocks_per_cu; /* 0: no cap; 1..8: at most this many step workgroups per CU   */
-    int32_t persistent;    /* 1: run a call's passes in one cooperative launch with a grid
-                            * barrier between passes, when every tile fits on the device
-                            * at once (else ordinary launches); for small grids, where
-                            * launches dominate.  A barrier that times out stops the
-                            * launch; the next mlb_diag / mlb_run_steady reports
-                            * MLB_E_DEVICE and the state must be set again             */
+    int32_t persistent;    /* 0: one launch per pass (graph chunks).
+                            * 1: a call's passes in one cooperative launch with a grid
+                            *    barrier between passes, when every tile fits on the device
+                            *    at once (else ordinary launches); for small grids, where
+                            *    launches dominate.
+                            * 2: a call's passes in one persistent launch driven by a
+                            *    work queue: a grid of the resident size takes (pass, tile)
+                            *    items from an atomic cursor and each item waits for the
+                            *    epoch flags of the tiles it depends on, so passes overlap
+                            *    instead of draining at a barrier; any grid or batch size.
+                            * Waits are bounded: a wait that times out stops the launch;
+                            * the next mlb_diag, mlb_run_steady, mlb_get_state*,
+                            * mlb_ctx_sync or step call reports MLB_E_DEVICE and the state
+                            * must be set again.  The implicit link depth and the
+                            * compensated surface take ordinary launches.               */
 } mlb_exec_opts;
 mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
 mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
 
 /* Autotuner: times the step for every (tblock, tile_rows, blocks_per_cu)
  * triple of a fixed candidate set (tblock 1 with tile rows 6..45 in steps of
- * 3k, tblock 2 with tile rows 8..44 of the form 3k + 2; caps 0, 2..5; plus
- * persistent launches where every tile fits on the device at once) with HIP
+ * 3k, tblock 2 with tile rows 8..44 of the form 3k + 2; caps 0, 2..5), each
+ * with graph launches, work-queue launches, and cooperative launches where
+ * every tile fits on the device at once, with HIP
  * events (median of 3 runs of `steps` steps), applies the
  * fastest and returns it in *best (may be NULL).  The grid's state and step
  * counter are restored afterwards (results are bitwise independent of these

@@ -288,6 +288,8 @@ mlb_status check_abort(mlb_ctx* c, Plan& P)
         HIPCHK(hipMemsetAsync(P.dsync, 0, sizeof(SyncState), c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         P.sync_base = 0;
+        P.wq[0].release();   // epochs of an abandoned launch: rebuilt on next use
+        P.wq[1].release();
         return fail(MLB_E_DEVICE, "a persistent launch timed out at a pass barrier; the state is incomplete");
     }
     return MLB_OK;
@@ -298,6 +300,90 @@ mlb_status check_abort(mlb_ctx* c, Plan& P)
 mlb_status peek_abort(mlb_ctx* c, Plan& P)
 {
     if (P.err_pending && *(volatile int32_t*)P.herr) return check_abort(c, P);
+    return MLB_OK;
+}
+
+// Dependency lists of a plan's tile list for work-queue launches.  A tile's
+// owned nodes form a (strip, band) cell of its basin; its window is what its
+// wave loads (one-step tiles columns x0-1 .. x0+62 and rows y0-1 .. y0+rows,
+// two-step tiles columns x0-2 .. x0+61 and rows y0-2 .. y0+rows+1, wrapped on
+// periodic axes, clamped otherwise).  W(t) = the tiles owning a node of t's
+// window; D(t) = W(t) plus every u with t in W(u) (u reads what t writes).
+// An item (p, t) waits until every tile of D(t) has completed pass p - 1:
+// its reads then see pass p - 1's values, and no tile still reads the
+// buffer it overwrites.
+// false when some tile has more than kWave dependencies.
+bool wq_dependencies(const std::vector<BasinDev>& hb, const std::vector<TileDev>& tl, int kind,
+                     std::vector<int32_t>& off, std::vector<int32_t>& nbr)
+{
+    const int nt = (int)tl.size(), strip = kind == 2 ? kStripOut2 : kStripOut, halo = kind == 2 ? 2 : 1;
+    std::vector<std::vector<int32_t>> dep(nt);
+    int i0 = 0;
+    while (i0 < nt) {   // the tiles of one basin are contiguous in the list
+        const int b = tl[i0].basin;
+        int i1 = i0;
+        while (i1 < nt && tl[i1].basin == b) ++i1;
+        const BasinDev& B = hb[b];
+        const int nx = B.nx, ny = B.ny;
+        int ty = ny;   // band height: the smallest positive first owned row
+        for (int i = i0; i < i1; ++i)
+            if (tl[i].yo > 0) ty = std::min(ty, tl[i].yo);
+        const int ns = (nx + strip - 1) / strip, nb = (ny + ty - 1) / ty;
+        std::vector<int32_t> cell((size_t)ns * nb, -1);
+        for (int i = i0; i < i1; ++i) cell[(size_t)(tl[i].yo / ty) * ns + tl[i].xo / strip] = i;
+        auto wrap = [](int v, int n, int per) { return per ? ((v % n) + n) % n : std::min(std::max(v, 0), n - 1); };
+        std::vector<int> sx, sy;
+        for (int i = i0; i < i1; ++i) {
+            const TileDev& T = tl[i];
+            sx.clear(); sy.clear();
+            for (int x = T.x0 - halo; x < T.x0 - halo + kWave; ++x) sx.push_back(wrap(x, nx, B.per_x) / strip);
+            for (int y = T.y0 - halo; y <= T.y0 + T.rows + halo - 1; ++y) sy.push_back(wrap(y, ny, B.per_y) / ty);
+            std::sort(sx.begin(), sx.end()); sx.erase(std::unique(sx.begin(), sx.end()), sx.end());
+            std::sort(sy.begin(), sy.end()); sy.erase(std::unique(sy.begin(), sy.end()), sy.end());
+            for (int yb : sy)
+                for (int xs : sx) {
+                    const int u = cell[(size_t)yb * ns + xs];
+                    if (u < 0) continue;   // a tile left out (every node it would own is SOLID)
+                    dep[i].push_back(u);
+                    dep[u].push_back(i);
+                }
+        }
+        i0 = i1;
+    }
+    off.assign(nt + 1, 0);
+    nbr.clear();
+    for (int i = 0; i < nt; ++i) {
+        auto& d = dep[i];
+        d.push_back(i);
+        std::sort(d.begin(), d.end());
+        d.erase(std::unique(d.begin(), d.end()), d.end());
+        if (d.size() > (size_t)kWave) return false;
+        off[i + 1] = off[i] + (int32_t)d.size();
+        nbr.insert(nbr.end(), d.begin(), d.end());
+    }
+    return true;
+}
+
+mlb_status build_workqueue(mlb_ctx* c, Plan& P, int kind)
+{
+    WqBuf& W = P.wq[kind - 1];
+    const int nt = (int)(kind == 2 ? P.ht2 : P.ht).size();
+    std::vector<int32_t> off, nbr;
+    if (!wq_dependencies(P.hb, kind == 2 ? P.ht2 : P.ht, kind, off, nbr)) { W.failed = true; return MLB_OK; }
+    W.release();
+    HIPCHK(hipMalloc((void**)&W.q.cursor, sizeof(uint32_t)));
+    HIPCHK(hipMalloc((void**)&W.q.epoch, std::max(1, nt) * sizeof(uint32_t)));
+    HIPCHK(hipMalloc((void**)&W.q.nbr_off, off.size() * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void**)&W.q.nbr, std::max<size_t>(1, nbr.size()) * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void**)&W.q.base, P.hb.size() * sizeof(int64_t)));
+    HIPCHK(hipMemsetAsync(W.q.epoch, 0, std::max(1, nt) * sizeof(uint32_t), c->stream));
+    HIPCHK(hipMemcpyAsync((void*)W.q.nbr_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync((void*)W.q.nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    W.q.err = &P.dsync->err;
+    W.passes = 0;
+    W.ok = true;
     return MLB_OK;
 }
 
@@ -344,9 +430,38 @@ mlb_status enqueue_steps(mlb_ctx* c, Plan& P, const mlb_exec_opts& o, int64_t n,
     HIPCHK(hipEventRecord(c->ev2, c->stream));
     c->bulk_passes = multi;
     c->bulk_kind = kind;
+    // work queue: all `multi` passes in persistent launches ordered per tile
+    // by epoch flags (not for the implicit link depth or the compensated
+    // surface: those basins use ordinary launches)
+    if (o.persistent == 2 && multi > 0 && !P.implicit && !P.comp) {
+        WqBuf& W = P.wq[kind - 1];
+        if (!W.ok && !W.failed) CHK(build_workqueue(c, P, kind));
+        if (W.ok) {
+            const int nt = kind == 2 ? nt2 : nt1;
+            int64_t nblk = (int64_t)workqueue_occupancy(kind, P.masked ? 1 : 0, P.closed ? 1 : 0) * c->ncu;
+            if (o.blocks_per_cu > 0) nblk = std::min<int64_t>(nblk, (int64_t)o.blocks_per_cu * c->ncu);
+            // items are 32-bit: at most 2^31 per launch
+            const int64_t maxp = std::max<int64_t>(1, ((int64_t)1 << 31) / std::max(1, nt));
+            while (multi > 0) {
+                const int np = (int)std::min<int64_t>(multi, std::min<int64_t>(maxp, 1 << 16));
+                // about one wave per tile of a pass: every wave then works or
+                // waits for the pass before, and few waves poll at once
+                const int nb = (int)std::max<int64_t>(
+                    1, std::min<int64_t>(nblk, ((int64_t)nt + kBlock / kWave - 1) / (kBlock / kWave)));
+                HIPCHK(launch_workqueue(P.db, (int)P.hb.size(), kind == 2 ? P.dt2 : P.dt, nt, P.parity, np, kind,
+                                        P.masked ? 1 : 0, P.closed ? 1 : 0, W.q, W.passes, c->spin_limit, nb, dyn,
+                                        c->stream));
+                W.passes += (uint32_t)np;
+                P.parity ^= np & 1;
+                nl += np;
+                multi -= np;
+                CHK(watch_abort(c, P));
+            }
+        }
+    }
     // persistent: all `multi` passes in cooperative launches with grid barriers
     // (not for the implicit link depth: those basins use ordinary launches)
-    if (o.persistent && multi > 0 && !P.coop_failed && !P.implicit && !P.comp) {
+    if (o.persistent == 1 && multi > 0 && !P.coop_failed && !P.implicit && !P.comp) {
         const int nt = kind == 2 ? nt2 : nt1;
         const int nblk = (nt + kBlock / kWave - 1) / (kBlock / kWave);
         if (persistent_capacity(kind, P.masked ? 1 : 0, c->ncu) < nblk) {
@@ -897,6 +1012,41 @@ mlb_status mlb_plan_tiles(const mlb_params* p, const uint8_t* kind, int64_t kind
     return MLB_OK;
 }
 
+mlb_status mlb_plan_workqueue(const mlb_params* p, const uint8_t* kind, int64_t kind_ld, int32_t tile_rows,
+                              int32_t tblock, int32_t* off, int64_t off_capacity, int32_t* nbr,
+                              int64_t nbr_capacity, int64_t* ntiles, int64_t* nnbr)
+{
+    CHK(validate_params(p));
+    if (!ntiles || !nnbr || (off_capacity > 0 && !off) || (nbr_capacity > 0 && !nbr))
+        return fail(MLB_E_INVAL, "a count or list pointer is NULL");
+    if (tile_rows < 4 || tile_rows > 4096) return fail(MLB_E_INVAL, "tile_rows out of range");
+    if (tblock != 1 && tblock != 2) return fail(MLB_E_INVAL, "tblock must be 1 or 2");
+    if (kind && kind_ld < p->nx) return fail(MLB_E_INVAL, "kind_ld < nx");
+    mlb_grid g;
+    g.p = *p;
+    (void)field_bytes(p, &g.ld);
+    if (kind) {
+        g.hmask.assign((size_t)g.ld * p->ny, (uint8_t)NODE_FLUID);
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                const uint8_t k = kind[(size_t)j * kind_ld + i];
+                if (k > NODE_SOLID) return fail(MLB_E_INVAL, "node kind must be FLUID, WALL or SOLID");
+                g.hmask[(size_t)j * g.ld + i] = k;
+            }
+    }
+    std::vector<TileDev> t;
+    make_tiles(&g, 0, tile_rows, t, tblock == 2 ? kStripOut2 : kStripOut);
+    std::vector<BasinDev> hb(1, make_basin(&g, 0));
+    std::vector<int32_t> o, n;
+    if (!wq_dependencies(hb, t, tblock, o, n))
+        return fail(MLB_E_STATE, "a tile depends on more than 64 tiles: work-queue launches are not used");
+    *ntiles = (int64_t)t.size();
+    *nnbr = (int64_t)n.size();
+    for (int64_t i = 0; i < std::min<int64_t>(off_capacity, (int64_t)o.size()); ++i) off[i] = o[i];
+    for (int64_t i = 0; i < std::min<int64_t>(nbr_capacity, (int64_t)n.size()); ++i) nbr[i] = n[i];
+    return MLB_OK;
+}
+
 mlb_status mlb_set_mask(mlb_grid* g, const uint8_t* kind, int64_t ld)
 {
     GRID_OK(g);
@@ -1072,7 +1222,7 @@ static mlb_status check_opts(const mlb_exec_opts* o)
     if (o->blocks_per_cu < 0 || o->blocks_per_cu > 8) return fail(MLB_E_INVAL, "blocks_per_cu must be 0..8");
     if (o->use_graph && (o->graph_chunk < 2 || o->graph_chunk > 100000))
         return fail(MLB_E_INVAL, "graph_chunk out of range");
-    if (o->persistent != 0 && o->persistent != 1) return fail(MLB_E_INVAL, "persistent must be 0 or 1");
+    if (o->persistent < 0 || o->persistent > 2) return fail(MLB_E_INVAL, "persistent must be 0, 1 or 2");
     return MLB_OK;
 }
 
@@ -1474,13 +1624,13 @@ mlb_status tune(mlb_ctx* c, mlb_exec_opts* opts, int steps, const std::vector<ml
     const int n = std::max(2, steps & ~1);
     bool one = false;   // the compensated surface runs one step per pass
     for (auto* g : gs) one |= g->etal != nullptr;
-    for (int ps = 0; ps < 2; ++ps)
+    for (int ps = 0; ps < 3; ++ps)
     for (int tb : kTuneBlocks)
     for (int tr : (tb == 2 ? std::vector<int>(std::begin(kTuneRows2), std::end(kTuneRows2))
                            : std::vector<int>(std::begin(kTuneRows), std::end(kTuneRows))))
         for (int cap : kTuneCaps) {
-            // persistent launches need every tile resident: no workgroup cap
-            if (ps && (cap != 0 || !fits_persistent(c, gs, tr, tb))) continue;
+            // cooperative launches need every tile resident: no workgroup cap
+            if (ps == 1 && (cap != 0 || !fits_persistent(c, gs, tr, tb))) continue;
             if (one && tb == 2) continue;
             mlb_exec_opts o = base;
             o.persistent = ps;

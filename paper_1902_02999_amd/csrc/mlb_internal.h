@@ -66,6 +66,20 @@ struct SyncState {
     int32_t pad;
 };
 
+// Work queue of a persistent launch (device memory).  Items are (pass, tile)
+// in pass-major, list order; a wave takes the next item from the cursor and
+// waits until every tile its item depends on (the tiles whose owned nodes
+// its window reads, and those whose windows read its owned nodes) has
+// completed the previous pass.
+struct WorkQueue {
+    uint32_t* cursor;        // [1] items handed out in the current launch
+    uint32_t* epoch;         // [ntiles] passes each tile has completed, over all launches
+    const int32_t* nbr_off;  // [ntiles + 1] dependency list of tile t: nbr[nbr_off[t] .. nbr_off[t+1])
+    const int32_t* nbr;      // tile indices (the tile itself included), at most 64 per tile
+    int64_t* base;           // [nbasins] each basin's step counter when the launch starts
+    int32_t* err;            // set when a bounded wait gave up (the plan's SyncState::err)
+};
+
 // One wave's work item: a strip of up to 62 columns and `rows` rows.
 struct TileDev {
     int32_t basin;
@@ -121,6 +135,16 @@ hipError_t launch_persistent(const BasinDev* d_basins, const TileDev* d_tiles, i
                              hipStream_t s);
 // Workgroups of the persistent kernel that fit on the device at once.
 int persistent_capacity(int kind, int masked, int ncu);
+// npasses passes of `kind` steps in one launch of `nblocks` workgroups driven
+// by the work queue q (the cursor is reset and the basins' step counters
+// snapshot by a prologue kernel on the same stream).  epoch0: passes the
+// queue's tiles completed before this launch.  closed: no basin has an open
+// edge (two-step passes take the kernel without open-edge logic).
+hipError_t launch_workqueue(const BasinDev* d_basins, int nbasins, const TileDev* d_tiles, int ntiles, int parity0,
+                            int npasses, int kind, int masked, int closed, const WorkQueue& q, uint32_t epoch0,
+                            int spin_limit, int nblocks, unsigned dyn_lds, hipStream_t s);
+// Resident workgroups per CU of the work-queue kernel.
+int workqueue_occupancy(int kind, int masked, int closed);
 hipError_t launch_reduce_state(const BasinDev* d_basins, const TileDev* d_tiles, int ntiles,
                                int parity, double* d_partials, hipStream_t s);
 int step_occupancy(int diag);

@@ -51,6 +51,22 @@ void plan_unwatch(Plan& P);
 // The grid's fields were replaced: its last checked diagnostics no longer apply.
 void grid_state_changed(mlb_grid* g);
 
+// Work queue of one tile list of a plan (device buffers, built on first use
+// by a work-queue launch; see WorkQueue).
+struct WqBuf {
+    WorkQueue q{};
+    uint32_t passes = 0;     // passes its tiles have completed (epoch0 of the next launch)
+    bool ok = false;         // built
+    bool failed = false;     // a tile has more than 64 dependencies: ordinary launches
+    void release()
+    {
+        (void)hipFree(q.cursor); (void)hipFree(q.epoch); (void)hipFree((void*)q.nbr_off);
+        (void)hipFree((void*)q.nbr); (void)hipFree(q.base);
+        q = WorkQueue{};
+        passes = 0; ok = false; failed = false;
+    }
+};
+
 // Device-side plan of a set of basins: descriptors, tile list,
 // reduction partials, and an optional captured chunk of steps.
 struct Plan {
@@ -73,6 +89,7 @@ struct Plan {
     int32_t* herr = nullptr;     // pinned copy of dsync->err
     uint64_t sync_base = 0;      // dsync->count when the next persistent launch starts
     bool coop_failed = false;    // a persistent launch was refused: use ordinary ones
+    WqBuf wq[2];                 // work queues of the one-step [0] and two-step [1] tile lists
     bool err_pending = false;    // herr holds a stream-ordered copy of dsync->err not yet checked
     mlb_ctx* watch = nullptr;    // the context listing this plan while err_pending
     unsigned gdyn = 0;         // dynamic LDS the captured graph was launched with
@@ -90,6 +107,7 @@ struct Plan {
         gexec = nullptr; graph = nullptr; gparity = -1; gsteps = 0; gkind = 0;
         (void)hipFree(db); (void)hipFree(dt); (void)hipFree(dt2); (void)hipFree(dpart);
         (void)hipFree(dsync);
+        wq[0].release(); wq[1].release();
         if (herr) (void)hipHostFree(herr);
         dsync = nullptr; herr = nullptr; sync_base = 0; coop_failed = false; err_pending = false;
         (void)hipFree(dout);

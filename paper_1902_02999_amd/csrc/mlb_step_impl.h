@@ -961,6 +961,13 @@ struct PlainStep {
     __device__ int64_t operator()(const BasinDev& B, int rd) const { return B.stepc[rd]; }
 };
 
+// A step number known when the pass starts (work-queue launches compute it
+// from the basin's counter at the launch and the pass index).
+struct FixedStep {
+    int64_t s;
+    __device__ int64_t operator()(const BasinDev&, int) const { return s; }
+};
+
 // The counter of the previous pass of a persistent launch was written by
 // another workgroup: read it as an agent-scope atomic (a vector load).
 struct CoherentStep {

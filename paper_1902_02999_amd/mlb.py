@@ -115,6 +115,9 @@ SIGNATURES = {
     "mlb_set_hbar": (C.c_int, [_VP, C.c_int32]),
     "mlb_plan_tiles": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_uint8), C.c_int64, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
+    "mlb_plan_workqueue": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_uint8), C.c_int64, C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int32), C.c_int64,
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mlb_set_surface": (C.c_int, [_VP, C.c_int32]),
     "mlb_set_wind": (C.c_int, [_VP, C.c_double, C.c_double]),
     "mlb_set_wind_stress": (C.c_int, [_VP, C.c_double, C.c_double]),
@@ -456,6 +459,25 @@ def plan_tiles(params: Params, tile_rows: int, tblock: int, kind=None) -> np.nda
     _check(lib().mlb_plan_tiles(C.byref(params), kp, kld, int(tile_rows), int(tblock),
                                 out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)), "mlb_plan_tiles")
     return out[:n.value]
+
+
+def plan_workqueue(params: Params, tile_rows: int, tblock: int, kind=None):
+    """The work-queue dependency lists of a grid (no device needed): (off, nbr)
+    with tile t's list nbr[off[t]:off[t+1]] over the tiles of plan_tiles."""
+    kp, kld = None, 0
+    if kind is not None:
+        ka = np.ascontiguousarray(np.asarray(kind).reshape(params.ny, params.nx), np.uint8)
+        kp, kld = ka.ctypes.data_as(C.POINTER(C.c_uint8)), params.nx
+    nt, nn = C.c_int64(), C.c_int64()
+    _check(lib().mlb_plan_workqueue(C.byref(params), kp, kld, int(tile_rows), int(tblock), None, 0, None, 0,
+                                    C.byref(nt), C.byref(nn)), "mlb_plan_workqueue")
+    off = np.zeros(nt.value + 1, np.int32)
+    nbr = np.zeros(max(nn.value, 1), np.int32)
+    _check(lib().mlb_plan_workqueue(C.byref(params), kp, kld, int(tile_rows), int(tblock),
+                                    off.ctypes.data_as(C.POINTER(C.c_int32)), off.size,
+                                    nbr.ctypes.data_as(C.POINTER(C.c_int32)), nbr.size, C.byref(nt), C.byref(nn)),
+           "mlb_plan_workqueue")
+    return off, nbr[:nn.value]
 
 
 def grid_from_spec(ctx: Context, spec, workspace=None) -> Grid:

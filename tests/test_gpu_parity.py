@@ -382,24 +382,32 @@ _PERSIST = [c for c in _TB2 if c[0] in ("closed64", "closed61x9_rows6", "periodi
                                           "ychannel_order2", "ydepth_walls", "tidal_strip")]
 
 
+@pytest.mark.parametrize("persistent", [1, 2], ids=["cooperative", "workqueue"])
 @pytest.mark.parametrize("case", _PERSIST, ids=[c[0] for c in _PERSIST])
-def test_persistent_launches_bitwise(ctx, case):
-    """All passes of a call in one cooperative launch with grid barriers give
-    the bits of one launch per pass, for one and two steps per pass."""
+def test_persistent_launches_bitwise(ctx, case, persistent):
+    """All passes of a call in one persistent launch, separated by grid
+    barriers (1) or ordered per tile by the work queue's epoch flags (2), give
+    the bits of one launch per pass, for one and two steps per pass (the
+    work queue also with a workgroup cap: fewer waves than tiles)."""
     name, spec, state, steps, rows = case
-    say("persistent case", name, spec.nx, spec.ny, "steps", steps)
+    say("persistent", persistent, "case", name, spec.nx, spec.ny, "steps", steps)
     for tb in (1, 2):
         ref = run_gpu(ctx, spec, steps, state, opts={"tile_rows": rows, "tblock": tb})
-        got = run_gpu(ctx, spec, steps, state, opts={"tile_rows": rows, "tblock": tb, "persistent": 1})
-        for a, b in zip(got, ref):
-            assert np.array_equal(a, b), (name, tb)
+        caps = (0, 1) if persistent == 2 else (0,)
+        for cap in caps:
+            say("  tblock", tb, "cap", cap)
+            got = run_gpu(ctx, spec, steps, state,
+                          opts={"tile_rows": rows, "tblock": tb, "persistent": persistent, "blocks_per_cu": cap})
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), (name, tb, cap)
 
 
-def test_persistent_steady_and_batch(ctx):
+@pytest.mark.parametrize("persistent", [1, 2], ids=["cooperative", "workqueue"])
+def test_persistent_steady_and_batch(ctx, persistent):
     from paper_1902_02999_amd import mlb
     spec = closed_spec(90, 70, 4)
     res = []
-    for ps in (0, 1):
+    for ps in (0, persistent):
         g = mlb.grid_from_spec(ctx, spec)
         g.set_exec_opts(tblock=2, tile_rows=6, persistent=ps)
         ok, d = g.run_steady(1e-5, 200000, 100)
@@ -414,13 +422,73 @@ def test_persistent_steady_and_batch(ctx):
     solo = [run_gpu(ctx, s, 45) for s in specs]
     grids = [mlb.grid_from_spec(ctx, s) for s in specs]
     b = mlb.Batch(ctx, grids)
-    b.set_exec_opts(tile_rows=9, tblock=2, persistent=1)
+    b.set_exec_opts(tile_rows=9, tblock=2, persistent=persistent)
     b.step(45)
     b.close()
     for g, ref in zip(grids, solo):
         for x, y in zip(g.get_state(), ref):
             assert np.array_equal(x, y)
         g.close()
+
+
+def test_workqueue_wait_timeout_is_reported(ctx, monkeypatch):
+    """A work-queue launch whose waits may poll zero times gives up at its
+    first wait (forced from the host); every state call reports it, later
+    launches of the plan do nothing until then, and the grid works again once
+    its state is set."""
+    from paper_1902_02999_amd import mlb
+    monkeypatch.setenv("MLB_SPIN_LIMIT", "0")
+    c = mlb.Context(0)
+    monkeypatch.delenv("MLB_SPIN_LIMIT")
+    spec = closed_spec(150, 90, 0)
+    state = wl.seeded_state(spec, 0, q_amp=0.1)
+    g = mlb.grid_from_spec(c, spec)
+    g.set_state(*state)
+    g.set_exec_opts(tile_rows=8, tblock=2, persistent=2)
+    for call in (lambda: g.diag(), lambda: g.get_state(), lambda: c.sync()):
+        g.set_state(*state)
+        g.step(20)
+        with pytest.raises(mlb.MlbError) as ei:
+            call()
+        assert ei.value.name == "MLB_E_DEVICE"
+        c.sync()   # reported and cleared
+    g.set_state(*state)
+    g.set_exec_opts(tile_rows=8, tblock=2, persistent=0)
+    g.step(20)
+    got = g.get_state()
+    g.close()
+    c.close()
+    ref = run_gpu(ctx, spec, 20, state)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+def test_workqueue_ensemble_512_bitwise(ctx):
+    """The 512-basin ensemble (sizes 64^2 .. 512^2, seed 1902) in one
+    work-queue launch per call gives the bits of one graph-launched pass per
+    two steps; states compared on the device."""
+    import torch
+    from paper_1902_02999_amd import mlb
+    specs = wl.ensemble(512, 1902)
+    outs = []
+    for ps in (0, 2):
+        grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+        b = mlb.Batch(ctx, grids)
+        b.set_exec_opts(tile_rows=17, tblock=2, persistent=ps, graph_chunk=100, blocks_per_cu=0)
+        say("ensemble, persistent", ps)
+        b.step(7)
+        b.step(30)
+        b.close()
+        fields = []
+        for g, sp in zip(grids, specs):
+            f = torch.empty((3, sp.ny, sp.nx), dtype=torch.float32, device="cuda")
+            g.get_state_device(f[0], f[1], f[2])
+            fields.append(f)
+            g.close()
+        ctx.sync()
+        outs.append(fields)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
 
 
 def test_persistent_barrier_timeout_is_reported(ctx, monkeypatch):

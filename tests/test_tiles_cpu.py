@@ -130,3 +130,50 @@ def test_costly_tiles_are_dispatched_first(tb):
             assert keys == sorted(keys)
         if per:
             assert n == 0
+
+
+def _wq_brute_force(t, tb, nx, ny, px, py):
+    """Dependency sets of the work queue from a node-level owner map: D(t) =
+    {t} + tiles owning a node of t's window + tiles whose window holds a node
+    t owns."""
+    owner = -np.ones((ny, nx), int)
+    for i, tile in enumerate(t):
+        xs, ys = owned(tile, tb, nx)
+        for y in ys:
+            owner[y, list(xs)] = i
+    reads = []
+    for tile in t:
+        cols, rws = window(tile, tb, nx, ny, px, py)
+        u = owner[np.ix_(sorted(set(rws)), sorted(set(cols)))]
+        reads.append(set(int(v) for v in np.unique(u) if v >= 0))
+    dep = [{i} | r for i, r in enumerate(reads)]
+    for i, r in enumerate(reads):
+        for u in r:
+            dep[u].add(i)
+    return dep
+
+
+@pytest.mark.parametrize("tb", [1, 2])
+@pytest.mark.parametrize("nx,ny,edges,masked", [
+    (200, 130, (wl.WALL,) * 4, False), (300, 7, (wl.PERIODIC,) * 4, False), (5, 5, (wl.WALL,) * 4, False),
+    (61, 62, (wl.DISCHARGE, wl.DEPTH, wl.WALL, wl.WALL), False), (130, 121, (wl.PERIODIC,) * 4, False),
+    (123, 77, (wl.PERIODIC, wl.PERIODIC, wl.DEPTH, wl.WALL), False), (64, 200, (wl.WALL,) * 4, False),
+    (150, 96, (wl.WALL,) * 4, True), (121, 90, (wl.PERIODIC,) * 4, True)])
+def test_workqueue_dependencies_match_brute_force(tb, nx, ny, edges, masked):
+    """The work queue's dependency lists are exactly the brute-force sets:
+    every tile whose owned nodes a tile reads, and every tile reading what it
+    owns (so no item overwrites what a pass still reads, nor reads before the
+    previous pass wrote), ascending, the tile itself included."""
+    p = mlb.make_params(nx, ny, 1.0, 1.0, 2.0, edges)
+    kind = wl.random_geometry(np.random.default_rng(nx + ny), nx, ny) if masked else None
+    if kind is not None and edges[0] == wl.PERIODIC:
+        kind = np.where(kind == wl.SOLID, wl.SOLID, wl.FLUID).astype(np.uint8)
+    for rows in (4, 5, 9, 17, 26, 44):
+        t = mlb.plan_tiles(p, rows, tb, kind=kind)
+        off, nbr = mlb.plan_workqueue(p, rows, tb, kind=kind)
+        assert off.size == len(t) + 1 and off[0] == 0 and off[-1] == nbr.size
+        want = _wq_brute_force(t, tb, nx, ny, edges[0] == wl.PERIODIC, edges[2] == wl.PERIODIC)
+        for i in range(len(t)):
+            got = nbr[off[i]:off[i + 1]]
+            assert list(got) == sorted(want[i]), (rows, i)
+            assert len(got) <= 64
