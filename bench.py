@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=15)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="bump: skip the small warm-vs-cold start measurement added to the default line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run the plain copy kernel on this many MiB and print GB/s")
@@ -285,11 +287,44 @@ def main():
         out["config"]["host_state_inclusive"] = pcie
     grid.close()
     ctx.close()
+    if not args.no_warm:
+        out["config"]["warm_vs_cold"] = warm_vs_cold_small()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def warm_vs_cold_small():
+    """The other half of the metric at a size that fits the default run
+    (about ten seconds): a three-level warm-start net trained from scratch
+    here, by the library's kernels, on the steady states of 128 closed 128^2
+    basins of the ensemble distributions (seed 2999), then wall seconds to
+    R <= 1e-6 warm (inference included) against cold on 12 held-out basins
+    (seed 3000).  The full-size experiment is --workload warm_start."""
+    from paper_1902_02999_amd import mlb, warmstart as ws, workloads as wl
+    ctx = mlb.Context(0)
+    n = 128
+    net = mlb.Net(ctx, n, n, base_ch=32, levels=3, in_ch=32, max_batch=8, seed=2999)
+    t0 = time.perf_counter()
+    data = ws.build_dataset(ctx, net, wl.learned_set(128, 2999, n=n), 1e-6, log=lambda *a: None)
+    for g in data.grids:
+        g.close()
+    data.grids = []
+    losses = ws.train(net, data, ws.TrainSpec(epochs=40, batch=8, lr=2e-3, lr_min=1e-5, warmup_steps=20),
+                      log=lambda *a: None)
+    train_s = time.perf_counter() - t0
+    del data
+    rows = ws.evaluate(ctx, net, wl.learned_set(12, 3000, n=n), 1e-6, log=lambda *a: None)
+    sm = ws.summary(rows)
+    net.close()
+    ctx.close()
+    return {"workload": "learned_warm_start_128 (3-level net, 128 training basins, 40 epochs, 12 held-out)",
+            "cold_s": round(sm["cold_s_total"], 4), "warm_s": round(sm["warm_s_total"], 4),
+            "speedup": round(sm["speedup_total"], 3), "cold_steps_median": sm["cold_steps_median"],
+            "warm_steps_median": sm["warm_steps_median"], "fallbacks": sm["fallbacks"],
+            "train_s": round(train_s, 1), "loss": [round(losses[0], 4), round(losses[-1], 4)]}
 
 
 def bench_ensemble(args, ctx, copy_gbps):

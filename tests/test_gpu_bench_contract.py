@@ -45,3 +45,6 @@ def test_default_report_fields():
     assert cb["value_1_thread"] > 0   # the oracle on one thread beside all cores
     # the roofline comes from the bulk two-step passes timed alone
     assert d["config"]["launch_us"] > 0
+    # the other half of the metric: wall seconds to R <= 1e-6, warm against cold
+    wc = d["config"]["warm_vs_cold"]
+    assert wc["cold_s"] > 0 and wc["warm_s"] > 0 and wc["cold_steps_median"] > 0
