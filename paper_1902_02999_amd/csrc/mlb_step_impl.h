@@ -863,20 +863,37 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     // stored.
     constexpr bool TAIL = !(EDGE && OPEN);
     const int nk = TAIL ? T.rows / 3 : (T.rows + 2) / 3;   // T.rows >= 4, so nk >= 1
-    for (int k = 0; k < nk; ++k) {
-        MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
-        ++rb;
-        MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_NOTHING);
-        ++ra;
-        MLB_ROW(SB, rb, q0, B1, B2, B0, b2, b0, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
-        ++rb;
-        MLB_ROW(SA, ra, wc, A2, A0, A1, a0, a1, wc = MLB_LD(ra + 4), MLB_Q2, MLB_NOTHING);
-        ++ra;
-        MLB_ROW(SB, rb, q1, B2, B0, B1, b0, b1, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
-        ++rb;
-        MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_NOTHING);
-        ++ra;
+    // One round: three (B, A) pairs, after which every rotating slot is back
+    // in place.  The loop runs two rounds per iteration, so a raw slot's
+    // register can alternate between rounds: stage A's window still holds a
+    // slot's old eta and H when the slot's next row is loaded.
+#define MLB_ROUND()                                                                                \
+    do {                                                                                          \
+        MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);          \
+        ++rb;                                                                                     \
+        MLB_ROW(SA, ra, wb, A1, A2, A0, a2, a0, wb = MLB_LD(ra + 4), MLB_Q1, MLB_NOTHING);        \
+        ++ra;                                                                                     \
+        MLB_ROW(SB, rb, q0, B1, B2, B0, b2, b0, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);          \
+        ++rb;                                                                                     \
+        MLB_ROW(SA, ra, wc, A2, A0, A1, a0, a1, wc = MLB_LD(ra + 4), MLB_Q2, MLB_NOTHING);        \
+        ++ra;                                                                                     \
+        MLB_ROW(SB, rb, q1, B2, B0, B1, b0, b1, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);          \
+        ++rb;                                                                                     \
+        MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_NOTHING);        \
+        ++ra;                                                                                     \
+    } while (0)
+    // (interior tiles only: the boundary paths carry more state and would
+    // spill with two rounds in flight)
+    constexpr bool TWO = !EDGE && !XO;
+    int k = 0;
+    if (TWO) {
+        for (; k + 1 < nk; k += 2) {
+            MLB_ROUND();
+            MLB_ROUND();
+        }
     }
+    for (; k < nk; ++k) MLB_ROUND();
+#undef MLB_ROUND
     if (TAIL) {
         MLB_ROW(SB, rb, q2, B0, B1, B2, b1, b2, MLB_NOTHING(), MLB_STORE2, MLB_STORE20);
         ++rb;
