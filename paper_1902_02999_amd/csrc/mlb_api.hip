@@ -67,8 +67,10 @@ BasinDev make_basin(const mlb_grid* g, int swap)
     b.extrap = g->p.extrap_order;
     const double e = g->e, dt = g->dt, gr = g->p.g, e2 = e * e;
     b.e = (float)e;
-    b.tpx = (float)(0.5 * dt * g->tx);
-    b.tpy = (float)(0.5 * dt * g->ty);
+    // (+ 0.0f: a negative zero becomes +0, so that adding the zero Coriolis
+    // term of Omega = 0 never changes a bit and the kernels may omit it)
+    b.tpx = (float)(0.5 * dt * g->tx) + 0.0f;
+    b.tpy = (float)(0.5 * dt * g->ty) + 0.0f;
     b.cfr = (float)(0.5 * dt * g->cb);
     b.omh = (float)(0.5 * dt * g->p.omega);
     b.c3e = (float)(1.0 / (3.0 * e));

@@ -89,8 +89,11 @@ struct Node {
 
 // Node quantities from the old state (Eqs. SWE-force, bed-stress, feq-full).
 // FRIC false: no bed friction (C_b = 0); the friction term is then exactly
-// zero for finite states and is not evaluated.
-template <bool FRIC>
+// zero for finite states and is not evaluated.  COR false: no Coriolis force
+// (Omega = 0); the term Omega q is then exactly zero and adding it changes no
+// bit (the host stores the wind terms without a negative zero), so it is not
+// evaluated either.
+template <bool FRIC, bool COR = true>
 __device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, float qy, float H, Node& d)
 {
     const float h = H + eta;
@@ -101,11 +104,15 @@ __device__ __forceinline__ void derive(const BasinDev& B, float eta, float qx, f
     if (FRIC) {
         const float s = __builtin_amdgcn_sqrtf(__builtin_fmaf(u, u, v * v));
         const float fr = B.cfr * s;
-        fpx = __builtin_fmaf(B.omh, qy, __builtin_fmaf(-fr, u, B.tpx));
-        fpy = __builtin_fmaf(-B.omh, qx, __builtin_fmaf(-fr, v, B.tpy));
+        fpx = __builtin_fmaf(-fr, u, B.tpx);
+        fpy = __builtin_fmaf(-fr, v, B.tpy);
     } else {
-        fpx = __builtin_fmaf(B.omh, qy, B.tpx);
-        fpy = __builtin_fmaf(-B.omh, qx, B.tpy);
+        fpx = B.tpx;
+        fpy = B.tpy;
+    }
+    if (COR) {
+        fpx = __builtin_fmaf(B.omh, qy, fpx);
+        fpy = __builtin_fmaf(-B.omh, qx, fpy);
     }
     // Out_a = quadratic part + linear part, each product fused into the sum
     // that uses it (every kernel variant evaluates this one expression)
@@ -502,7 +509,7 @@ __device__ __forceinline__ void carry_init(const Node& dS, const Row& C, Carry& 
 // plain local, so the whole window lives in registers.
 #define MLB_ROW(V, r, RAWN, S, C, N, DC, DN, LOADNEXT, EMIT, EMIT0)                                 \
     do {                                                                                          \
-        derive<FRIC>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                        \
+        derive<FRIC, COR>(B, RAWN.eta, RAWN.qx, RAWN.qy, RAWN.H, DN);                                   \
         take_coef<IMPL, COMP>(RAWN, DN);                                                          \
         exchange<EDGE>(DN, N);                                                                    \
         if (COMP) N.el = DN.el;                                                                   \
@@ -657,6 +664,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
     const int ny = B.ny, ld = B.ld, per_y = B.per_y, extrap = B.extrap;
     constexpr bool OPEN = EDGE;   // one-step edge tiles keep the general boundary logic
     constexpr bool XO = false;
+    constexpr bool COR = true;
     const Lane L = lane_setup<EDGE, OPEN>(B, T, T.x0 + lane - 1, lane >= 1 && lane <= kStripOut, T.x0, T.x0 + kStripOut - 1);
     const int wr = rd ^ 1;
     // fields are device (global) memory: typed so, loads and stores are
@@ -755,7 +763,8 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
 // DIAG: the second stage also reduces its stored level n+2 against level n+1
 // (the queue rows) into the tile's FP64 partials, as the one-step checked pass
 // does against its old state.
-template <bool EDGE, bool FRIC, bool MASK, bool OPEN, bool IMPL, bool XO = false, bool DIAG = false>
+template <bool EDGE, bool FRIC, bool MASK, bool OPEN, bool IMPL, bool XO = false, bool DIAG = false,
+          bool COR = true>
 __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, int rd, int64_t step,
                                           double* __restrict__ part = nullptr)
 {
@@ -790,14 +799,14 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     Row A0, A1, A2;
     {
         const Raw w = MLB_LD(r0 - 2);
-        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a0);
+        derive<FRIC, COR>(B, w.eta, w.qx, w.qy, w.H, a0);
         take_coef<IMPL, false>(w, a0);
         exchange<EDGE>(a0, A0);
         if (MASK) { mask_row(w.m, A0); a0.mk = w.m; }
     }
     {
         const Raw w = MLB_LD(r0 - 1);
-        derive<FRIC>(B, w.eta, w.qx, w.qy, w.H, a1);
+        derive<FRIC, COR>(B, w.eta, w.qx, w.qy, w.H, a1);
         take_coef<IMPL, false>(w, a1);
         exchange<EDGE>(a1, A1);
         if (MASK) { mask_row(w.m, A1); a1.mk = w.m; }
@@ -820,7 +829,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0-1
     ++ra;
     // B's window row r0-1
-    derive<FRIC>(B, q0.eta, q0.qx, q0.qy, q0.H, b0);
+    derive<FRIC, COR>(B, q0.eta, q0.qx, q0.qy, q0.H, b0);
     take_coef<IMPL, false>(q0, b0);
     exchange<EDGE>(b0, B0);
     if (MASK) { mask_row(q0.m, B0); b0.mk = q0.m; }
@@ -831,7 +840,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
     MLB_ROW(SA, ra, wa, A0, A1, A2, a1, a2, wa = MLB_LD(ra + 4), MLB_Q0, MLB_A0);   // row r0+2
     ++ra;
     // B's window row r0 (final now) and its links towards row r0-1
-    derive<FRIC>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
+    derive<FRIC, COR>(B, q1.eta, q1.qx, q1.qy, q1.H, b1);
     take_coef<IMPL, false>(q1, b1);
     exchange<EDGE>(b1, B1);
     if (MASK) { mask_row(q1.m, B1); b1.mk = q1.m; }
@@ -964,11 +973,13 @@ __device__ __forceinline__ void pass_tile(const BasinDev* __restrict__ basins, c
             if (masked) run_tile2<true, true, MASKED, OPEN, IMPL, false, DIAG>(B, T, rd, step, part);
             else if (xo) run_tile2<false, true, false, true, IMPL, true, DIAG>(B, T, rd, step, part);
             else if (edge) run_tile2<true, true, false, OPEN, IMPL, false, DIAG>(B, T, rd, step, part);
+            else if (B.omh == 0.0f) run_tile2<false, true, false, false, IMPL, false, DIAG, false>(B, T, rd, step, part);
             else run_tile2<false, true, false, false, IMPL, false, DIAG>(B, T, rd, step, part);
         } else {
             if (masked) run_tile2<true, false, MASKED, OPEN, IMPL, false, DIAG>(B, T, rd, step, part);
             else if (xo) run_tile2<false, false, false, true, IMPL, true, DIAG>(B, T, rd, step, part);
             else if (edge) run_tile2<true, false, false, OPEN, IMPL, false, DIAG>(B, T, rd, step, part);
+            else if (B.omh == 0.0f) run_tile2<false, false, false, false, IMPL, false, DIAG, false>(B, T, rd, step, part);
             else run_tile2<false, false, false, false, IMPL, false, DIAG>(B, T, rd, step, part);
         }
     }
