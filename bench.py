@@ -31,16 +31,12 @@ FLOP_PER_LUP = {True: 104, False: 97}
 FLOP_IMPLICIT = 5              # implicit link depth: scale the increment, correct qx and qy (two FMAs)
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_02999_amd", "csrc", "mlb_kernels.hip")
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "step_kernel_bump4096_traffic.json"),
-                 2: [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json")] +
-                    [os.path.join(ROOT, "profiles", "step2_kernel_bump4096_rows%d_traffic.json" % r)
-                     for r in (14, 17, 20, 23, 26)],
+                 2: os.path.join(ROOT, "profiles", "step2_kernel_bump4096_traffic.json"),
                  "implicit": os.path.join(ROOT, "profiles", "step_kernel_implicit_bump4096_traffic.json"),
                  "implicit2": os.path.join(ROOT, "profiles", "step2_kernel_implicit_bump4096_traffic.json"),
                  "dish4096": os.path.join(ROOT, "profiles", "step_kernel_masked_dish4096_traffic.json"),
-                 "dish4096_2": [os.path.join(ROOT, "profiles", "step2_kernel_masked_dish4096_rows%d_traffic.json" % r)
-                                for r in (17, 26)],
-                 "ensemble": [os.path.join(ROOT, "profiles", "step2_kernel_closed_ensemble512_rows%d_traffic.json" % r)
-                              for r in (14, 17, 20, 26)],
+                 "dish4096_2": os.path.join(ROOT, "profiles", "step2_kernel_masked_dish4096_traffic.json"),
+                 "ensemble": os.path.join(ROOT, "profiles", "step2_kernel_closed_ensemble512_traffic.json"),
                  "elab": os.path.join(ROOT, "profiles", "elab_step_kernel_lake4096_traffic.json")}
 
 
