@@ -399,7 +399,7 @@ mlb_status mlb_copy_probe(mlb_ctx* ctx, size_t bytes, int32_t reps, double* gbps
  * layer by layer in forward order, each 3x3 weight [Cout][3][3][Cin] then its
  * bias; the head weight [3][base_ch] then its bias.
  * Requirements: in_ch and base_ch multiples of 32; width / 2^(L-1) a
- * multiple of 32; height a multiple of 2^(L-1). */
+ * multiple of 32; height a multiple of 2^(L-1); base_ch 2^(L-1) <= 2048. */
 typedef struct mlb_net mlb_net;
 typedef struct {
     int32_t height, width;   /* field size                                            */

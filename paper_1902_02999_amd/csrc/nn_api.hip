@@ -55,7 +55,6 @@ struct mlb_net {
     float* g_bot = nullptr;
     float* g_y = nullptr;
     __bf16* dz = nullptr;
-    float* dzf = nullptr;
     float* wpart = nullptr;
     float* cpart = nullptr;
     double* lpart = nullptr;
@@ -93,17 +92,21 @@ void net_free(mlb_net* n)
     n->allocs.clear();
 }
 
-// Pixel chunks of the bias-gradient sums (partials of kBiasChunks x channels)
-// and of the head's weight gradient (kHeadChunks x out x in, in the split-K
-// buffer; its bias partials use the bias buffer).
+// Blocks of the ReLU-mask kernel, each writing one partial sum of the bias
+// gradient per channel (at most kBiasChunks x channels), and pixel chunks of
+// the head's weight gradient (kHeadChunks x out x in, in the split-K buffer;
+// its bias partials use the bias buffer).
 constexpr int kBiasChunks = 1024;
 constexpr int kHeadChunks = 2048;
 
+// Pixel splits of a layer's weight gradient: about 512 workgroups (one per
+// 32 x 32 channel pair and split), each wave at least 8 row segments of 32
+// pixels (a workgroup has four waves).
 int nsplit_for(const Layer& ly, int64_t npix)
 {
-    const int per = (ly.cout / 32) * 9 * (ly.cin / 32);
-    int64_t s = 4096 / std::max(1, per);
-    s = std::max<int64_t>(1, std::min<int64_t>(s, npix / 32));
+    const int64_t pairs = (int64_t)(ly.cout / 32) * (ly.cin / 32);
+    int64_t s = std::max<int64_t>(1, 512 / std::max<int64_t>(1, pairs));
+    s = std::min(s, std::max<int64_t>(1, npix / 32 / (4 * 8)));
     return (int)s;
 }
 
@@ -185,7 +188,6 @@ mlb_status build(mlb_net* n)
     CHK(dalloc(n, &n->yout, px(0) * c.out_ch));
     CHK(dalloc(n, &n->g_y, px(0) * c.out_ch));
     CHK(dalloc(n, &n->dz, maxpc));
-    CHK(dalloc(n, &n->dzf, maxpc));
     // split-K partials: the largest nsplit * cout * 9 * cin over layers and levels
     size_t wl = 0;
     for (int i = 0; i < (int)n->L.size() - 1; ++i) {
@@ -241,8 +243,7 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     hipStream_t s = n->ctx->stream;
     const int h = n->hh(lev), w = n->ww(lev);
     const int64_t P = (int64_t)nb * h * w;
-    HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->dzf, s));
-    HIPCHK(nn::chan_sum(n->dzf, P, ly.cout, ly.cout, n->cpart, kBiasChunks, n->grad + ly.boff, s));
+    HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->cpart, kBiasChunks, n->grad + ly.boff, s));
     nn::WgradArgs g{};
     g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff;
     g.n = nb; g.h = h; g.w = w; g.cin = ly.cin; g.cout = ly.cout;
@@ -362,6 +363,7 @@ mlb_status mlb_net_create(mlb_ctx* ctx, const mlb_net_cfg* cfg, uint64_t seed, m
         return fail(MLB_E_INVAL, "net config: levels >= 2, base_ch and in_ch multiples of 32, out_ch 3");
     const int f = 1 << (c.levels - 1);
     if (c.width % (32 * f) || c.height % f || c.height < f) return fail(MLB_E_INVAL, "net config: field size");
+    if ((int64_t)c.base_ch * f > 2048) return fail(MLB_E_INVAL, "net config: at most 2048 channels at the deepest level");
     HIPCHK(hipSetDevice(ctx->device));
     mlb_net* n = new (std::nothrow) mlb_net();
     if (!n) return fail(MLB_E_NOMEM, "net");

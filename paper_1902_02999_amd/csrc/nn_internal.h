@@ -37,8 +37,10 @@ struct WgradArgs {
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s);
 hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s);
 hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, int nchunk, float* dst, hipStream_t s);
+// dz = dy masked by y > 0 (BF16, contiguous) and db = the channel sums of dz
+// (FP32, fixed order; part holds max_blocks x c partials).
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
-                     __bf16* dz, float* dzf, hipStream_t s);
+                     __bf16* dz, float* part, int max_blocks, float* db, hipStream_t s);
 hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream_t s);
 hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c, __bf16* y, hipStream_t s);
 hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, int ldx, int xoff, int accumulate,

@@ -47,23 +47,33 @@ __device__ __forceinline__ bf16x8 zero8()
 // implicit GEMM on MFMA.  A workgroup of eight waves computes kConvRows image
 // rows (one per wave) of PT = 16 MB pixels x NT = 16 NB output channels (MB,
 // NB in {2, 4}: each A fragment serves NB products and each B fragment MB).
-// Per block of 32 input channels the workgroup loads the rows' input with
+// Per block of 32 input channels the workgroup stages the rows' input with
 // its one-pixel halo, (kConvRows + 2) x (PT + 2) x 32 values (zero outside
-// the image), and the NT x 9 x 32 weights once into LDS; the nine taps then
-// read their shifted A fragments and their B fragments from there instead of
-// from global memory.  Every
-// output sums over channel blocks, then taps, in that order.  OUT_F32: FP32
+// the image), and the NT x 9 x 32 weights in LDS; the nine taps then read
+// their shifted A fragments and their B fragments from there instead of from
+// global memory.  Each thread fetches its share of a block (a fixed number of
+// 16-byte chunks) with all loads in flight at once, into registers, and
+// writes them to LDS; with PF the fetch of block k + 1 is issued right after
+// block k is in LDS, so it runs under block k's MFMAs (one LDS buffer: the
+// registers carry the next block across the barrier).  Every output sums
+// over channel blocks, then taps, in that order, whatever PF.  OUT_F32: FP32
 // output (optionally accumulated into), else BF16.
 constexpr int kConvRows = 8;               // one wave per row: kConvRows x 64 threads
 constexpr int kConvThreads = kConvRows * 64;
-template <bool OUT_F32, int MB, int NB>
+// LDS elements per staged pixel: 32 channels + 8 of padding.  With 80-byte
+// pixels the 16-byte A-fragment reads of neighbouring pixels start in
+// distinct banks (64-byte pixels put every fourth pixel on the same banks).
+constexpr int kConvPix = 40;
+template <bool OUT_F32, int MB, int NB, bool PF>
 __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 {
     constexpr int PT = 16 * MB, NT = 16 * NB, TW = PT + 2;
     constexpr int CHUNKS = (kConvRows + 2) * TW * 4;   // 16-byte chunks of 8 channels
     constexpr int WS = 9 * 32 + 8;                    // per output channel: 9 taps x 32 inputs, padded
     constexpr int WCHUNKS = NT * 9 * 4;
-    __shared__ __attribute__((aligned(16))) __bf16 tile[(kConvRows + 2) * TW * 32];
+    constexpr int XPT = (CHUNKS + kConvThreads - 1) / kConvThreads;    // input chunks per thread
+    constexpr int WPT = (WCHUNKS + kConvThreads - 1) / kConvThreads;   // weight chunks per thread
+    __shared__ __attribute__((aligned(16))) __bf16 tile[(kConvRows + 2) * TW * kConvPix];
     __shared__ __attribute__((aligned(16))) __bf16 wtile[NT * WS];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int ntile = a.cout / NT, xtiles = a.w / PT, ygroups = (a.h + kConvRows - 1) / kConvRows;
@@ -82,21 +92,53 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    bf16x8 xr[XPT], wr[WPT];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int j = 0; j < XPT; ++j) {
+            const int i = threadIdx.x + j * kConvThreads;
+            xr[j] = zero8();
+            if (i < CHUNKS) {
+                const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
+                const int yy = y0 + rr - 1, xx = x0 + px - 1;
+                if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
+                    xr[j] = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const int i = threadIdx.x + j * kConvThreads;
+            if (i < WCHUNKS) {
+                const int ch8 = i & 3, t = (i >> 2) % 9, n = (i >> 2) / 9;
+                wr[j] = load8(a.wt + ((size_t)(n0 + n) * 9 + t) * a.cin + c0 + ch8 * 8);
+            }
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int j = 0; j < XPT; ++j) {
+            const int i = threadIdx.x + j * kConvThreads;
+            if (i < CHUNKS) {
+                const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
+                *(bf16x8*)&tile[(rr * TW + px) * kConvPix + ch8 * 8] = xr[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < WPT; ++j) {
+            const int i = threadIdx.x + j * kConvThreads;
+            if (i < WCHUNKS) {
+                const int ch8 = i & 3, t = (i >> 2) % 9, n = (i >> 2) / 9;
+                *(bf16x8*)&wtile[n * WS + t * 32 + ch8 * 8] = wr[j];
+            }
+        }
+    };
+
+    if (PF) fetch(0);
     for (int c0 = 0; c0 < a.cin; c0 += 32) {
-        for (int i = threadIdx.x; i < CHUNKS; i += kConvThreads) {
-            const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
-            const int yy = y0 + rr - 1, xx = x0 + px - 1;
-            bf16x8 v = zero8();
-            if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-                v = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
-            *(bf16x8*)&tile[(rr * TW + px) * 32 + ch8 * 8] = v;
-        }
-        for (int i = threadIdx.x; i < WCHUNKS; i += kConvThreads) {
-            const int ch8 = i & 3, t = (i >> 2) % 9, n = (i >> 2) / 9;
-            *(bf16x8*)&wtile[n * WS + t * 32 + ch8 * 8] =
-                load8(a.wt + ((size_t)(n0 + n) * 9 + t) * a.cin + c0 + ch8 * 8);
-        }
+        if (!PF) fetch(c0);
+        stash();
         __syncthreads();
+        if (PF && c0 + 32 < a.cin) fetch(c0 + 32);
         if (active) {
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
@@ -104,7 +146,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
                 bf16x8 A[MB], Bm[NB];
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
-                    A[mb] = *(const bf16x8*)&tile[((wv + 1 + dy) * TW + mb * 16 + l16 + 1 + dx) * 32 + lq * 8];
+                    A[mb] = *(const bf16x8*)&tile[((wv + 1 + dy) * TW + mb * 16 + l16 + 1 + dx) * kConvPix + lq * 8];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     Bm[nb] = *(const bf16x8*)&wtile[(nb * 16 + l16) * WS + t * 32 + lq * 8];
@@ -140,87 +182,169 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 }
 
 // ------------------------------------------------------------------ weight gradient
-// Partial dW over a pixel range: part[s][n][t][c] = sum_{p in chunk s} dz[p][n] X[p + off_t][c].
-// One wave: 32 output channels x (one tap row dy, its three taps dx = -1, 0, 1,
-// 32 input channels), K = pixels.  The dz fragment serves all three taps, and
-// each lane loads its ten input pixels (8 + the two neighbours) once for the
-// three shifted B fragments.
-__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
-{
-    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int ntile = a.cout / 32, ctile = a.cin / 32;
-    const int per_split = ntile * 3 * ctile;
-    if (wave >= per_split * a.nsplit) return;
-    const int s = wave / per_split;
-    int r = wave % per_split;
-    const int ct = r % ctile; r /= ctile;
-    const int ty = r % 3;                   // taps 3 ty .. 3 ty + 2
-    const int nt = r / 3;
-    const int dy = ty - 1;
-    const int64_t nch = (int64_t)a.n * a.h * a.w / 32;                     // 32-pixel chunks
-    const int64_t pbeg = nch * s / a.nsplit * 32, pend = nch * (s + 1) / a.nsplit * 32;
-    const int n0 = nt * 32, c0 = ct * 32;
+// Partial dW over a pixel range: part[s][n][t][c] = sum_{p in split s} dz[p][n] X[p + off_t][c]
+// (GEMM M = output channels, N = input channels, K = pixels, one per tap).
+// A workgroup of four waves takes 32 output x 32 input channels and all nine
+// taps of split s.  The split's pixels are row segments of kWgSeg pixels
+// (widths are multiples of 32, so a segment lies in one image row); wave w
+// takes segments w, w + 4, ... of the split.  Per segment a wave stages in
+// its own LDS area, transposed so that pixels are contiguous (the MFMA K
+// order): dz for its 32 pixels, and X for the rows y - 1, y, y + 1 and the
+// pixels x0 - 1 .. x0 + 32 (zero outside the image).  Both come in as
+// 16-byte chunks of 8 channels of one pixel, two pixels per lane, and go out
+// as 32-bit pixel pairs per channel; each group of 8 channel rows is shifted
+// by 8 banks, so that the lanes of a store (four channel groups, eight pixel
+// pairs per 32 lanes) hit distinct banks while the fragment reads stay
+// 16-byte aligned.  The A fragment (dz) serves all nine
+// taps; per tap row one aligned 16-byte read plus the next 4 bytes give the
+// B fragments of its three taps (shifted by whole BF16 elements).  The next
+// segment's chunks are fetched into registers while the current one is
+// multiplied.  At the end the four waves' sums are added in wave order in
+// LDS, so the partials depend only on the split count.
+constexpr int kWgSeg = 32;              // pixels per row segment
+constexpr int kWgWaves = 4;
+constexpr int kWgPitch = 40;            // LDS elements per transposed row: 34 pixels + padding (80-byte rows)
+constexpr int kWgRows = 32 * kWgPitch + 4 * 16;   // 32 channel rows, four groups shifted by 16 elements
+constexpr int kWgRed = 9 * 32 + 4;      // row of the final reduction (output channel): 9 taps x 32, padded
+constexpr int kWgXTasks = 3 * 17 * 4;   // (tap row, pixel pair, channel group) of a segment's X
+constexpr int kWgXPer = (kWgXTasks + 63) / 64;
+struct WgStage {
+    __bf16 x[3 * kWgRows];              // [tap row][input channel][pixel x0 - 1 + i]
+    __bf16 dz[kWgRows];                 // [output channel][pixel x0 + i]
+};
+// offset of channel row c in a staged array
+__device__ __forceinline__ int wg_row(int c) { return c * kWgPitch + (c >> 3) * 16; }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-    f32x4 acc[3][2][2];
+__device__ __forceinline__ unsigned pack2(__bf16 lo, __bf16 hi)
+{
+    return (unsigned)__builtin_bit_cast(unsigned short, lo) | ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
+}
+
+__global__ __launch_bounds__(kWgWaves * 64) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_wgrad_kernel(WgradArgs a)
+{
+    static_assert(sizeof(WgStage) * kWgWaves >= 32 * kWgRed * sizeof(float), "reduction area");
+    __shared__ __attribute__((aligned(16))) WgStage stage[kWgWaves];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    const int ntile = a.cout / 32, ctile = a.cin / 32;
+    int b = blockIdx.x;
+    const int ct = b % ctile; b /= ctile;
+    const int nt = b % ntile;
+    const int s = b / ntile;
+    const int n0 = nt * 32, c0 = ct * 32;
+    const int64_t nseg = (int64_t)a.n * a.h * a.w / kWgSeg;
+    const int64_t sbeg = nseg * s / a.nsplit, send = nseg * (s + 1) / a.nsplit;
+    WgStage& L = stage[wv];
+
+    f32x4 acc[9][2][2];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < 2; ++j) acc[t][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
-        bf16x8 A[2];
-        // A (rows n, K = pixels): dz[p][n] for 8 consecutive pixels
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int n = n0 + mb * 16 + l16;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) A[mb][e] = a.dz[(p0 + lq * 8 + e) * a.cout + n];
-        }
-        // B (K = pixels, cols c): X at the tap-shifted pixel (zero outside the
-        // image).  The width is a multiple of 32, so the chunk lies in one row.
+    // one segment's chunks in registers: dz (this lane's pixel pair and
+    // channel group) and X (up to kWgXPer pixel pairs of one channel group)
+    bf16x8 du, dv, xu[kWgXPer], xv[kWgXPer];
+    const int dpp = (lane >> 2) * 2, dcg = lane & 3;
+    auto fetch = [&](int64_t g) {
+        const int64_t p0 = g * kWgSeg;
         const int64_t ry = p0 / a.w;
-        const int xb = (int)(p0 - ry * a.w) + lq * 8 - 1;   // pixel of xv[.][0]
-        const int yy = (int)(ry % a.h) + dy;
-        const bool rowok = yy >= 0 && yy < a.h;
-        const int64_t q0 = p0 + lq * 8 - 1 + (int64_t)dy * a.w;
-        __bf16 xv[2][10];
+        const int x0 = (int)(p0 - ry * a.w), y = (int)(ry % a.h);
+        du = load8(a.dz + (p0 + dpp) * a.cout + n0 + dcg * 8);
+        dv = load8(a.dz + (p0 + dpp + 1) * a.cout + n0 + dcg * 8);
 #pragma unroll
-        for (int e = 0; e < 10; ++e) {
-            const int xx = xb + e;
-            const bool ok = rowok && xx >= 0 && xx < a.w;
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-                xv[nb][e] = ok ? a.x[(q0 + e) * a.ldx + a.xoff + c0 + nb * 16 + l16] : (__bf16)0.0f;
+        for (int k = 0; k < kWgXPer; ++k) {
+            const int task = lane + 64 * k;
+            xu[k] = zero8();
+            xv[k] = zero8();
+            if (task < kWgXTasks) {
+                const int cg = task & 3, pr = (task >> 2) % 17, r = (task >> 2) / 17;
+                const int yy = y + r - 1, xa = x0 - 1 + 2 * pr;   // pixels xa, xa + 1 (xa <= w - 1)
+                if (yy >= 0 && yy < a.h) {
+                    const int64_t q = p0 + (int64_t)(r - 1) * a.w + (xa - x0);
+                    const __bf16* src = a.x + q * a.ldx + a.xoff + c0 + cg * 8;
+                    if (xa >= 0) xu[k] = load8(src);
+                    if (xa + 1 < a.w) xv[k] = load8(src + a.ldx);
+                }
+            }
         }
+    };
+    auto stash = [&]() {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {       // dx = d - 1
-            bf16x8 Bm[2];
+        for (int e = 0; e < 8; ++e) *(unsigned*)&L.dz[wg_row(dcg * 8 + e) + dpp] = pack2(du[e], dv[e]);
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
+        for (int k = 0; k < kWgXPer; ++k) {
+            const int task = lane + 64 * k;
+            if (task < kWgXTasks) {
+                const int cg = task & 3, pr = (task >> 2) % 17, r = (task >> 2) / 17;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) Bm[nb][e] = xv[nb][e + d];
+                for (int e = 0; e < 8; ++e)
+                    *(unsigned*)&L.x[r * kWgRows + wg_row(cg * 8 + e) + 2 * pr] = pack2(xu[k][e], xv[k][e]);
+            }
+        }
+    };
+
+    int64_t g = sbeg + wv;
+    if (g < send) fetch(g);
+    for (; g < send; g += kWgWaves) {
+        // a wave's LDS operations complete in order: the staging stores are
+        // seen by the fragment reads below, and this segment's reads precede
+        // the next segment's stores
+        stash();
+        if (g + kWgWaves < send) fetch(g + kWgWaves);
+        bf16x8 A[2];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb) A[mb] = *(const bf16x8*)&L.dz[wg_row(mb * 16 + l16) + lq * 8];
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) acc[d][mb][nb] = mfma(A[mb], Bm[nb], acc[d][mb][nb]);
+        for (int r = 0; r < 3; ++r) {
+            bf16x8 Bm[3][2];   // [dx + 1][nb]
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const __bf16* row = &L.x[r * kWgRows + wg_row(nb * 16 + l16) + lq * 8];
+                const u32x4 w0 = *(const u32x4*)row;          // pixels x0 - 1 + 8 lq .. + 7: tap dx = -1
+                const unsigned w1 = *(const unsigned*)(row + 8);
+                const u32x4 m0 = {__builtin_amdgcn_alignbit(w0[1], w0[0], 16), __builtin_amdgcn_alignbit(w0[2], w0[1], 16),
+                                  __builtin_amdgcn_alignbit(w0[3], w0[2], 16), __builtin_amdgcn_alignbit(w1, w0[3], 16)};
+                const u32x4 p1 = {w0[1], w0[2], w0[3], w1};
+                Bm[0][nb] = __builtin_bit_cast(bf16x8, w0);
+                Bm[1][nb] = __builtin_bit_cast(bf16x8, m0);
+                Bm[2][nb] = __builtin_bit_cast(bf16x8, p1);
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb)
+                        acc[3 * r + d][mb][nb] = mfma(A[mb], Bm[d][nb], acc[3 * r + d][mb][nb]);
         }
     }
+    // the four waves' sums, added in wave order: red[n][t][c] (rows of kWgRed)
+    float* red = (float*)stage;
+    for (int w = 0; w < kWgWaves; ++w) {
+        __syncthreads();
+        if (wv == w) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float& o = red[(mb * 16 + lq * 4 + i) * kWgRed + t * 32 + nb * 16 + l16];
+                            o = w == 0 ? acc[t][mb][nb][i] : o + acc[t][mb][nb][i];
+                        }
+        }
+    }
+    __syncthreads();
     float* out = a.part + (size_t)s * a.cout * 9 * a.cin;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int n = n0 + mb * 16 + lq * 4 + i;
-                    const int c = c0 + nb * 16 + l16;
-                    out[((size_t)n * 9 + 3 * ty + d) * a.cin + c] = acc[d][mb][nb][i];
-                }
+    for (int i = threadIdx.x; i < 32 * 9 * 32; i += kWgWaves * 64) {
+        const int c = i & 31, t = (i >> 5) % 9, n = i / (32 * 9);
+        out[((size_t)(n0 + n) * 9 + t) * a.cin + c0 + c] = red[n * kWgRed + t * 32 + c];
+    }
 }
 
 // Column sums in a fixed order: out[y][j] = sum over rows i of chunk y
@@ -241,8 +365,18 @@ __global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ 
     const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min<int64_t>(r0 + chunk, nrows);
     const bool act = rl < lanes && j < ncols;
     float s = 0.0f;
-    if (act)
-        for (int64_t i = r0 + rl; i < r1; i += lanes) s += a[i * ld + j];
+    if (act) {
+        // eight rows' loads in flight at once, added in row order
+        int64_t i = r0 + rl;
+        for (; i + 7 * lanes < r1; i += 8 * lanes) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = a[(i + u * lanes) * ld + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; i < r1; i += lanes) s += a[i * ld + j];
+    }
     red[t] = s;
     __syncthreads();
     if (act && rl == 0) {
@@ -252,36 +386,55 @@ __global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ 
 }
 
 // ------------------------------------------------------------------ elementwise
-// dz (BF16 and FP32, contiguous [p][c]) = dy (FP32, stride ldd at doff) where
-// the activation y (BF16, stride ldy at yoff) > 0.
-// One thread per 8 channels of a pixel (channel counts, strides and offsets
-// are multiples of 8: 16-byte BF16 and 32-byte FP32 accesses).
-__global__ void relu_mask_kernel(const float* __restrict__ dy, int ldd, int doff, const __bf16* __restrict__ y,
-                                 int ldy, int yoff, int64_t npix, int c, __bf16* __restrict__ dz,
-                                 float* __restrict__ dzf)
+// dz (BF16, contiguous [p][c]) = dy (FP32, stride ldd at doff) where the
+// activation y (BF16, stride ldy at yoff) > 0, and the FP32 channel sums of
+// dz over the pixels this block visits (partials of the bias gradient):
+// part[blockIdx.x][c].  Thread t takes channel group t % G (8 channels;
+// G = c / 8 <= 256) of pixel slot t / G; the block walks pixel groups
+// blockIdx.x, blockIdx.x + gridDim.x, ... of `slots` = 256 / G pixels.  Each
+// thread sums its pixels in that order, then the slots' sums are added in
+// slot order, so the partials depend only on the grid size.  Channel counts,
+// strides and offsets are multiples of 8 (16-byte BF16 and 32-byte FP32
+// accesses).
+constexpr int kReluThreads = 256;
+__global__ __launch_bounds__(kReluThreads) void relu_mask_kernel(const float* __restrict__ dy, int ldd, int doff,
+                                                                 const __bf16* __restrict__ y, int ldy, int yoff,
+                                                                 int64_t npix, int c, __bf16* __restrict__ dz,
+                                                                 float* __restrict__ part)
 {
-    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c8 = c / 8;
-    if (i8 >= npix * c8) return;
-    const int64_t p = i8 / c8;
-    const int ch = (int)(i8 - p * c8) * 8;
-    const bf16x8 yv = load8(y + p * ldy + yoff + ch);
-    const f32x4* d = (const f32x4*)(dy + p * ldd + doff + ch);
-    const f32x4 d0 = d[0], d1 = d[1];
-    f32x4 o0, o1;
-    bf16x8 ob;
+    __shared__ float red[kReluThreads * 8];
+    const int G = c / 8, slots = kReluThreads / G;
+    const int t = threadIdx.x, sl = t / G, ch = (t - sl * G) * 8;
+    float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (sl < slots) {
+        const int64_t stride = (int64_t)gridDim.x * slots;
+        for (int64_t p = (int64_t)blockIdx.x * slots + sl; p < npix; p += stride) {
+            const bf16x8 yv = load8(y + p * ldy + yoff + ch);
+            const f32x4* d = (const f32x4*)(dy + p * ldd + doff + ch);
+            const f32x4 d0 = d[0], d1 = d[1];
+            bf16x8 ob;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        o0[e] = (float)yv[e] > 0.0f ? d0[e] : 0.0f;
-        o1[e] = (float)yv[e + 4] > 0.0f ? d1[e] : 0.0f;
-        ob[e] = (__bf16)o0[e];
-        ob[e + 4] = (__bf16)o1[e];
+            for (int e = 0; e < 4; ++e) {
+                const float o0 = (float)yv[e] > 0.0f ? d0[e] : 0.0f;
+                const float o1 = (float)yv[e + 4] > 0.0f ? d1[e] : 0.0f;
+                ob[e] = (__bf16)o0;
+                ob[e + 4] = (__bf16)o1;
+                sum[e] += o0;
+                sum[e + 4] += o1;
+            }
+            *(bf16x8*)(dz + p * c + ch) = ob;
+        }
     }
-    const int64_t o = i8 * 8;
-    *(bf16x8*)(dz + o) = ob;
-    f32x4* of = (f32x4*)(dzf + o);
-    of[0] = o0;
-    of[1] = o1;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[t * 8 + e] = sum[e];
+    __syncthreads();
+    if (t < G) {
+        for (int k = 1; k < slots; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sum[e] += red[(k * G + t) * 8 + e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) part[(int64_t)blockIdx.x * c + ch + e] = sum[e];
+    }
 }
 
 // Rotated, transposed weights for the data gradient: wr[c][t][n] = w[n][8 - t][c].
@@ -487,14 +640,19 @@ __global__ void f32_to_bf16_kernel(const float* __restrict__ src, int64_t n, __b
     if (i < n) dst[i] = (__bf16)src[i];
 }
 
-// Input features (FP32 [p][nin]) -> BF16 [p][ldc] with zero padding channels.
+// Input features (FP32 [p][nin]) -> BF16 [p][ldc] with zero padding channels;
+// one thread per 8 output channels of a pixel (ldc a multiple of 8).
 __global__ void pack_input_kernel(const float* __restrict__ x, int64_t npix, int nin, int ldc, __bf16* __restrict__ y)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npix * ldc) return;
-    const int64_t p = i / ldc;
-    const int c = (int)(i % ldc);
-    y[i] = (__bf16)(c < nin ? x[p * nin + c] : 0.0f);
+    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8 = ldc / 8;
+    if (i8 >= npix * c8) return;
+    const int64_t p = i8 / c8;
+    const int c0 = (int)(i8 - p * c8) * 8;
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)(c0 + e < nin ? x[p * nin + c0 + e] : 0.0f);
+    *(bf16x8*)(y + i8 * 8) = v;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -509,13 +667,22 @@ static void col_sum(const float* a, int64_t nrows, int64_t ncols, int64_t ld, in
                        0, s, a, nrows, ncols, ld, chunk, out);
 }
 
-template <int MB, int NB>
+template <int MB, int NB, bool PF>
 static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
 {
     const int64_t blocks = (int64_t)a.n * ((a.h + kConvRows - 1) / kConvRows) * (a.w / (16 * MB)) *
                            (a.cout / (16 * NB));
-    if (a.yf) hipLaunchKernelGGL((conv3x3_lds_kernel<true, MB, NB>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
-    else hipLaunchKernelGGL((conv3x3_lds_kernel<false, MB, NB>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
+    if (a.yf) hipLaunchKernelGGL((conv3x3_lds_kernel<true, MB, NB, PF>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
+    else hipLaunchKernelGGL((conv3x3_lds_kernel<false, MB, NB, PF>), dim3((unsigned)blocks), dim3(kConvThreads), 0, s, a);
+}
+
+template <int MB, int NB>
+static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
+{
+    // prefetching pays where there is a next block; it costs registers
+    // (fewer resident workgroups) where there is none
+    if (a.cin > 32) conv3x3_launch<MB, NB, true>(a, s);
+    else conv3x3_launch<MB, NB, false>(a, s);
 }
 
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
@@ -531,8 +698,9 @@ hipError_t conv3x3(const ConvArgs& a, hipStream_t s)
 
 hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
 {
-    const int64_t waves = (int64_t)(a.cout / 32) * 3 * (a.cin / 32) * a.nsplit;
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s, a);
+    if (a.w % kWgSeg || a.cout % 32 || a.cin % 32 || a.nsplit < 1) return hipErrorInvalidValue;
+    const int64_t blocks = (int64_t)(a.cout / 32) * (a.cin / 32) * a.nsplit;
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)blocks), dim3(kWgWaves * 64), 0, s, a);
     const int64_t len = (int64_t)a.cout * 9 * a.cin;
     col_sum(a.part, a.nsplit, len, len, 1, dw, s);
     return hipGetLastError();
@@ -548,11 +716,15 @@ hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, in
 }
 
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
-                     __bf16* dz, float* dzf, hipStream_t s)
+                     __bf16* dz, float* part, int max_blocks, float* db, hipStream_t s)
 {
-    if (c % 8 || ldd % 4 || doff % 4 || ldy % 8 || yoff % 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(npix * c / 8, 256)), dim3(256), 0, s, dy, ldd, doff, y, ldy,
-                       yoff, npix, c, dz, dzf);
+    if (c % 8 || c / 8 > kReluThreads || ldd % 4 || doff % 4 || ldy % 8 || yoff % 8 || npix < 1 || max_blocks < 1)
+        return hipErrorInvalidValue;
+    const int slots = kReluThreads / (c / 8);
+    const int nb = (int)std::min<int64_t>(max_blocks, (npix + slots - 1) / slots);
+    hipLaunchKernelGGL(relu_mask_kernel, dim3(nb), dim3(kReluThreads), 0, s, dy, ldd, doff, y, ldy, yoff, npix, c, dz,
+                       part);
+    col_sum(part, nb, c, c, 1, db, s);
     return hipGetLastError();
 }
 
@@ -635,7 +807,8 @@ hipError_t f32_to_bf16(const float* src, int64_t n, __bf16* dst, hipStream_t s)
 
 hipError_t pack_input(const float* x, int64_t npix, int nin, int ldc, __bf16* y, hipStream_t s)
 {
-    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(npix * ldc, 256)), dim3(256), 0, s, x, npix, nin, ldc, y);
+    if (ldc % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for(npix * ldc / 8, 256)), dim3(256), 0, s, x, npix, nin, ldc, y);
     return hipGetLastError();
 }
 

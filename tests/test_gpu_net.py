@@ -227,7 +227,7 @@ def test_bad_configs_rejected(ctx):
     from paper_1902_02999_amd import mlb
     for kw in (dict(height=64, width=64, base_ch=16), dict(height=64, width=96, levels=2),
                dict(height=63, width=64, levels=2), dict(height=64, width=64, in_ch=8),
-               dict(height=64, width=64, levels=1)):
+               dict(height=64, width=64, levels=1), dict(height=64, width=64, base_ch=2048, levels=2)):
         args = dict(height=64, width=64, base_ch=32, levels=2, in_ch=32)
         args.update(kw)
         with pytest.raises(mlb.MlbError):
