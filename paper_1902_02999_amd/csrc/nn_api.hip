@@ -99,14 +99,15 @@ void net_free(mlb_net* n)
 constexpr int kBiasChunks = 1024;
 constexpr int kHeadChunks = 2048;
 
-// Pixel splits of a layer's weight gradient: about 512 workgroups (one per
-// 32 x 32 channel pair and split), each wave at least 8 row segments of 32
-// pixels (a workgroup has four waves).
-int nsplit_for(const Layer& ly, int64_t npix)
+// Pixel splits of a layer's weight gradient: about 256 workgroups (one per
+// 32 x 32 channel pair and split), each of whose four groups walks at least
+// one unit (a 32-pixel column strip over 16 rows).
+int nsplit_for(const Layer& ly, int nb, int h, int w)
 {
     const int64_t pairs = (int64_t)(ly.cout / 32) * (ly.cin / 32);
-    int64_t s = std::max<int64_t>(1, 512 / std::max<int64_t>(1, pairs));
-    s = std::min(s, std::max<int64_t>(1, npix / 32 / (4 * 8)));
+    const int64_t units = (int64_t)nb * (w / 32) * ((h + 15) / 16);
+    int64_t s = std::max<int64_t>(1, 256 / std::max<int64_t>(1, pairs));
+    s = std::min(s, std::max<int64_t>(1, units / 4));
     return (int)s;
 }
 
@@ -193,8 +194,7 @@ mlb_status build(mlb_net* n)
     for (int i = 0; i < (int)n->L.size() - 1; ++i) {
         const Layer& ly = n->L[i];
         const int lev = i < 2 * Lv ? i / 2 : (Lv - 2 - (i - 2 * Lv) / 3);
-        const int64_t P = (int64_t)px(lev);
-        wl = std::max(wl, (size_t)nsplit_for(ly, P) * ly.cout * 9 * ly.cin);
+        wl = std::max(wl, (size_t)nsplit_for(ly, c.max_batch, n->hh(lev), n->ww(lev)) * ly.cout * 9 * ly.cin);
     }
     wl = std::max(wl, (size_t)kHeadChunks * c.out_ch * n->ch(0));
     n->wpart_len = wl;
@@ -247,7 +247,7 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     nn::WgradArgs g{};
     g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff;
     g.n = nb; g.h = h; g.w = w; g.cin = ly.cin; g.cout = ly.cout;
-    g.nsplit = nsplit_for(ly, P);
+    g.nsplit = nsplit_for(ly, nb, h, w);
     g.part = n->wpart;
     if ((size_t)g.nsplit * ly.cout * 9 * ly.cin > n->wpart_len) return fail(MLB_E_DEVICE, "split-K buffer too small");
     HIPCHK(nn::conv3x3_wgrad(g, n->grad + ly.woff, s));

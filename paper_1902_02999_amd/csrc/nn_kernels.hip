@@ -184,164 +184,189 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 // ------------------------------------------------------------------ weight gradient
 // Partial dW over a pixel range: part[s][n][t][c] = sum_{p in split s} dz[p][n] X[p + off_t][c]
 // (GEMM M = output channels, N = input channels, K = pixels, one per tap).
-// A workgroup of four waves takes 32 output x 32 input channels and all nine
-// taps of split s.  The split's pixels are row segments of kWgSeg pixels
-// (widths are multiples of 32, so a segment lies in one image row); wave w
-// takes segments w, w + 4, ... of the split.  Per segment a wave stages in
-// its own LDS area, transposed so that pixels are contiguous (the MFMA K
-// order): dz for its 32 pixels, and X for the rows y - 1, y, y + 1 and the
-// pixels x0 - 1 .. x0 + 32 (zero outside the image).  Both come in as
-// 16-byte chunks of 8 channels of one pixel, two pixels per lane, and go out
-// as 32-bit pixel pairs per channel; each group of 8 channel rows is shifted
-// by 8 banks, so that the lanes of a store (four channel groups, eight pixel
-// pairs per 32 lanes) hit distinct banks while the fragment reads stay
-// 16-byte aligned.  The A fragment (dz) serves all nine
-// taps; per tap row one aligned 16-byte read plus the next 4 bytes give the
-// B fragments of its three taps (shifted by whole BF16 elements).  The next
-// segment's chunks are fetched into registers while the current one is
-// multiplied.  At the end the four waves' sums are added in wave order in
-// LDS, so the partials depend only on the split count.
+// The pixels are cut into units: a column strip of kWgSeg = 32 pixels of one
+// image (widths are multiples of 32) over kWgUnitRows consecutive rows.  A
+// workgroup takes 32 output x 32 input channels and split s; it holds
+// kWgGroups groups of three waves, and group g walks units s G + g,
+// (s + nsplit) G + g, ... row by row.  Wave r of a group sums the three taps
+// of tap row dy = r - 1.  Per row y the group stages in LDS, transposed so
+// that pixels are contiguous (the MFMA K order), dz of the row segment and X
+// of row y + 1 (pixels x0 - 1 .. x0 + 32, zero outside the image); rows y - 1
+// and y are still there from the two rows before (a ring of three rows; a
+// unit's first row stages all three).  Chunks of 8 channels of one pixel come
+// in as 16-byte loads, a pixel pair per thread, and go out as 32-bit pixel
+// pairs per channel; each group of 8 channel rows is shifted by 8 banks, so
+// the stores of 32 lanes hit distinct banks while the fragment reads stay
+// 16-byte aligned.  The rows two steps ahead are fetched into registers while
+// a row is multiplied.  Per tap row one aligned 16-byte read and the next 4
+// bytes give the B fragments of its three taps (shifted by whole BF16
+// elements).  At the end the groups' sums are added in group order in LDS,
+// so the partials depend only on the split count.
 constexpr int kWgSeg = 32;              // pixels per row segment
-constexpr int kWgWaves = 4;
+constexpr int kWgUnitRows = 16;         // rows per unit
+constexpr int kWgGroups = 4;
+constexpr int kWgThreads = kWgGroups * 3 * 64;
 constexpr int kWgPitch = 40;            // LDS elements per transposed row: 34 pixels + padding (80-byte rows)
 constexpr int kWgRows = 32 * kWgPitch + 4 * 16;   // 32 channel rows, four groups shifted by 16 elements
 constexpr int kWgRed = 9 * 32 + 4;      // row of the final reduction (output channel): 9 taps x 32, padded
-constexpr int kWgXTasks = 3 * 17 * 4;   // (tap row, pixel pair, channel group) of a segment's X
-constexpr int kWgXPer = (kWgXTasks + 63) / 64;
 struct WgStage {
-    __bf16 x[3 * kWgRows];              // [tap row][input channel][pixel x0 - 1 + i]
+    __bf16 x[3 * kWgRows];              // ring of three X rows: [slot][input channel][pixel x0 - 1 + i]
     __bf16 dz[kWgRows];                 // [output channel][pixel x0 + i]
 };
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // offset of channel row c in a staged array
 __device__ __forceinline__ int wg_row(int c) { return c * kWgPitch + (c >> 3) * 16; }
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned pack2(__bf16 lo, __bf16 hi)
 {
     return (unsigned)__builtin_bit_cast(unsigned short, lo) | ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
 }
 
-__global__ __launch_bounds__(kWgWaves * 64) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_wgrad_kernel(WgradArgs a)
+// One thread's share of staging a row: task 0..63 a dz pixel pair and channel
+// group, 64..131 an X pixel pair and channel group of one input row.
+struct WgChunk {
+    bf16x8 u, v;
+};
+
+__global__ __launch_bounds__(kWgThreads) void conv3x3_wgrad_kernel(WgradArgs a)
 {
-    static_assert(sizeof(WgStage) * kWgWaves >= 32 * kWgRed * sizeof(float), "reduction area");
-    __shared__ __attribute__((aligned(16))) WgStage stage[kWgWaves];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    static_assert(sizeof(WgStage) * kWgGroups >= 32 * kWgRed * sizeof(float), "reduction area");
+    __shared__ __attribute__((aligned(16))) WgStage stage[kWgGroups];
+    const int grp = threadIdx.x / 192, gt = threadIdx.x % 192;   // group, thread within the group
+    const int r = gt >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int ntile = a.cout / 32, ctile = a.cin / 32;
     int b = blockIdx.x;
     const int ct = b % ctile; b /= ctile;
     const int nt = b % ntile;
     const int s = b / ntile;
     const int n0 = nt * 32, c0 = ct * 32;
-    const int64_t nseg = (int64_t)a.n * a.h * a.w / kWgSeg;
-    const int64_t sbeg = nseg * s / a.nsplit, send = nseg * (s + 1) / a.nsplit;
-    WgStage& L = stage[wv];
+    const int strips = a.w / kWgSeg, ychunks = (a.h + kWgUnitRows - 1) / kWgUnitRows;
+    const int units = a.n * strips * ychunks;
+    const int ustride = a.nsplit * kWgGroups;
+    const int niter = (units + ustride - 1) / ustride;   // units per group, the same for every group
+    WgStage& L = stage[grp];
 
-    f32x4 acc[9][2][2];
+    f32x4 acc[3][2][2];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[t][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < 2; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // one segment's chunks in registers: dz (this lane's pixel pair and
-    // channel group) and X (up to kWgXPer pixel pairs of one channel group)
-    bf16x8 du, dv, xu[kWgXPer], xv[kWgXPer];
-    const int dpp = (lane >> 2) * 2, dcg = lane & 3;
-    auto fetch = [&](int64_t g) {
-        const int64_t p0 = g * kWgSeg;
-        const int64_t ry = p0 / a.w;
-        const int x0 = (int)(p0 - ry * a.w), y = (int)(ry % a.h);
-        du = load8(a.dz + (p0 + dpp) * a.cout + n0 + dcg * 8);
-        dv = load8(a.dz + (p0 + dpp + 1) * a.cout + n0 + dcg * 8);
+    // task of this thread: dz (pair, channel group) or X (pair, channel group)
+    const bool tdz = gt < 64, tx = gt >= 64 && gt < 64 + 68;
+    const int tpair = tdz ? gt >> 2 : (gt - 64) >> 2, tcg = gt & 3;
+    // fetch: the chunks of row segment (img, x0, y): dz row y (if ydz) and X row yx
+    auto fetch = [&](WgChunk& k, int img, int x0, int y, int yx, bool ok) {
+        k.u = zero8();
+        k.v = zero8();
+        if (!ok) return;
+        if (tdz) {
+            const int64_t p = ((int64_t)img * a.h + y) * a.w + x0 + 2 * tpair;
+            k.u = load8(a.dz + p * a.cout + n0 + tcg * 8);
+            k.v = load8(a.dz + (p + 1) * a.cout + n0 + tcg * 8);
+        } else if (tx && yx >= 0 && yx < a.h) {
+            const int xa = x0 - 1 + 2 * tpair;                   // pixels xa, xa + 1 (xa <= w - 1)
+            const __bf16* src = a.x + (((int64_t)img * a.h + yx) * a.w + xa) * a.ldx + a.xoff + c0 + tcg * 8;
+            if (xa >= 0) k.u = load8(src);
+            if (xa + 1 < a.w) k.v = load8(src + a.ldx);
+        }
+    };
+    // stash: dz into its slot, X row into ring slot `slot`
+    auto stash = [&](const WgChunk& k, int slot) {
+        if (tdz) {
 #pragma unroll
-        for (int k = 0; k < kWgXPer; ++k) {
-            const int task = lane + 64 * k;
-            xu[k] = zero8();
-            xv[k] = zero8();
-            if (task < kWgXTasks) {
-                const int cg = task & 3, pr = (task >> 2) % 17, r = (task >> 2) / 17;
-                const int yy = y + r - 1, xa = x0 - 1 + 2 * pr;   // pixels xa, xa + 1 (xa <= w - 1)
-                if (yy >= 0 && yy < a.h) {
-                    const int64_t q = p0 + (int64_t)(r - 1) * a.w + (xa - x0);
-                    const __bf16* src = a.x + q * a.ldx + a.xoff + c0 + cg * 8;
-                    if (xa >= 0) xu[k] = load8(src);
-                    if (xa + 1 < a.w) xv[k] = load8(src + a.ldx);
+            for (int e = 0; e < 8; ++e) *(unsigned*)&L.dz[wg_row(tcg * 8 + e) + 2 * tpair] = pack2(k.u[e], k.v[e]);
+        } else if (tx) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *(unsigned*)&L.x[slot * kWgRows + wg_row(tcg * 8 + e) + 2 * tpair] = pack2(k.u[e], k.v[e]);
+        }
+    };
+
+    for (int it = 0; it < niter; ++it) {
+        const int u = (it * a.nsplit + s) * kWgGroups + grp;
+        const bool uok = u < units;
+        int uu = uok ? u : 0;
+        const int yc = uu % ychunks; uu /= ychunks;
+        const int xs = uu % strips;
+        const int img = uu / strips;
+        const int x0 = xs * kWgSeg, y0 = yc * kWgUnitRows;
+        const int y1 = min(a.h, y0 + kWgUnitRows);
+        // the unit's first rows: X rows y0 - 1 and y0 into their ring slots
+        {
+            WgChunk k0, k1;
+            fetch(k0, img, x0, y0, y0 - 1, uok);
+            fetch(k1, img, x0, y0, y0, uok);
+            __syncthreads();                // the previous unit's last reads are done
+            if (!tdz) {
+                stash(k0, (y0 + 2) % 3);
+                stash(k1, y0 % 3);
+            }
+        }
+        // rows y0 .. y0 + kWgUnitRows - 1 (rows past y1 do nothing but keep
+        // the barriers of all groups in step); two rows fetched ahead
+        WgChunk pf[2];
+        fetch(pf[0], img, x0, y0, y0 + 1, uok && y0 < y1);
+        fetch(pf[1], img, x0, y0 + 1, y0 + 2, uok && y0 + 1 < y1);
+#pragma unroll 2
+        for (int j = 0; j < kWgUnitRows; ++j) {
+            const int y = y0 + j;
+            const bool rok = uok && y < y1;
+            __syncthreads();                // the reads of the row before are done
+            stash(pf[j & 1], (y + 1) % 3);
+            __syncthreads();
+            fetch(pf[j & 1], img, x0, y + 2, y + 3, uok && y + 2 < y1);
+            if (rok) {
+                bf16x8 A[2];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) A[mb] = *(const bf16x8*)&L.dz[wg_row(mb * 16 + l16) + lq * 8];
+                const int slot = (y + r + 2) % 3;            // X row y + r - 1
+                bf16x8 Bm[3][2];                             // [dx + 1][nb]
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    const __bf16* row = &L.x[slot * kWgRows + wg_row(nb * 16 + l16) + lq * 8];
+                    const u32x4 w0 = *(const u32x4*)row;      // pixels x0 - 1 + 8 lq .. + 7: tap dx = -1
+                    const unsigned w1 = *(const unsigned*)(row + 8);
+                    const u32x4 m0 = {__builtin_amdgcn_alignbit(w0[1], w0[0], 16), __builtin_amdgcn_alignbit(w0[2], w0[1], 16),
+                                      __builtin_amdgcn_alignbit(w0[3], w0[2], 16), __builtin_amdgcn_alignbit(w1, w0[3], 16)};
+                    const u32x4 p1 = {w0[1], w0[2], w0[3], w1};
+                    Bm[0][nb] = __builtin_bit_cast(bf16x8, w0);
+                    Bm[1][nb] = __builtin_bit_cast(bf16x8, m0);
+                    Bm[2][nb] = __builtin_bit_cast(bf16x8, p1);
                 }
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < 2; ++nb) acc[d][mb][nb] = mfma(A[mb], Bm[d][nb], acc[d][mb][nb]);
             }
         }
-    };
-    auto stash = [&]() {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) *(unsigned*)&L.dz[wg_row(dcg * 8 + e) + dpp] = pack2(du[e], dv[e]);
-#pragma unroll
-        for (int k = 0; k < kWgXPer; ++k) {
-            const int task = lane + 64 * k;
-            if (task < kWgXTasks) {
-                const int cg = task & 3, pr = (task >> 2) % 17, r = (task >> 2) / 17;
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    *(unsigned*)&L.x[r * kWgRows + wg_row(cg * 8 + e) + 2 * pr] = pack2(xu[k][e], xv[k][e]);
-            }
-        }
-    };
-
-    int64_t g = sbeg + wv;
-    if (g < send) fetch(g);
-    for (; g < send; g += kWgWaves) {
-        // a wave's LDS operations complete in order: the staging stores are
-        // seen by the fragment reads below, and this segment's reads precede
-        // the next segment's stores
-        stash();
-        if (g + kWgWaves < send) fetch(g + kWgWaves);
-        bf16x8 A[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) A[mb] = *(const bf16x8*)&L.dz[wg_row(mb * 16 + l16) + lq * 8];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            bf16x8 Bm[3][2];   // [dx + 1][nb]
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const __bf16* row = &L.x[r * kWgRows + wg_row(nb * 16 + l16) + lq * 8];
-                const u32x4 w0 = *(const u32x4*)row;          // pixels x0 - 1 + 8 lq .. + 7: tap dx = -1
-                const unsigned w1 = *(const unsigned*)(row + 8);
-                const u32x4 m0 = {__builtin_amdgcn_alignbit(w0[1], w0[0], 16), __builtin_amdgcn_alignbit(w0[2], w0[1], 16),
-                                  __builtin_amdgcn_alignbit(w0[3], w0[2], 16), __builtin_amdgcn_alignbit(w1, w0[3], 16)};
-                const u32x4 p1 = {w0[1], w0[2], w0[3], w1};
-                Bm[0][nb] = __builtin_bit_cast(bf16x8, w0);
-                Bm[1][nb] = __builtin_bit_cast(bf16x8, m0);
-                Bm[2][nb] = __builtin_bit_cast(bf16x8, p1);
-            }
+    }
+    // the groups' sums, added in group order: red[n][t][c] (rows of kWgRed)
+    float* red = (float*)stage;
+    for (int g = 0; g < kWgGroups; ++g) {
+        __syncthreads();
+        if (grp == g) {
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                     for (int nb = 0; nb < 2; ++nb)
-                        acc[3 * r + d][mb][nb] = mfma(A[mb], Bm[d][nb], acc[3 * r + d][mb][nb]);
-        }
-    }
-    // the four waves' sums, added in wave order: red[n][t][c] (rows of kWgRed)
-    float* red = (float*)stage;
-    for (int w = 0; w < kWgWaves; ++w) {
-        __syncthreads();
-        if (wv == w) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t)
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            float& o = red[(mb * 16 + lq * 4 + i) * kWgRed + t * 32 + nb * 16 + l16];
-                            o = w == 0 ? acc[t][mb][nb][i] : o + acc[t][mb][nb][i];
+                            float& o = red[(mb * 16 + lq * 4 + i) * kWgRed + (3 * r + d) * 32 + nb * 16 + l16];
+                            o = g == 0 ? acc[d][mb][nb][i] : o + acc[d][mb][nb][i];
                         }
         }
     }
     __syncthreads();
     float* out = a.part + (size_t)s * a.cout * 9 * a.cin;
-    for (int i = threadIdx.x; i < 32 * 9 * 32; i += kWgWaves * 64) {
+    for (int i = threadIdx.x; i < 32 * 9 * 32; i += kWgThreads) {
         const int c = i & 31, t = (i >> 5) % 9, n = i / (32 * 9);
         out[((size_t)(n0 + n) * 9 + t) * a.cin + c0 + c] = red[n * kWgRed + t * 32 + c];
     }
@@ -700,7 +725,7 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
 {
     if (a.w % kWgSeg || a.cout % 32 || a.cin % 32 || a.nsplit < 1) return hipErrorInvalidValue;
     const int64_t blocks = (int64_t)(a.cout / 32) * (a.cin / 32) * a.nsplit;
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)blocks), dim3(kWgWaves * 64), 0, s, a);
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)blocks), dim3(kWgThreads), 0, s, a);
     const int64_t len = (int64_t)a.cout * 9 * a.cin;
     col_sum(a.part, a.nsplit, len, len, 1, dw, s);
     return hipGetLastError();
