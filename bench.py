@@ -56,6 +56,12 @@ def roofline_of(bytes_per_launch: float, flop_per_launch: float, launch_s: float
     return r, round(tfl, 2)
 
 
+def traffic_rate(traffic, launch_s: float):
+    """HBM rate [GB/s] of the measured bytes per launch (None without a
+    counter summary for this kernel and size)."""
+    return None if traffic is None else round(traffic / launch_s / 1e9, 1)
+
+
 def measured_traffic(nodes: int, key, tile_rows=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summaries, or None when none was taken on this kernel
@@ -274,7 +280,8 @@ def main():
                    "autotuned": tuned is not None, "graph": not args.no_graph, "fp32_TFLOPs": tfl,
                    # per-step bytes of the one-step formulation x update rate
                    "effective_GBps": round(mlups * 1e6 * bpl / 1e9, 1),
-                   "launch_GBps": round(gbs, 1), "launch_us": round(launch_s * 1e6, 3),
+                   "launch_GBps": round(gbs, 1), "traffic_GBps": traffic_rate(traffic, launch_s),
+                   "launch_us": round(launch_s * 1e6, 3),
                    "bulk_passes": None if bulk is None else bulk[1], "call_event_ms": round(ev_ms, 4),
                    "copy_probe_GBps": round(copy_gbps, 1)},
         "roofline": roofline,
@@ -359,6 +366,7 @@ def bench_ensemble(args, ctx, copy_gbps):
         "config": {"workload": "ensemble_512_basins_64-512_seed1902", "basins": len(specs), "nodes": nodes,
                    "exec": opts, "autotuned": tuned is not None, "nonfinite": bad, "copy_probe_GBps": round(copy_gbps, 1),
                    "effective_GBps": round(mlups * 1e6 * BYTES_PER_LUP / 1e9, 1), "launch_GBps": round(gbs, 1),
+                   "traffic_GBps": traffic_rate(traffic, launch_s),
                    "launch_us": round(launch_s * 1e6, 3), "fp32_TFLOPs": tfl},
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu else cpu_baseline_ensemble(specs, args.cpu_seconds)}), flush=True)
@@ -448,8 +456,8 @@ def bench_geometry(args, ctx, copy_gbps):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": spec.name, "nodes": spec.nodes, "water_nodes": water, "dx_m": spec.dx,
                       "nu": spec.nu, "exec": opts, "autotuned": tuned is not None, "nonfinite": d["nonfinite"],
-                      "launch_us": round(launch_s * 1e6, 3), "copy_probe_GBps": round(copy_gbps, 1), "fp32_TFLOPs": tfl,
-                      "steady_1e-6": steady},
+                      "launch_us": round(launch_s * 1e6, 3), "traffic_GBps": traffic_rate(traffic, launch_s),
+                      "copy_probe_GBps": round(copy_gbps, 1), "fp32_TFLOPs": tfl, "steady_1e-6": steady},
            "roofline": roofline}
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(spec, args.cpu_seconds)
     if out["cpu_baseline"] is not None and water != spec.nodes:

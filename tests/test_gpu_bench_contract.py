@@ -38,7 +38,7 @@ def test_default_report_fields():
     assert set(rf) == {"bound", "achieved", "peak", "unit", "frac", "traffic"}
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert rf["achieved"] > 0 and rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
-    assert rf["traffic"] is None   # no counter summary at this size
+    assert rf["traffic"] is None and d["config"]["traffic_GBps"] is None   # no counter summary at this size
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["unit"] == "MLUPS" and cb["value"] > 0 and cb["cores"] >= 1
     assert "512x512" in cb["sample"]

@@ -192,7 +192,10 @@ def test_stall_rule_stops_at_the_noise_floor(ctx, trained):
     """A tolerance under FP32's noise floor (but within the stall band of it)
     stalls instead of running to max_steps; the warm run reports the stall
     without falling back.  The floor is measured first: the lowest residual
-    of 50 checks once the flow has settled."""
+    of 50 checks once the flow has settled.  The tolerance is a quarter of
+    it: runs from other starts settle into other FP32 cycles whose floors
+    differ by up to about 2x (the warm run's lowest residual has been 1.7x
+    the cold run's), and the stall band reaches 10x the tolerance."""
     from paper_1902_02999_amd import mlb
     net = trained[0]
     spec = wl.learned_set(1, 3005, n=N)[0]
@@ -204,7 +207,7 @@ def test_stall_rule_stops_at_the_noise_floor(ctx, trained):
         ok, d = g.run_steady(0.0, 100, 100)
         res.append(d["residual"])
     g.close()
-    tol = min(res) / 8.0
+    tol = min(res) / 4.0
     say("floor", min(res), max(res), "tol", tol)
     ctx.set_stall_checks(20)
     try:
