@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kBlock) void reduce_state_kernel(const BasinDev* __
 }
 
 // Per-basin sum of the tile partials in a fixed order: thread i of the block
-// sums tiles i, i + kFinBlock, ... of the basin, then a fixed butterfly across
-// each wave and the waves' results in order.
+// sums tiles i, i + kFinBlock, ... of the basin in that order, then a fixed
+// butterfly across each wave and the waves' results in order.
 constexpr int kFinBlock = 1024;
 __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const BasinDev* __restrict__ basins,
                                                              const double* __restrict__ partials,
@@ -65,7 +65,23 @@ __global__ __launch_bounds__(kFinBlock) void finalize_kernel(const BasinDev* __r
     // one-step tile list, those of a two-step pass by the two-step list
     const int first = kind == 2 ? B.first_tile2 : B.first_tile, nt = kind == 2 ? B.ntiles2 : B.ntiles;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = tid; i < nt; i += kFinBlock) {
+    // four tiles' loads in flight at once, added in tile order
+    int i = tid;
+    for (; i + 3 * kFinBlock < nt; i += 4 * kFinBlock) {
+        double v[4][5];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double* p = partials + (size_t)(first + i + u * kFinBlock) * kPartials;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) v[u][k] = p[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s[0] += v[u][0]; s[1] += v[u][1]; s[2] += v[u][2]; s[3] += v[u][3];
+            s[4] = v[u][4] > s[4] ? v[u][4] : s[4];
+        }
+    }
+    for (; i < nt; i += kFinBlock) {
         const double* p = partials + (size_t)(first + i) * kPartials;
         s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] += p[3];
         s[4] = p[4] > s[4] ? p[4] : s[4];

@@ -383,6 +383,9 @@ __device__ __forceinline__ void take_coef(const Raw& w, Node& d)
 // FP32 (a count per lane stays far below 2^24; the speed is a diagnostic).
 struct Sums { double eta, dq, q; float bad, vmax; };
 
+// COMP false: no low part of the surface (el is zero); the sum starts at +0
+// and is never -0, so adding +0 would change no bit and is left out.
+template <bool COMP = true>
 __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn, float Hn, float oqx,
                                         float oqy, float el)
 {
@@ -394,7 +397,7 @@ __device__ __forceinline__ void account(Sums& s, float en, float qxn, float qyn,
     if (ok) {
         const double a = qxn, b = qyn, da = a - (double)oqx, db = b - (double)oqy;
         s.eta += en;
-        s.eta += el;
+        if (COMP) s.eta += el;
         s.dq += da * da + db * db;
         s.q += a * a + b * b;
         const float sp = __builtin_amdgcn_sqrtf(qxn * qxn + qyn * qyn) * __builtin_amdgcn_rcpf(hf);
@@ -718,7 +721,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
             const uint32_t o = ((uint32_t)(r * ld) + (uint32_t)L.x) * 4u;                         \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
             if (COMP) stf(EL1, o, el_);                                                           \
-            if (DIAG) account(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y, COMP ? el_ : 0.0f);      \
+            if (DIAG) account<COMP>(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y, COMP ? el_ : 0.0f);      \
         }                                                                                         \
     } while (0)
 #define MLB_STORE0(ge_, gx_, gy_, gl_)                                                            \
@@ -727,7 +730,7 @@ __device__ __forceinline__ void run_tile(const BasinDev& B, const TileDev T, int
             const uint32_t o = (uint32_t)L.x * 4u;                                                \
             stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
             if (COMP) stf(EL1, o, gl_);                                                           \
-            if (DIAG) account(sums, ge_, gx_, gy_, V.pH, V.poqx, V.poqy, COMP ? gl_ : 0.0f);      \
+            if (DIAG) account<COMP>(sums, ge_, gx_, gy_, V.pH, V.poqx, V.poqy, COMP ? gl_ : 0.0f);      \
         }                                                                                         \
     } while (0)
     // single-exit counted loop: the tile's rows are rounded up to a multiple
@@ -852,7 +855,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         if (L.own_col && rb >= T.yo && rb < r1 && !(MASK && D_.mk == NODE_SOLID)) {               \
             const uint32_t o = ((uint32_t)(rb * ld) + (uint32_t)L.x) * 4u;                        \
             stf(E1, o, en_); stf(QX1, o, qx_); stf(QY1, o, qy_);                                  \
-            if (DIAG) account(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y, 0.0f);                   \
+            if (DIAG) account<false>(sums, en_, qx_, qy_, D_.H, D_.q0x, D_.q0y, 0.0f);                   \
         }                                                                                         \
     } while (0)
 #define MLB_STORE20(ge_, gx_, gy_, gl_)                                                           \
@@ -860,7 +863,7 @@ __device__ __forceinline__ void run_tile2(const BasinDev& B, const TileDev T, in
         if (L.own_col) {                                                                          \
             const uint32_t o = (uint32_t)L.x * 4u;                                                \
             stf(E1, o, ge_); stf(QX1, o, gx_); stf(QY1, o, gy_);                                  \
-            if (DIAG) account(sums, ge_, gx_, gy_, SB.pH, SB.poqx, SB.poqy, 0.0f);                \
+            if (DIAG) account<false>(sums, ge_, gx_, gy_, SB.pH, SB.poqx, SB.poqy, 0.0f);                \
         }                                                                                         \
     } while (0)
     // B row rb consumes A's row rb+1; then A computes row rb+3.  Tiles pad
