@@ -332,12 +332,14 @@ mlb_status mlb_get_exec_opts(const mlb_grid* g, mlb_exec_opts* o);
 mlb_status mlb_set_exec_opts(mlb_grid* g, const mlb_exec_opts* o);
 
 /* Autotuner: times the step for every (tblock, tile_rows, blocks_per_cu)
- * triple of a fixed candidate set (tblock 1 with tile rows 6..45 in steps of
- * 3k, tblock 2 with tile rows 8..44 of the form 3k + 2; caps 0, 2..5), each
- * with graph launches, work-queue launches, and cooperative launches where
- * every tile fits on the device at once, with HIP
- * events (median of 3 runs of `steps` steps), applies the
- * fastest and returns it in *best (may be NULL).  The grid's state and step
+ * triple of a fixed candidate set (tblock 1 with tile rows 4..45, tblock 2
+ * with tile rows 5..44 of the form 3k + 2; caps 0, 2..5), each with graph
+ * launches, work-queue launches, and cooperative launches where every tile
+ * fits on the device at once, with HIP events (median of 3 runs of `steps`
+ * steps; a persistent mode whose first two candidates take more than twice
+ * the best graph launch is not timed further), then times the four fastest
+ * again (median of 5 runs of at least 200 steps), applies the fastest of
+ * those and returns it in *best (may be NULL).  The grid's state and step
  * counter are restored afterwards (results are bitwise independent of these
  * options).  cache_path (may be NULL): a text file of
  * "key tile_rows blocks_per_cu tblock persistent us" lines; a matching key is applied
