@@ -704,9 +704,11 @@ static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
 template <int MB, int NB>
 static void conv3x3_launch(const ConvArgs& a, hipStream_t s)
 {
-    // prefetching pays where there is a next block; it costs registers
-    // (fewer resident workgroups) where there is none
-    if (a.cin > 32) conv3x3_launch<MB, NB, true>(a, s);
+    // prefetching pays where a workgroup runs several blocks; its registers
+    // leave one workgroup per CU, so with one or two blocks two workgroups
+    // per CU without it overlap better (measured 3 % faster forward passes
+    // with the threshold at 64 input channels than at 32)
+    if (a.cin > 64) conv3x3_launch<MB, NB, true>(a, s);
     else conv3x3_launch<MB, NB, false>(a, s);
 }
 
