@@ -48,7 +48,7 @@ struct mlb_net {
     int64_t step = 0;
     // activations (BF16) and gradients (FP32), index = level
     __bf16* xin = nullptr;
-    std::vector<__bf16*> encin, enca, cat, upin, deca, decb;
+    std::vector<__bf16*> encin, enca, cat, deca, decb;
     __bf16* bot = nullptr;
     float* yout = nullptr;
     std::vector<float*> g_encin, g_enca, g_cat, g_upin, g_deca, g_decb;
@@ -163,7 +163,7 @@ mlb_status build(mlb_net* n)
     auto px = [&](int l) { return B * n->hh(l) * n->ww(l); };
     CHK(dalloc(n, &n->xin, px(0) * c.in_ch));
     n->encin.assign(Lv, nullptr); n->enca.assign(Lv, nullptr); n->cat.assign(Lv, nullptr);
-    n->upin.assign(Lv, nullptr); n->deca.assign(Lv, nullptr); n->decb.assign(Lv, nullptr);
+    n->deca.assign(Lv, nullptr); n->decb.assign(Lv, nullptr);
     n->g_encin.assign(Lv, nullptr); n->g_enca.assign(Lv, nullptr); n->g_cat.assign(Lv, nullptr);
     n->g_upin.assign(Lv, nullptr); n->g_deca.assign(Lv, nullptr); n->g_decb.assign(Lv, nullptr);
     size_t maxpc = 0;
@@ -175,7 +175,6 @@ mlb_status build(mlb_net* n)
         if (l < Lv - 1) {
             CHK(dalloc(n, &n->cat[l], p * 2 * n->ch(l)));
             CHK(dalloc(n, &n->g_cat[l], p * 2 * n->ch(l)));
-            CHK(dalloc(n, &n->upin[l], p * n->ch(l + 1)));
             CHK(dalloc(n, &n->g_upin[l], p * n->ch(l + 1)));
             CHK(dalloc(n, &n->deca[l], p * n->ch(l)));
             CHK(dalloc(n, &n->g_deca[l], p * n->ch(l)));
@@ -220,11 +219,11 @@ mlb_status refresh_bf16(mlb_net* n)
 }
 
 mlb_status conv_fwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, __bf16* y, int ldy, int yoff, int lev,
-                    int nb)
+                    int nb, int up = 0)
 {
     const Layer& ly = n->L[li];
     nn::ConvArgs a{};
-    a.x = x; a.ldx = ldx; a.xoff = xoff;
+    a.x = x; a.ldx = ldx; a.xoff = xoff; a.up = up;
     a.wt = n->wb + ly.wb; a.bias = n->theta + ly.boff;
     a.yb = y; a.yf = nullptr; a.ldy = ldy; a.yoff = yoff;
     a.n = nb; a.h = n->hh(lev); a.w = n->ww(lev); a.cin = ly.cin; a.cout = ly.cout;
@@ -237,7 +236,7 @@ mlb_status conv_fwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, __bf
 // gradient of its activated output y; writes dW, db into the gradient vector
 // and, when dx is given, the FP32 gradient of its input (contiguous, cin channels).
 mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, const __bf16* y, int ldy, int yoff,
-                    const float* dy, int ldd, int doff, float* dx, int lev, int nb)
+                    const float* dy, int ldd, int doff, float* dx, int lev, int nb, int up = 0)
 {
     const Layer& ly = n->L[li];
     hipStream_t s = n->ctx->stream;
@@ -245,7 +244,7 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     const int64_t P = (int64_t)nb * h * w;
     HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->cpart, kBiasChunks, n->grad + ly.boff, s));
     nn::WgradArgs g{};
-    g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff;
+    g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff; g.up = up;
     g.n = nb; g.h = h; g.w = w; g.cin = ly.cin; g.cout = ly.cout;
     g.nsplit = nsplit_for(ly, nb, h, w);
     g.part = n->wpart;
@@ -285,10 +284,10 @@ mlb_status forward(mlb_net* n, const float* x, int nb)
         else CHK(conv_fwd(n, n->enc(l, 1), n->enca[l], n->ch(l), 0, n->bot, n->ch(l), 0, l, nb));
     }
     for (int l = Lv - 2; l >= 0; --l) {
+        // the upsampling conv reads level l + 1 nearest-upsampled (up = 1)
         const __bf16* src = l == Lv - 2 ? n->bot : n->decb[l + 1];
         const int cu = n->ch(l + 1);
-        HIPCHK(nn::up2(src, nb, n->hh(l + 1), n->ww(l + 1), cu, n->upin[l], s));
-        CHK(conv_fwd(n, n->dec(l, 0), n->upin[l], cu, 0, n->cat[l], 2 * n->ch(l), 0, l, nb));
+        CHK(conv_fwd(n, n->dec(l, 0), src, cu, 0, n->cat[l], 2 * n->ch(l), 0, l, nb, 1));
         CHK(conv_fwd(n, n->dec(l, 1), n->cat[l], 2 * n->ch(l), 0, n->deca[l], n->ch(l), 0, l, nb));
         CHK(conv_fwd(n, n->dec(l, 2), n->deca[l], n->ch(l), 0, n->decb[l], n->ch(l), 0, l, nb));
     }
@@ -310,7 +309,9 @@ mlb_status backward(mlb_net* n, int nb)
         const int cl = n->ch(l), cu = n->ch(l + 1);
         CHK(conv_bwd(n, n->dec(l, 2), n->deca[l], cl, 0, n->decb[l], cl, 0, n->g_decb[l], cl, 0, n->g_deca[l], l, nb));
         CHK(conv_bwd(n, n->dec(l, 1), n->cat[l], 2 * cl, 0, n->deca[l], cl, 0, n->g_deca[l], cl, 0, n->g_cat[l], l, nb));
-        CHK(conv_bwd(n, n->dec(l, 0), n->upin[l], cu, 0, n->cat[l], 2 * cl, 0, n->g_cat[l], 2 * cl, 0, n->g_upin[l], l, nb));
+        const __bf16* src = l == Lv - 2 ? n->bot : n->decb[l + 1];
+        CHK(conv_bwd(n, n->dec(l, 0), src, cu, 0, n->cat[l], 2 * cl, 0, n->g_cat[l], 2 * cl, 0, n->g_upin[l], l, nb,
+                     1));
         float* dst = l + 1 <= Lv - 2 ? n->g_decb[l + 1] : n->g_bot;
         HIPCHK(nn::up2_back(n->g_upin[l], nb, n->hh(l + 1), n->ww(l + 1), cu, dst, s));
     }

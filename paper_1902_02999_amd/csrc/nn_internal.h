@@ -14,6 +14,7 @@ constexpr int kNetFeatures = 8;   // input features per pixel (MLB_NET_FEATURES)
 struct ConvArgs {
     const __bf16* x;     // [n][h][w][ldx], channels xoff .. xoff + cin
     int ldx, xoff;
+    int up;              // x is [n][h/2][w/2][ldx], read nearest-upsampled: pixel (y, x) is x's (y/2, x/2)
     const __bf16* wt;    // [cout][9][cin]
     const float* bias;   // [cout] or null
     __bf16* yb;          // BF16 output [n][h][w][ldy] at yoff (when yf is null)
@@ -29,6 +30,7 @@ struct WgradArgs {
     const __bf16* dz;    // [n][h][w][cout] contiguous
     const __bf16* x;     // [n][h][w][ldx] at xoff
     int ldx, xoff;
+    int up;              // x is [n][h/2][w/2][ldx], read nearest-upsampled (as ConvArgs::up)
     int n, h, w, cin, cout;
     int nsplit;
     float* part;         // [nsplit][cout][9][cin]
@@ -45,7 +47,6 @@ hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream
 hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c, __bf16* y, hipStream_t s);
 hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, int ldx, int xoff, int accumulate,
                       hipStream_t s);
-hipError_t up2(const __bf16* x, int n, int h, int w, int c, __bf16* y, hipStream_t s);
 hipError_t up2_back(const float* dy, int n, int h, int w, int c, float* dx, hipStream_t s);
 hipError_t head(const __bf16* x, int64_t npix, int cin, const float* w, const float* b, int cout, float* y,
                 hipStream_t s);

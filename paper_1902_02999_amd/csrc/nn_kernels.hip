@@ -101,8 +101,11 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
             if (i < CHUNKS) {
                 const int ch8 = i & 3, px = (i >> 2) % TW, rr = (i >> 2) / TW;
                 const int yy = y0 + rr - 1, xx = x0 + px - 1;
-                if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-                    xr[j] = load8(a.x + (((size_t)img * a.h + yy) * a.w + xx) * a.ldx + a.xoff + c0 + ch8 * 8);
+                if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w) {
+                    const size_t src = a.up ? ((size_t)img * (a.h >> 1) + (yy >> 1)) * (a.w >> 1) + (xx >> 1)
+                                            : ((size_t)img * a.h + yy) * a.w + xx;
+                    xr[j] = load8(a.x + src * a.ldx + a.xoff + c0 + ch8 * 8);
+                }
             }
         }
 #pragma unroll
@@ -269,9 +272,13 @@ __global__ __launch_bounds__(kWgThreads) void conv3x3_wgrad_kernel(WgradArgs a)
             k.v = load8(a.dz + (p + 1) * a.cout + n0 + tcg * 8);
         } else if (tx && yx >= 0 && yx < a.h) {
             const int xa = x0 - 1 + 2 * tpair;                   // pixels xa, xa + 1 (xa <= w - 1)
-            const __bf16* src = a.x + (((int64_t)img * a.h + yx) * a.w + xa) * a.ldx + a.xoff + c0 + tcg * 8;
-            if (xa >= 0) k.u = load8(src);
-            if (xa + 1 < a.w) k.v = load8(src + a.ldx);
+            auto pix = [&](int xx) {
+                return a.up ? ((int64_t)img * (a.h >> 1) + (yx >> 1)) * (a.w >> 1) + (xx >> 1)
+                            : ((int64_t)img * a.h + yx) * a.w + xx;
+            };
+            const __bf16* src = a.x + a.xoff + c0 + tcg * 8;
+            if (xa >= 0) k.u = load8(src + pix(xa) * a.ldx);
+            if (xa + 1 < a.w) k.v = load8(src + pix(xa + 1) * a.ldx);
         }
     };
     // stash: dz into its slot, X row into ring slot `slot`
@@ -518,20 +525,6 @@ __global__ void pool2_back_kernel(const float* __restrict__ dy, int n, int h, in
         for (int e = 0; e < 4; ++e) v[e] = old[e] + v[e];
     }
     *o = v;
-}
-
-// nearest x2: y[fine] = x[coarse]
-__global__ void up2_kernel(const __bf16* __restrict__ x, int n, int h, int w, int c, __bf16* __restrict__ y)
-{
-    const int64_t i8 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 8 channels per thread
-    const int hf = 2 * h, wf = 2 * w, c8 = c / 8;
-    if (i8 >= (int64_t)n * hf * wf * c8) return;
-    int64_t r = i8 / c8;
-    const int ch = (int)(i8 - r * c8) * 8;
-    const int xx = (int)(r % wf); r /= wf;
-    const int yy = (int)(r % hf);
-    const int img = (int)(r / hf);
-    *(bf16x8*)(y + i8 * 8) = load8(x + (((int64_t)img * h + yy / 2) * w + xx / 2) * c + ch);
 }
 
 // dx[coarse] = sum of the 4 fine gradients
@@ -790,13 +783,6 @@ hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, in
     if (c % 4 || ldx % 4 || xoff % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(pool2_back_kernel, dim3(blocks_for((int64_t)n * h * w * c / 4, 256)), dim3(256), 0, s,
                        dy, n, h, w, c, dx, ldx, xoff, accumulate);
-    return hipGetLastError();
-}
-
-hipError_t up2(const __bf16* x, int n, int h, int w, int c, __bf16* y, hipStream_t s)
-{
-    if (c % 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(up2_kernel, dim3(blocks_for((int64_t)n * 4 * h * w * c / 8, 256)), dim3(256), 0, s, x, n, h, w, c, y);
     return hipGetLastError();
 }
 
