@@ -549,21 +549,33 @@ __global__ void up2_back_kernel(const float* __restrict__ dy, int n, int h, int 
 }
 
 // ------------------------------------------------------------------ head (1x1), loss
-// y[p][o] = b[o] + sum_c x[p][c] w[o][c]   (FP32 weights, FP32 output)
+// y[p][o] = b[o] + sum_c x[p][c] w[o][c]   (FP32 weights, FP32 output), the
+// products added in channel order.  A pixel's channels are loaded once, in
+// groups of up to kHeadVec 16-byte chunks with their loads in flight
+// together, and serve every output.
+constexpr int kHeadVec = 8;    // 64 channels per group
+constexpr int kHeadOut = 3;    // outputs of the head (the net's out_ch)
 __global__ void head_kernel(const __bf16* __restrict__ x, int64_t npix, int cin, const float* __restrict__ w,
                             const float* __restrict__ b, int cout, float* __restrict__ y)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
-    for (int o = 0; o < cout; ++o) {
-        float s = b[o];
-        for (int c8 = 0; c8 < cin; c8 += 8) {   // cin: a multiple of 8
-            const bf16x8 v = load8(x + p * cin + c8);
+    float s[kHeadOut];
+    for (int o = 0; o < cout; ++o) s[o] = b[o];
+    for (int c0 = 0; c0 < cin; c0 += 8 * kHeadVec) {   // cin: a multiple of 8
+        const int nv = min(kHeadVec, (cin - c0) / 8);
+        bf16x8 v[kHeadVec];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) s = __builtin_fmaf((float)v[e], w[o * cin + c8 + e], s);
-        }
-        y[p * cout + o] = s;
+        for (int k = 0; k < kHeadVec; ++k)
+            if (k < nv) v[k] = load8(x + p * cin + c0 + 8 * k);
+        for (int o = 0; o < cout; ++o)
+#pragma unroll
+            for (int k = 0; k < kHeadVec; ++k)
+                if (k < nv)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) s[o] = __builtin_fmaf((float)v[k][e], w[o * cin + c0 + 8 * k + e], s[o]);
     }
+    for (int o = 0; o < cout; ++o) y[p * cout + o] = s[o];
 }
 
 // dx[p][c] = sum_o dy[p][o] w[o][c]
@@ -795,6 +807,7 @@ hipError_t up2_back(const float* dy, int n, int h, int w, int c, float* dx, hipS
 
 hipError_t head(const __bf16* x, int64_t npix, int cin, const float* w, const float* b, int cout, float* y, hipStream_t s)
 {
+    if (cin % 8 || cout < 1 || cout > kHeadOut) return hipErrorInvalidValue;
     hipLaunchKernelGGL(head_kernel, dim3(blocks_for(npix, 256)), dim3(256), 0, s, x, npix, cin, w, b, cout, y);
     return hipGetLastError();
 }
