@@ -147,9 +147,7 @@ mlb_status build(mlb_net* n)
     CHK(dalloc(n, &n->v, o));
     CHK(dalloc(n, &n->wmap, o));
     CHK(dalloc(n, &n->wb, ob));
-    size_t maxw = 0;
-    for (const Layer& ly : n->L) maxw = std::max(maxw, (size_t)ly.cout * 9 * ly.cin);
-    CHK(dalloc(n, &n->wflip, maxw));
+    CHK(dalloc(n, &n->wflip, ob));   // every conv layer's flipped weights, at its own offset
     std::vector<int64_t> wmap(o, -1);
     for (const Layer& ly : n->L)
         if (ly.k == 3)
@@ -251,10 +249,9 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     if ((size_t)g.nsplit * ly.cout * 9 * ly.cin > n->wpart_len) return fail(MLB_E_DEVICE, "split-K buffer too small");
     HIPCHK(nn::conv3x3_wgrad(g, n->grad + ly.woff, s));
     if (dx) {
-        HIPCHK(nn::weight_flip(n->wb + ly.wb, ly.cout, ly.cin, n->wflip, s));
         nn::ConvArgs a{};
         a.x = n->dz; a.ldx = ly.cout; a.xoff = 0;
-        a.wt = n->wflip; a.bias = nullptr;
+        a.wt = n->wflip + ly.wb; a.bias = nullptr;
         a.yb = nullptr; a.yf = dx; a.ldy = ly.cin; a.yoff = 0;
         a.n = nb; a.h = h; a.w = w; a.cin = ly.cout; a.cout = ly.cin;
         a.relu = 0; a.accumulate = 0;
@@ -302,6 +299,22 @@ mlb_status backward(mlb_net* n, int nb)
     const int Lv = c.levels;
     hipStream_t s = n->ctx->stream;
     const int64_t P0 = (int64_t)nb * c.height * c.width;
+    // rotated, transposed weights of every conv layer for the data gradients,
+    // up to kFlipMaxLayers layers per launch
+    nn::FlipLayers fl{};
+    for (size_t i = 0; i < n->L.size(); ++i) {
+        const Layer& ly = n->L[i];
+        if (ly.k == 3) {
+            fl.off[fl.count] = ly.wb;
+            fl.cout[fl.count] = ly.cout;
+            fl.cin[fl.count] = ly.cin;
+            ++fl.count;
+        }
+        if (fl.count == nn::kFlipMaxLayers || (i + 1 == n->L.size() && fl.count > 0)) {
+            HIPCHK(nn::weight_flip_all(n->wb, fl, n->wflip, s));
+            fl.count = 0;
+        }
+    }
     const Layer& hd = n->L[n->head()];
     HIPCHK(nn::head_back(n->g_y, n->decb[0], P0, hd.cout, hd.cin, n->theta + hd.woff, n->g_decb[0], n->wpart, kHeadChunks,
                          n->grad + hd.woff, n->grad + hd.boff, n->cpart, s));
@@ -629,15 +642,16 @@ mlb_status mlb_net_train(mlb_net* n, const float* x, const float* t, const float
         for (int b0 = 0; b0 < ns; b0 += B, ++it) {
             const int nb = std::min(B, ns - b0);
             double cnt = 0.0;
-            for (int k = 0; k < nb; ++k) {
-                const int idx = order[b0 + k];
-                HIPCHK(hipMemcpyAsync(xb + k * sx, x + (size_t)idx * sx, sx * sizeof(float), hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(tb + k * st, t + (size_t)idx * st, st * sizeof(float), hipMemcpyDeviceToDevice, s));
-                if (mask) {
-                    HIPCHK(hipMemcpyAsync(mb + k * hw, mask + (size_t)idx * hw, hw * sizeof(float),
-                                          hipMemcpyDeviceToDevice, s));
-                    cnt += hsum[idx];
+            for (int k0 = 0; k0 < nb; k0 += nn::kGatherMax) {
+                nn::GatherIdx gi{};
+                gi.count = std::min(nb - k0, nn::kGatherMax);
+                for (int k = 0; k < gi.count; ++k) {
+                    gi.i[k] = order[b0 + k0 + k];
+                    if (mask) cnt += hsum[gi.i[k]];
                 }
+                HIPCHK(nn::gather_samples(x, sx, gi, xb + (size_t)k0 * sx, s));
+                HIPCHK(nn::gather_samples(t, st, gi, tb + (size_t)k0 * st, s));
+                if (mask) HIPCHK(nn::gather_samples(mask, hw, gi, mb + (size_t)k0 * hw, s));
             }
             if (mask && !(cnt > 0)) continue;   // an all-dry minibatch carries no information
             CHK(mlb_net_loss_grad(n, xb, tb, mask ? mb : nullptr, cnt, nb, nullptr, nullptr));

@@ -43,7 +43,23 @@ hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, in
 // (FP32, fixed order; part holds max_blocks x c partials).
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
                      __bf16* dz, float* part, int max_blocks, float* db, hipStream_t s);
-hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream_t s);
+// Rotated, transposed weights of several layers in one launch: for layer l,
+// wr[off[l] + (c * 9 + 8 - t) * cout[l] + n] = w[off[l] + (n * 9 + t) * cin[l] + c].
+constexpr int kFlipMaxLayers = 32;
+struct FlipLayers {
+    int64_t off[kFlipMaxLayers];
+    int32_t cout[kFlipMaxLayers], cin[kFlipMaxLayers];
+    int32_t count;
+};
+hipError_t weight_flip_all(const __bf16* w, const FlipLayers& L, __bf16* wr, hipStream_t s);
+// dst[k] = src[idx[k]] for k < count, each sample `elems` floats (a minibatch
+// gathered from a sample-major array).
+constexpr int kGatherMax = 64;
+struct GatherIdx {
+    int32_t i[kGatherMax];
+    int32_t count;
+};
+hipError_t gather_samples(const float* src, int64_t elems, const GatherIdx& idx, float* dst, hipStream_t s);
 hipError_t pool2(const __bf16* x, int ldx, int xoff, int n, int h, int w, int c, __bf16* y, hipStream_t s);
 hipError_t pool2_back(const float* dy, int n, int h, int w, int c, float* dx, int ldx, int xoff, int accumulate,
                       hipStream_t s);

@@ -469,15 +469,36 @@ __global__ __launch_bounds__(kReluThreads) void relu_mask_kernel(const float* __
     }
 }
 
-// Rotated, transposed weights for the data gradient: wr[c][t][n] = w[n][8 - t][c].
-__global__ void weight_flip_kernel(const __bf16* __restrict__ w, int cout, int cin, __bf16* __restrict__ wr)
+// Rotated, transposed weights for the data gradient: wr[c][t][n] = w[n][8 - t][c],
+// layer blockIdx.y of the table (each layer at the same offset in w and wr).
+__global__ void weight_flip_kernel(const __bf16* __restrict__ w, FlipLayers L, __bf16* __restrict__ wr)
 {
+    const int l = blockIdx.y;
+    const int cout = L.cout[l], cin = L.cin[l];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)cout * 9 * cin) return;
     const int c = (int)(i % cin);
     const int t = (int)((i / cin) % 9);
     const int n = (int)(i / ((int64_t)cin * 9));
-    wr[((size_t)c * 9 + (8 - t)) * cout + n] = w[i];
+    wr[L.off[l] + ((int64_t)c * 9 + (8 - t)) * cout + n] = w[L.off[l] + i];
+}
+
+// Minibatch gather: sample blockIdx.y of the index list, 16-byte vectors when
+// the sample size and both bases allow it.
+__global__ void gather_kernel(const float* __restrict__ src, int64_t elems, GatherIdx idx, float* __restrict__ dst,
+                              int vec)
+{
+    const int k = blockIdx.y;
+    const float* a = src + (int64_t)idx.i[k] * elems;
+    float* b = dst + (int64_t)k * elems;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (vec) {
+        const int64_t n4 = elems >> 2;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += stride)
+            ((float4*)b)[e] = ((const float4*)a)[e];
+    } else {
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems; e += stride) b[e] = a[e];
+    }
 }
 
 __global__ void pool2_kernel(const __bf16* __restrict__ x, int ldx, int xoff, int n, int h, int w, int c,
@@ -775,9 +796,22 @@ hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ld
     return hipGetLastError();
 }
 
-hipError_t weight_flip(const __bf16* w, int cout, int cin, __bf16* wr, hipStream_t s)
+hipError_t weight_flip_all(const __bf16* w, const FlipLayers& L, __bf16* wr, hipStream_t s)
 {
-    hipLaunchKernelGGL(weight_flip_kernel, dim3(blocks_for((int64_t)cout * 9 * cin, 256)), dim3(256), 0, s, w, cout, cin, wr);
+    if (L.count < 1 || L.count > kFlipMaxLayers) return hipErrorInvalidValue;
+    int64_t most = 0;
+    for (int l = 0; l < L.count; ++l) most = std::max<int64_t>(most, (int64_t)L.cout[l] * 9 * L.cin[l]);
+    hipLaunchKernelGGL(weight_flip_kernel, dim3(blocks_for(most, 256), (unsigned)L.count), dim3(256), 0, s, w, L, wr);
+    return hipGetLastError();
+}
+
+hipError_t gather_samples(const float* src, int64_t elems, const GatherIdx& idx, float* dst, hipStream_t s)
+{
+    if (idx.count < 1 || idx.count > kGatherMax || elems < 1) return hipErrorInvalidValue;
+    const int vec = (elems % 4 == 0) && ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
+    const int64_t work = vec ? elems / 4 : elems;
+    const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(work, 256), 1024);
+    hipLaunchKernelGGL(gather_kernel, dim3(bx, (unsigned)idx.count), dim3(256), 0, s, src, elems, idx, dst, vec);
     return hipGetLastError();
 }
 
