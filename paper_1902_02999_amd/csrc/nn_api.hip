@@ -240,8 +240,11 @@ mlb_status conv_bwd(mlb_net* n, int li, const __bf16* x, int ldx, int xoff, cons
     hipStream_t s = n->ctx->stream;
     const int h = n->hh(lev), w = n->ww(lev);
     const int64_t P = (int64_t)nb * h * w;
-    HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->cpart, kBiasChunks, n->grad + ly.boff, s));
+    // the bias partials are summed by the weight gradient's final launch
+    int nparts = 0;
+    HIPCHK(nn::relu_mask(dy, ldd, doff, y, ldy, yoff, P, ly.cout, n->dz, n->cpart, kBiasChunks, nullptr, &nparts, s));
     nn::WgradArgs g{};
+    g.bpart = n->cpart; g.bparts = nparts; g.db = n->grad + ly.boff;
     g.dz = n->dz; g.x = x; g.ldx = ldx; g.xoff = xoff; g.up = up;
     g.n = nb; g.h = h; g.w = w; g.cin = ly.cin; g.cout = ly.cout;
     g.nsplit = nsplit_for(ly, nb, h, w);

@@ -34,15 +34,19 @@ struct WgradArgs {
     int n, h, w, cin, cout;
     int nsplit;
     float* part;         // [nsplit][cout][9][cin]
+    const float* bpart;  // or null: [bparts][cout] bias partials, summed into db by the same final launch
+    int bparts;
+    float* db;
 };
 
 hipError_t conv3x3(const ConvArgs& a, hipStream_t s);
 hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s);
 hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, int nchunk, float* dst, hipStream_t s);
 // dz = dy masked by y > 0 (BF16, contiguous) and db = the channel sums of dz
-// (FP32, fixed order; part holds max_blocks x c partials).
+// (FP32, fixed order; part holds max_blocks x c partials, *nparts of them
+// used).  db null: the partials are left for the caller to sum.
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
-                     __bf16* dz, float* part, int max_blocks, float* db, hipStream_t s);
+                     __bf16* dz, float* part, int max_blocks, float* db, int* nparts, hipStream_t s);
 // Rotated, transposed weights of several layers in one launch: for layer l,
 // wr[off[l] + (c * 9 + 8 - t) * cout[l] + n] = w[off[l] + (n * 9 + t) * cin[l] + c].
 constexpr int kFlipMaxLayers = 32;

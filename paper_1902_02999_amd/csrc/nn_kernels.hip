@@ -386,15 +386,15 @@ __global__ __launch_bounds__(kWgThreads) void conv3x3_wgrad_kernel(WgradArgs a)
 // l, l + lanes, ... of the chunk, then lane 0 adds the lanes' sums in lane
 // order.  Serves the split-K weight gradients and the bias gradients.
 constexpr int kColSumCols = 32;
-__global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ a, int64_t nrows, int64_t ncols,
-                                                      int64_t ld, int64_t chunk, float* __restrict__ out)
+__device__ __forceinline__ void col_sum_block(const float* __restrict__ a, int64_t nrows, int64_t ncols, int64_t ld,
+                                              int64_t chunk, float* __restrict__ out, int64_t bx, int64_t by)
 {
     __shared__ float red[256];
     const int cw = (int)min<int64_t>(ncols, kColSumCols);
     const int lanes = 256 / cw;
     const int t = threadIdx.x, jl = t % cw, rl = t / cw;
-    const int64_t j = (int64_t)blockIdx.x * cw + jl;
-    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = min<int64_t>(r0 + chunk, nrows);
+    const int64_t j = bx * cw + jl;
+    const int64_t r0 = by * chunk, r1 = min<int64_t>(r0 + chunk, nrows);
     const bool act = rl < lanes && j < ncols;
     float s = 0.0f;
     if (act) {
@@ -413,8 +413,26 @@ __global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ 
     __syncthreads();
     if (act && rl == 0) {
         for (int k = 1; k < lanes; ++k) s += red[t + k * cw];
-        out[(int64_t)blockIdx.y * ncols + j] = s;
+        out[by * ncols + j] = s;
     }
+}
+
+__global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ a, int64_t nrows, int64_t ncols,
+                                                      int64_t ld, int64_t chunk, float* __restrict__ out)
+{
+    col_sum_block(a, nrows, ncols, ld, chunk, out, blockIdx.x, blockIdx.y);
+}
+
+// Two column sums in one launch (each over all its rows, one chunk): blocks
+// below nbx1 take the first array, the rest the second; every column is
+// summed exactly as col_sum_kernel sums it.
+__global__ __launch_bounds__(256) void col_sum2_kernel(const float* __restrict__ a, int64_t nrows, int64_t ncols,
+                                                       float* __restrict__ out, int64_t nbx1,
+                                                       const float* __restrict__ a2, int64_t nrows2,
+                                                       int64_t ncols2, float* __restrict__ out2)
+{
+    if ((int64_t)blockIdx.x < nbx1) col_sum_block(a, nrows, ncols, ncols, nrows, out, blockIdx.x, 0);
+    else col_sum_block(a2, nrows2, ncols2, ncols2, nrows2, out2, (int64_t)blockIdx.x - nbx1, 0);
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -475,12 +493,13 @@ __global__ void weight_flip_kernel(const __bf16* __restrict__ w, FlipLayers L, _
 {
     const int l = blockIdx.y;
     const int cout = L.cout[l], cin = L.cin[l];
+    // i runs over the output (contiguous stores, strided loads)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)cout * 9 * cin) return;
-    const int c = (int)(i % cin);
-    const int t = (int)((i / cin) % 9);
-    const int n = (int)(i / ((int64_t)cin * 9));
-    wr[L.off[l] + ((int64_t)c * 9 + (8 - t)) * cout + n] = w[L.off[l] + i];
+    const int n = (int)(i % cout);
+    const int tr = (int)((i / cout) % 9);
+    const int c = (int)(i / ((int64_t)cout * 9));
+    wr[L.off[l] + i] = w[L.off[l] + ((int64_t)n * 9 + (8 - tr)) * cin + c];
 }
 
 // Minibatch gather: sample blockIdx.y of the index list, 16-byte vectors when
@@ -770,7 +789,15 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
     const int64_t blocks = (int64_t)(a.cout / 32) * (a.cin / 32) * a.nsplit;
     hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3((unsigned)blocks), dim3(kWgThreads), 0, s, a);
     const int64_t len = (int64_t)a.cout * 9 * a.cin;
-    col_sum(a.part, a.nsplit, len, len, 1, dw, s);
+    if (a.bpart) {
+        // the split-K sums and the bias partials of the same layer, one launch
+        const int64_t nb1 = blocks_for(len, (int)std::min<int64_t>(len, kColSumCols));
+        const int64_t nb2 = blocks_for(a.cout, (int)std::min<int64_t>(a.cout, kColSumCols));
+        hipLaunchKernelGGL(col_sum2_kernel, dim3((unsigned)(nb1 + nb2)), dim3(256), 0, s, a.part, (int64_t)a.nsplit, len,
+                           dw, nb1, a.bpart, (int64_t)a.bparts, (int64_t)a.cout, a.db);
+    } else {
+        col_sum(a.part, a.nsplit, len, len, 1, dw, s);
+    }
     return hipGetLastError();
 }
 
@@ -784,7 +811,7 @@ hipError_t chan_sum(const float* g, int64_t npix, int c, int ld, float* part, in
 }
 
 hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ldy, int yoff, int64_t npix, int c,
-                     __bf16* dz, float* part, int max_blocks, float* db, hipStream_t s)
+                     __bf16* dz, float* part, int max_blocks, float* db, int* nparts, hipStream_t s)
 {
     if (c % 8 || c / 8 > kReluThreads || ldd % 4 || doff % 4 || ldy % 8 || yoff % 8 || npix < 1 || max_blocks < 1)
         return hipErrorInvalidValue;
@@ -792,7 +819,8 @@ hipError_t relu_mask(const float* dy, int ldd, int doff, const __bf16* y, int ld
     const int nb = (int)std::min<int64_t>(max_blocks, (npix + slots - 1) / slots);
     hipLaunchKernelGGL(relu_mask_kernel, dim3(nb), dim3(kReluThreads), 0, s, dy, ldd, doff, y, ldy, yoff, npix, c, dz,
                        part);
-    col_sum(part, nb, c, c, 1, db, s);
+    if (nparts) *nparts = nb;
+    if (db) col_sum(part, nb, c, c, 1, db, s);
     return hipGetLastError();
 }
 
