@@ -619,16 +619,27 @@ __global__ void head_kernel(const __bf16* __restrict__ x, int64_t npix, int cin,
 }
 
 // dx[p][c] = sum_o dy[p][o] w[o][c]
-__global__ void head_back_kernel(const float* __restrict__ dy, int64_t npix, int cout, const float* __restrict__ w,
-                                 int cin, float* __restrict__ dx)
+// dx[p][c] = sum over o, in order, of dy[p][o] w[o][c]: a thread takes four
+// channels of one pixel (16-byte stores), a block ppb = 256 / (cin / 4) pixels.
+__global__ __launch_bounds__(256) void head_back_kernel(const float* __restrict__ dy, int64_t npix, int cout,
+                                                        const float* __restrict__ w, int cin, float* __restrict__ dx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npix * cin) return;
-    const int64_t p = i / cin;
-    const int c = (int)(i % cin);
-    float s = 0.0f;
-    for (int o = 0; o < cout; ++o) s = __builtin_fmaf(dy[p * cout + o], w[o * cin + c], s);
-    dx[i] = s;
+    const int c4n = cin >> 2, ppb = 256 / c4n;
+    const int t = threadIdx.x, pl = t / c4n;
+    if (pl >= ppb) return;
+    const int64_t p = (int64_t)blockIdx.x * ppb + pl;
+    if (p >= npix) return;
+    const int c = (t - pl * c4n) * 4;
+    float4 s = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int o = 0; o < cout; ++o) {
+        const float d = dy[p * cout + o];
+        const float4 wv = *(const float4*)(w + (size_t)o * cin + c);
+        s.x = __builtin_fmaf(d, wv.x, s.x);
+        s.y = __builtin_fmaf(d, wv.y, s.y);
+        s.z = __builtin_fmaf(d, wv.z, s.z);
+        s.w = __builtin_fmaf(d, wv.w, s.w);
+    }
+    *(float4*)(dx + p * cin + c) = s;
 }
 
 // part[chunk][o][c] = sum over the chunk's pixels of dy[p][o] x[p][c]
@@ -640,7 +651,19 @@ __global__ void head_wgrad_partial_kernel(const float* __restrict__ dy, const __
     const int o = j / cin, c = j % cin;
     const int64_t b = (int64_t)blockIdx.x * chunk, e = min<int64_t>(b + chunk, npix);
     float s = 0.0f;
-    for (int64_t p = b; p < e; ++p) s = __builtin_fmaf(dy[p * cout + o], (float)x[p * cin + c], s);
+    int64_t p = b;
+    // sixteen pixels' loads in flight at once, added in pixel order
+    for (; p + 15 < e; p += 16) {
+        float d[16], xv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            d[u] = dy[(p + u) * cout + o];
+            xv[u] = (float)x[(p + u) * cin + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s = __builtin_fmaf(d[u], xv[u], s);
+    }
+    for (; p < e; ++p) s = __builtin_fmaf(dy[p * cout + o], (float)x[p * cin + c], s);
     part[(size_t)blockIdx.x * cout * cin + j] = s;
 }
 
@@ -877,7 +900,10 @@ hipError_t head(const __bf16* x, int64_t npix, int cin, const float* w, const fl
 hipError_t head_back(const float* dy, const __bf16* x, int64_t npix, int cout, int cin, const float* w,
                      float* dx, float* part, int nchunk, float* dw, float* db, float* bpart, hipStream_t s)
 {
-    hipLaunchKernelGGL(head_back_kernel, dim3(blocks_for(npix * cin, 256)), dim3(256), 0, s, dy, npix, cout, w, cin, dx);
+    // four channels per thread, whole pixels per block (cin a multiple of 8, at most 1024)
+    if (cin % 8 || cin > 1024 || (uintptr_t)w % 16 || (uintptr_t)dx % 16) return hipErrorInvalidValue;
+    const int ppb = 256 / (cin / 4);
+    hipLaunchKernelGGL(head_back_kernel, dim3(blocks_for(npix, ppb)), dim3(256), 0, s, dy, npix, cout, w, cin, dx);
     const int chunk = (int)((npix + nchunk - 1) / nchunk);
     hipLaunchKernelGGL(head_wgrad_partial_kernel, dim3(nchunk, (cout * cin + 255) / 256), dim3(256), 0, s,
                        dy, x, npix, cout, cin, chunk, part);
