@@ -398,14 +398,14 @@ __device__ __forceinline__ void col_sum_block(const float* __restrict__ a, int64
     const bool act = rl < lanes && j < ncols;
     float s = 0.0f;
     if (act) {
-        // eight rows' loads in flight at once, added in row order
+        // 32 rows' loads in flight at once, added in row order
         int64_t i = r0 + rl;
-        for (; i + 7 * lanes < r1; i += 8 * lanes) {
-            float v[8];
+        for (; i + 31 * lanes < r1; i += 32 * lanes) {
+            float v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = a[(i + u * lanes) * ld + j];
+            for (int u = 0; u < 32; ++u) v[u] = a[(i + u * lanes) * ld + j];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
+            for (int u = 0; u < 32; ++u) s += v[u];
         }
         for (; i < r1; i += lanes) s += a[i * ld + j];
     }
@@ -423,16 +423,44 @@ __global__ __launch_bounds__(256) void col_sum_kernel(const float* __restrict__ 
     col_sum_block(a, nrows, ncols, ld, chunk, out, blockIdx.x, blockIdx.y);
 }
 
+// The same sums for arrays of at least kColSumCols columns and few rows, one
+// thread per column (256 columns per block): the thread forms the sums of
+// the 256 / kColSumCols = 8 lanes of col_sum_block itself (rows l, l + 8,
+// ... in order, from 0.0f) and adds them in lane order, so every column gets
+// the bits col_sum_block gives it.
+constexpr int kColSumLanes = 256 / kColSumCols;
+constexpr int kColSumFewRows = 16;
+__device__ __forceinline__ void col_sum_cols_block(const float* __restrict__ a, int64_t nrows, int64_t ncols,
+                                                   float* __restrict__ out, int64_t bx)
+{
+    const int64_t j = bx * 256 + threadIdx.x;
+    if (j >= ncols) return;
+    float lane[kColSumLanes];
+#pragma unroll
+    for (int l = 0; l < kColSumLanes; ++l) lane[l] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kColSumFewRows; ++i)
+        if (i < nrows) lane[i % kColSumLanes] += a[i * ncols + j];
+    float s = lane[0];
+#pragma unroll
+    for (int l = 1; l < kColSumLanes; ++l) s += lane[l];
+    out[j] = s;
+}
+
 // Two column sums in one launch (each over all its rows, one chunk): blocks
-// below nbx1 take the first array, the rest the second; every column is
-// summed exactly as col_sum_kernel sums it.
+// below nbx1 take the first array (one thread per column when cols1 is set),
+// the rest the second; every column is summed exactly as col_sum_kernel sums it.
 __global__ __launch_bounds__(256) void col_sum2_kernel(const float* __restrict__ a, int64_t nrows, int64_t ncols,
-                                                       float* __restrict__ out, int64_t nbx1,
+                                                       float* __restrict__ out, int64_t nbx1, int cols1,
                                                        const float* __restrict__ a2, int64_t nrows2,
                                                        int64_t ncols2, float* __restrict__ out2)
 {
-    if ((int64_t)blockIdx.x < nbx1) col_sum_block(a, nrows, ncols, ncols, nrows, out, blockIdx.x, 0);
-    else col_sum_block(a2, nrows2, ncols2, ncols2, nrows2, out2, (int64_t)blockIdx.x - nbx1, 0);
+    if ((int64_t)blockIdx.x < nbx1) {
+        if (cols1) col_sum_cols_block(a, nrows, ncols, out, blockIdx.x);
+        else col_sum_block(a, nrows, ncols, ncols, nrows, out, blockIdx.x, 0);
+    } else {
+        col_sum_block(a2, nrows2, ncols2, ncols2, nrows2, out2, (int64_t)blockIdx.x - nbx1, 0);
+    }
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -814,10 +842,11 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* dw, hipStream_t s)
     const int64_t len = (int64_t)a.cout * 9 * a.cin;
     if (a.bpart) {
         // the split-K sums and the bias partials of the same layer, one launch
-        const int64_t nb1 = blocks_for(len, (int)std::min<int64_t>(len, kColSumCols));
+        const int cols1 = len >= kColSumCols && a.nsplit <= kColSumFewRows;
+        const int64_t nb1 = cols1 ? blocks_for(len, 256) : blocks_for(len, (int)std::min<int64_t>(len, kColSumCols));
         const int64_t nb2 = blocks_for(a.cout, (int)std::min<int64_t>(a.cout, kColSumCols));
         hipLaunchKernelGGL(col_sum2_kernel, dim3((unsigned)(nb1 + nb2)), dim3(256), 0, s, a.part, (int64_t)a.nsplit, len,
-                           dw, nb1, a.bpart, (int64_t)a.bparts, (int64_t)a.cout, a.db);
+                           dw, nb1, cols1, a.bpart, (int64_t)a.bparts, (int64_t)a.cout, a.db);
     } else {
         col_sum(a.part, a.nsplit, len, len, 1, dw, s);
     }
