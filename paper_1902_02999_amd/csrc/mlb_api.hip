@@ -1526,7 +1526,7 @@ namespace {
 // tiles serve small grids, where a wave's serial row walk, not bandwidth,
 // sets the time of a pass.
 const int kTuneRows[] = {4, 6, 9, 12, 15, 21, 27, 33, 45};
-const int kTuneRows2[] = {5, 8, 11, 14, 17, 20, 23, 26, 32, 44};
+const int kTuneRows2[] = {4, 5, 8, 11, 14, 17, 20, 23, 26, 32, 44};
 const int kTuneCaps[] = {0, 2, 3, 4, 5};
 const int kTuneBlocks[] = {1, 2};
 

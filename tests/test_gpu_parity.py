@@ -297,7 +297,19 @@ def _two_step_cases():
                  edges=(wl.WALL, wl.WALL, wl.DEPTH, wl.DISCHARGE), extrap_order=2,
                  depth_bc={wl.S: (2.0, 0.03, 20.0, 0.5)}, discharge_bc={wl.N: (0.0, 0.5)})
     cases.append(("ydepth_walls", sp, None, 66, 15))
+    cases.append(("ydepth_walls_rows4", sp, None, 66, 4))
     cases.append(("tidal_strip", wl.tidal_strip(), None, 500, 15))
+    # four-row tiles (the shortest the tuner tries) on grids of many tiles
+    sp = closed_spec(64, 64, 0)
+    cases.append(("closed64_rows4", sp, wl.seeded_state(sp, 0, q_amp=0.1), 131, 4))
+    sp = wl.bump_channel(150, 67, sigma=12.0)
+    sp.extrap_order = 2
+    cases.append(("channel_order2_rows4", sp, None, 120, 4))
+    sp = wl.Spec("ychannel", 40, 90, 1.0, 25.0 / 6.0, bumpy(40, 90, 7, amp=0.2), 2.0,
+                 edges=(wl.PERIODIC, wl.PERIODIC, wl.DISCHARGE, wl.DEPTH), extrap_order=2,
+                 depth_bc={wl.N: (2.0, 0.05, 30.0, 0.0)}, discharge_bc={wl.S: (0.1, 1.5)},
+                 qy0=np.full((90, 40), 1.5))
+    cases.append(("ychannel_order2_rows4", sp, None, 99, 4))
     return cases
 
 
