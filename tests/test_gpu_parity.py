@@ -536,6 +536,41 @@ def test_workqueue_ensemble_512_bitwise(ctx):
         assert torch.equal(a, b)
 
 
+
+def test_ensemble_512_sampled_against_oracle(ctx):
+    """The 512-basin ensemble (sizes 64^2 .. 512^2, seed 1902) in the launch
+    configuration its benchmark times (one batch, two steps per pass, 17-row
+    tiles, 4 workgroups per CU, graph chunks of 100 steps; closed basins, so
+    the two-step kernel without open-edge logic) against the oracle on a
+    sample of its basins: the largest, the smallest and six drawn at random
+    (seeded), 41 steps from seeded perturbed states, each at the bar.  The
+    other basins start from rest and share every launch."""
+    from paper_1902_02999_amd import mlb
+    specs = wl.ensemble(512, 1902)
+    sizes = np.array([s.nx for s in specs])
+    rng = np.random.default_rng(7)
+    pick = sorted({int(np.argmax(sizes)), int(np.argmin(sizes))} |
+                  {int(i) for i in rng.choice(len(specs), 6, replace=False)})
+    states = {i: wl.seeded_state(specs[i], i, q_amp=0.1) for i in pick}
+    grids = [mlb.grid_from_spec(ctx, s) for s in specs]
+    for i in pick:
+        grids[i].set_state(*states[i])
+    b = mlb.Batch(ctx, grids)
+    b.set_exec_opts(tile_rows=17, tblock=2, use_graph=True, graph_chunk=100, blocks_per_cu=4)
+    say("ensemble 512 basins, 41 steps; sampled", [(i, specs[i].nx) for i in pick])
+    b.step(41)
+    b.close()
+    got = {i: grids[i].get_state() for i in pick}
+    for g in grids:
+        g.close()
+    for i in pick:
+        ref = oracle_from_spec(specs[i], *states[i])
+        ref.run(41)
+        dh, du = compare(*got[i], ref.h, ref.qx, ref.qy)
+        say("basin", i, specs[i].nx, "dh", dh, "du", du)
+        assert dh <= H_TOL and du <= U_TOL, (i, specs[i].nx)
+
+
 def test_persistent_barrier_timeout_is_reported(ctx, monkeypatch):
     """A barrier wait forced to give up at once (spin limit 0, set from the
     host) ends the launch; the next check reports it, and the grid works
