@@ -64,6 +64,16 @@ constexpr int kConvThreads = kConvRows * 64;
 // pixels the 16-byte A-fragment reads of neighbouring pixels start in
 // distinct banks (64-byte pixels put every fourth pixel on the same banks).
 constexpr int kConvPix = 40;
+// The dispatcher deals workgroups to the eight XCDs in turn.  Block b of a
+// grid of 8 k blocks takes list entry (b % 8) k + b / 8, so XCD j runs the
+// j-th eighth of the list and neighbouring entries (which share input data)
+// share one L2; blocks past 8 k keep their own index.
+__device__ __forceinline__ int xcd_block(int b, int nblocks)
+{
+    const int per = nblocks / 8;
+    return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
 template <bool OUT_F32, int MB, int NB, bool PF>
 __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
 {
@@ -77,7 +87,9 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_lds_kernel(ConvArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 wtile[NT * WS];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int ntile = a.cout / NT, xtiles = a.w / PT, ygroups = (a.h + kConvRows - 1) / kConvRows;
-    int b = blockIdx.x;                     // (image, row group, pixel tile, channel tile), channels fastest
+    // (image, row group, pixel tile, channel tile), channels fastest; the
+    // channel tiles of one input tile run on one XCD
+    int b = xcd_block(blockIdx.x, gridDim.x);
     const int nt = b % ntile; b /= ntile;
     const int xt = b % xtiles; b /= xtiles;
     const int yg = b % ygroups;
@@ -239,7 +251,7 @@ __global__ __launch_bounds__(kWgThreads) void conv3x3_wgrad_kernel(WgradArgs a)
     const int grp = threadIdx.x / 192, gt = threadIdx.x % 192;   // group, thread within the group
     const int r = gt >> 6, lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
     const int ntile = a.cout / 32, ctile = a.cin / 32;
-    int b = blockIdx.x;
+    int b = xcd_block(blockIdx.x, gridDim.x);   // the input-channel tiles of one (nt, split) on one XCD
     const int ct = b % ctile; b /= ctile;
     const int nt = b % ntile;
     const int s = b / ntile;
